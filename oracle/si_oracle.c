@@ -1,0 +1,213 @@
+/*
+ * si_oracle.c -- FP64 reference for spin-image generation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library is
+ * checked against.  Only tests, the smoke check and the benchmark's CPU
+ * baseline may build, load or call it; the library never does, and the two
+ * share no code.
+ *
+ * What it computes is the plain definition of the parallel spin-image
+ * algorithm (Section 2.1, Algorithm 1; the same body restricted to
+ * [start, end) is Algorithm 2): for each of the N chosen oriented points
+ * P = (p, n) and for every one of the M oriented points X = (x, n_x),
+ *
+ *   c     = n . n_x                          support-angle test on the normals
+ *   beta  = n . (x - p)                      signed height above P's tangent plane
+ *   alpha = sqrt(|x - p|^2 - beta^2)         distance from P's normal axis
+ *
+ * X contributes to P's W x W image if the angle between the normals is at
+ * most S and its bin lies inside the image.  Everything is evaluated in
+ * double precision from the float32 inputs (widening is exact).
+ *
+ * Readings of the paper taken here (the paper is silent or ambiguous):
+ *   - angle test acos(c) <= S is evaluated as c >= cos(S), the same predicate
+ *     for S in [0, pi]; for S >= pi every pair passes (the paper runs with
+ *     S = 2 pi, Section 4.1);
+ *   - the row coordinate is v = W/2 - beta/B, i.e. the dimensionally
+ *     consistent form of the printed (W/2 - beta)/B, and the column
+ *     coordinate is u = alpha/B;
+ *   - the inner loop runs over all M points, so the self-pair (x = p) counts;
+ *   - normals are used as given, not renormalised;
+ *   - SI_BIN_CEIL is the printed binning: k = ceil(v), l = ceil(u), counted
+ *     if 0 <= k < W and 0 <= l < W, image[k][l] += 1;
+ *   - SI_BIN_BILINEAR spreads a unit weight over the four grid nodes around
+ *     (v, u) (Johnson's bilinear interpolation, which this paper does not
+ *     print); a pair counts only if the whole 2x2 footprint lies inside the
+ *     image, 0 <= v < W-1 and u < W-1, so image mass equals the count.
+ *
+ * Boundary flags.  Float32 evaluation may legitimately decide differently
+ * from float64 for pairs that lie within eps of a decision boundary.  With
+ * eps > 0, every condition whose argument lies within eps of its threshold is
+ * "unsure".  A pair with a surely-false condition is out; a pair whose
+ * outcome depends on an unsure support condition is ambiguous (counted in
+ * cnt_amb, excluded from img_sure, and every bin it might touch gets
+ * touch += 1).  In ceil mode a surely-in pair whose bin is unsure (beta or
+ * alpha within eps of a bin edge, or 0 < |alpha^2| < 1e-6 near the axis) is
+ * counted in cnt_sure but, too, only recorded in touch.  eps = 0 turns all
+ * flags off (designed inputs whose values are exact).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define SIO_BILINEAR 0
+#define SIO_CEIL 1
+
+/* condition states */
+#define C_FALSE 0
+#define C_TRUE 1
+#define C_UNSURE 2
+
+static int cond(int value, double dist, double eps)
+{
+    if (eps > 0.0 && fabs(dist) < eps)
+        return C_UNSURE;
+    return value ? C_TRUE : C_FALSE;
+}
+
+static void touch_box(int32_t* t, int W, long r0, long r1, long c0, long c1)
+{
+    if (!t)
+        return;
+    if (r0 < 0) r0 = 0;
+    if (c0 < 0) c0 = 0;
+    if (r1 > W - 1) r1 = W - 1;
+    if (c1 > W - 1) c1 = W - 1;
+    for (long r = r0; r <= r1; ++r)
+        for (long c = c0; c <= c1; ++c)
+            t[r * W + c] += 1;
+}
+
+/*
+ * Returns 0 on success, -1 on invalid arguments.
+ *   xyz, nrm : M x 3 float32, row-major
+ *   idx      : N int32 indices into [0, M)
+ *   img_sure : N x W x W doubles (zeroed here)
+ *   cnt_sure, cnt_amb : N int64 each
+ *   touch    : N x W x W int32 (zeroed here) or NULL
+ */
+int sio_generate(const float* xyz, const float* nrm, int64_t M,
+                 const int32_t* idx, int64_t N,
+                 int32_t W, float bin, float support_angle, int32_t mode,
+                 double eps, double* img_sure, int64_t* cnt_sure,
+                 int64_t* cnt_amb, int32_t* touch, int32_t nthreads)
+{
+    if (M <= 0 || N < 0 || W < 1 || !(bin > 0.0f) || !(support_angle >= 0.0f))
+        return -1;
+    if (mode != SIO_BILINEAR && mode != SIO_CEIL)
+        return -1;
+    for (int64_t i = 0; i < N; ++i)
+        if (idx[i] < 0 || idx[i] >= M)
+            return -1;
+
+    const double B = (double)bin;
+    const double S = (double)support_angle;
+    const int vacuous = S >= M_PI;
+    const double cosS = cos(S);
+    const double half = 0.5 * (double)W;
+    const double WW = (double)W;
+    /* support thresholds in scene units */
+    const double beta_hi = (mode == SIO_CEIL) ? B * (half + 1.0) : B * half;
+    const double beta_lo = B * (1.0 - half);
+    const double alpha_max = B * (WW - 1.0);
+
+    (void)nthreads;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t i = 0; i < N; ++i) {
+        double* img = img_sure + (size_t)i * W * W;
+        int32_t* tch = touch ? touch + (size_t)i * W * W : NULL;
+        memset(img, 0, sizeof(double) * (size_t)W * W);
+        if (tch)
+            memset(tch, 0, sizeof(int32_t) * (size_t)W * W);
+        int64_t sure = 0, amb = 0;
+
+        const int64_t pi = idx[i];
+        const double px = xyz[3 * pi], py = xyz[3 * pi + 1], pz = xyz[3 * pi + 2];
+        const double nx = nrm[3 * pi], ny = nrm[3 * pi + 1], nz = nrm[3 * pi + 2];
+
+        for (int64_t j = 0; j < M; ++j) {
+            const double qx = xyz[3 * j], qy = xyz[3 * j + 1], qz = xyz[3 * j + 2];
+            const double mx = nrm[3 * j], my = nrm[3 * j + 1], mz = nrm[3 * j + 2];
+
+            const double c = nx * mx + ny * my + nz * mz;
+            const double dx = qx - px, dy = qy - py, dz = qz - pz;
+            const double beta = nx * dx + ny * dy + nz * dz;
+            const double dd = dx * dx + dy * dy + dz * dz;
+            const double a2 = dd - beta * beta;
+            const double alpha = sqrt(a2 > 0.0 ? a2 : 0.0);
+            const double v = half - beta / B;
+            const double u = alpha / B;
+
+            int ca = vacuous ? C_TRUE : cond(c >= cosS, c - cosS, eps);
+            int c1, c2, c3;
+            if (mode == SIO_CEIL) {
+                const double kk = ceil(v), ll = ceil(u);
+                c1 = cond(kk >= 0.0, beta - beta_hi, eps);      /* k >= 0 */
+                c2 = cond(kk < WW, beta - beta_lo, eps);        /* k < W  */
+                c3 = cond(ll >= 0.0 && ll < WW, alpha - alpha_max, eps);
+            } else {
+                c1 = cond(v >= 0.0, beta - beta_hi, eps);
+                c2 = cond(v < WW - 1.0, beta - beta_lo, eps);
+                c3 = cond(u < WW - 1.0, alpha - alpha_max, eps);
+            }
+            if (ca == C_FALSE || c1 == C_FALSE || c2 == C_FALSE || c3 == C_FALSE)
+                continue;
+            const int unsure = (ca == C_UNSURE) || (c1 == C_UNSURE) ||
+                               (c2 == C_UNSURE) || (c3 == C_UNSURE);
+
+            if (mode == SIO_CEIL) {
+                const long k = (long)ceil(v), l = (long)ceil(u);
+                if (unsure) {
+                    ++amb;
+                    touch_box(tch, W, k - 1, k + 1, l - 1, l + 1);
+                    continue;
+                }
+                ++sure;
+                int row_unsure = 0, col_unsure = 0;
+                /* x == p (the self-pair, duplicate points) is exact in any
+                   precision: beta = alpha = 0, never ambiguous */
+                if (eps > 0.0 && (dx != 0.0 || dy != 0.0 || dz != 0.0)) {
+                    const double m = nearbyint(v);             /* nearest row edge */
+                    row_unsure = fabs(beta - B * (half - m)) < eps;
+                    const double q = nearbyint(u);             /* nearest column edge */
+                    col_unsure = (q >= 1.0 && fabs(alpha - B * q) < eps) ||
+                                 (a2 != 0.0 && fabs(a2) < 1e-6);
+                }
+                if (row_unsure || col_unsure) {
+                    touch_box(tch, W, row_unsure ? k - 1 : k, row_unsure ? k + 1 : k,
+                              col_unsure ? l - 1 : l, col_unsure ? l + 1 : l);
+                } else {
+                    img[k * W + l] += 1.0;
+                }
+            } else {
+                const double fi = floor(v), fj = floor(u);
+                if (unsure) {
+                    ++amb;
+                    touch_box(tch, W, (long)fi - 1, (long)fi + 2, (long)fj - 1, (long)fj + 2);
+                    continue;
+                }
+                ++sure;
+                const long i0 = (long)fi, j0 = (long)fj;
+                const double a = v - fi, b = u - fj;
+                img[i0 * W + j0] += (1.0 - a) * (1.0 - b);
+                img[(i0 + 1) * W + j0] += a * (1.0 - b);
+                img[i0 * W + j0 + 1] += (1.0 - a) * b;
+                img[(i0 + 1) * W + j0 + 1] += a * b;
+            }
+        }
+        cnt_sure[i] = sure;
+        cnt_amb[i] = amb;
+    }
+    return 0;
+}
+
+int sio_abi_version(void) { return 1; }
