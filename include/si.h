@@ -1,0 +1,297 @@
+/*
+ * si.h -- C ABI of the MI355X (gfx950) spin-image library.
+ *
+ * Computes spin images (Section 2.1, Algorithm 1 of "Efficient Generation of
+ * Parallel Spin-images Using Dynamic Loop Scheduling", arXiv 1811.00901):
+ * for every chosen oriented point P = (p, n) and every scene point X = (x, n_x)
+ *
+ *     beta  = n . (x - p)
+ *     alpha = sqrt(|x - p|^2 - beta^2)
+ *
+ * X is rejected when the angle between n and n_x exceeds the support angle S
+ * or when its bin falls outside the W x W image; otherwise it is accumulated
+ * into P's image.  The per-image loop is a DOALL loop (Section 2.2) that the
+ * library distributes over persistent GPU workgroups with the loop-scheduling
+ * techniques of Section 2.2 (STATIC, SS, GSS, FAC) or with an order and chunk
+ * sizes predicted by a learned per-image cost model.
+ *
+ * Conventions for every entry point:
+ *   - All functions return si_status and never abort or throw across the ABI;
+ *     si_last_error() gives a thread-local text for the last failure.
+ *   - "device" pointers are HIP device memory on the current device (for
+ *     example the storage of a torch tensor); "host" pointers are CPU memory.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously on it; input and output buffers must stay valid
+ *     until the stream has reached the call.  Where a function must read a
+ *     result back to the host it synchronises the stream, and says so.
+ *   - The caller owns every buffer it passes in.  The library owns scenes and
+ *     cost models until the matching si_free_* call.
+ *   - Distinct scenes, models and streams may be used from different threads.
+ *     Calls that run concurrently on different streams share a pool of 64
+ *     work-counter slots per device, so at most 64 generation launches may be
+ *     in flight at once.
+ */
+#ifndef SI_H
+#define SI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SI_ABI_VERSION 1
+
+typedef enum si_status {
+    SI_OK = 0,
+    SI_E_INVALID = -1,     /* an argument is out of its documented domain */
+    SI_E_OOM = -2,         /* device or host allocation failed */
+    SI_E_DEVICE = -3,      /* a HIP runtime call failed */
+    SI_E_UNSUPPORTED = -4  /* valid request this build does not implement */
+} si_status;
+
+/* Loop-scheduling techniques (Section 2.2) plus the learned schedule. */
+enum {
+    SI_SCHED_STATIC = 0,  /* one contiguous block per workgroup, no counter   */
+    SI_SCHED_SS = 1,      /* self-scheduling: one image per claim             */
+    SI_SCHED_GSS = 2,     /* guided: ceil(remaining / P) per claim            */
+    SI_SCHED_FAC = 3,     /* factoring: batches of P chunks ceil(R_b/(x P))   */
+    SI_SCHED_LEARNED = 4  /* cost-model order + cost-weighted factoring       */
+};
+
+/* Binning of a pair into the image (see si_params). */
+enum {
+    SI_BIN_BILINEAR = 0,
+    SI_BIN_CEIL = 1
+};
+
+typedef struct si_scene si_scene;           /* opaque, library-owned */
+typedef struct si_cost_model si_cost_model; /* opaque, library-owned */
+
+/*
+ * Spin-image parameters (Section 2.1 and the notation table): W pixels per
+ * side, bin size B in scene units, support angle S in radians.
+ *   W    in [2, 64]
+ *   bin  finite, > 0
+ *   support_angle finite, >= 0; values >= pi disable the angle test (the
+ *        paper's runs use S = 2 pi, Section 4.1).  The test acos(n.n_x) <= S
+ *        is evaluated as n.n_x >= cos(S) with cos(S) computed in double
+ *        precision and rounded to float.
+ *   mode SI_BIN_CEIL: the printed binning, k = ceil(W/2 - beta/B) (row),
+ *        l = ceil(alpha/B) (column), counted when 0 <= k, l < W, bin += 1.
+ *        SI_BIN_BILINEAR: with v = W/2 - beta/B and u = alpha/B, a unit
+ *        weight spread over the four grid nodes around (v, u); counted when
+ *        0 <= v < W-1 and u < W-1.  Weights are accumulated as exact 16.16
+ *        fixed point (each pair adds exactly 1.0 to the image), so images do
+ *        not depend on summation order.
+ */
+typedef struct si_params {
+    int32_t W;
+    float bin;
+    float support_angle;
+    int32_t mode;
+} si_params;
+
+/*
+ * Schedule of the per-image loop over P persistent workgroups.
+ *   kind            SI_SCHED_*
+ *   num_workgroups  P; 0 = library default for the device and W
+ *   min_chunk       lower bound of every dynamic chunk (0 or 1 = none)
+ *   fac_divisor     x of SI_SCHED_FAC / SI_SCHED_LEARNED; 0 = 2 (FAC2)
+ *   model           SI_SCHED_LEARNED only; trained cost model
+ *   fallback_to_fac SI_SCHED_LEARNED without a model: 1 = run FAC, 0 = error
+ *   group           images that share one pass over their common candidate
+ *                   points (1..8); 0 = library default
+ */
+typedef struct si_sched {
+    int32_t kind;
+    int32_t num_workgroups;
+    int32_t min_chunk;
+    float fac_divisor;
+    const si_cost_model* model;
+    int32_t fallback_to_fac;
+    int32_t group;
+} si_sched;
+
+/*
+ * Optional run statistics, filled after synchronising the stream.
+ *   kernel_ms        device time of the generation launch(es) (HIP events)
+ *   pairs_in_support sum of the per-image in-support counts
+ *   pairs_tested     candidate pairs evaluated (after cell-list pruning)
+ *   sched_used       the SI_SCHED_* actually run (FAC when LEARNED fell back)
+ *   n_wg, n_chunks   workgroups launched, chunks in the schedule
+ *   n_invalid        oriented indices outside [0, M) (their images are zero
+ *                    and their count is 0xFFFFFFFF; the call returns
+ *                    SI_E_INVALID when this is nonzero)
+ *   n_overflow       images re-accumulated on the 64-bit path because an
+ *                    image had 65536 or more in-support pairs
+ *   wg_busy_ns       caller-owned host array of wg_busy_cap entries or NULL;
+ *                    receives each workgroup's busy time in ns
+ */
+typedef struct si_stats {
+    double kernel_ms;
+    uint64_t pairs_in_support;
+    uint64_t pairs_tested;
+    int32_t sched_used;
+    int32_t n_wg;
+    int32_t n_chunks;
+    int32_t n_invalid;
+    int32_t n_overflow;
+    int32_t wg_busy_cap;
+    uint64_t* wg_busy_ns;
+} si_stats;
+
+/* Static facts about a built scene. */
+typedef struct si_scene_info {
+    int64_t M;
+    float cell_size;            /* edge of a grid cell (scene units) */
+    float max_support_radius;   /* largest support radius the grid is valid for */
+    int32_t dims[3];            /* cells per axis */
+    float origin[3];            /* lower corner of the grid */
+    int64_t n_cells;
+} si_scene_info;
+
+/*
+ * Build a scene: the list of oriented points OP (Section 2.1) in the layout
+ * the kernels read -- a uniform grid of cells of edge h >= R / s (s = 2 cells
+ * per support radius), points sorted by cell into 32-byte float4 position and
+ * normal records.  The grid is conservative for every pair with
+ * |x - p| <= max_support_radius; max_support_radius <= 0 builds a single
+ * cell (brute force over all M points, the paper's O(N M) loop).
+ *   points_xyz, normals_xyz  device, M x 3 float32, row-major; read only
+ *   M                        number of oriented points, > 0, < 2^31
+ * Synchronises the stream once (to read the bounding box).  Returns
+ * SI_E_INVALID for M <= 0, NULL pointers or a non-finite radius; a NaN
+ * coordinate is placed in cell 0 and is never in support of anything.
+ */
+si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int64_t M,
+                         float max_support_radius, void* hip_stream, si_scene** out);
+
+/* Release a scene (NULL is ignored).  Work using it must have completed. */
+void si_free_scene(si_scene* scene);
+
+/* Fill *out with the scene's grid description (host). */
+si_status si_scene_info_get(const si_scene* scene, si_scene_info* out);
+
+/*
+ * Largest |x - p| of a pair that can be inside the image for these params
+ * (closed form of the extent conditions), written to *radius (host).
+ */
+si_status si_support_radius(const si_params* params, float* radius);
+
+/*
+ * Generate N spin images (Section 2.1, Algorithm 1; each claimed chunk
+ * [start, end) is Algorithm 2).
+ *   oriented_idx  device, N int32 indices into the scene's points in the
+ *                 order given to si_build_scene; duplicates allowed.  The
+ *                 paper's case is 0..N-1.
+ *   images_out    device, N x W x W float32; image i (of oriented_idx[i]) is
+ *                 images_out[i], row index = beta axis, column = alpha axis
+ *   counts_out    device, N uint32 in-support counts
+ *   stats         host or NULL; when set the stream is synchronised
+ * The images and counts do not depend on the schedule or on thread timing.
+ * Returns SI_E_INVALID for bad params/schedule, a support radius above the
+ * scene's max_support_radius, or (when stats is set) invalid indices.
+ * N == 0 is a no-op returning SI_OK.
+ */
+si_status si_generate(const si_scene* scene, const int32_t* oriented_idx, int64_t N,
+                      const si_params* params, const si_sched* sched,
+                      float* images_out, uint32_t* counts_out, si_stats* stats,
+                      void* hip_stream);
+
+/* One scene's share of a batched launch. */
+typedef struct si_batch_item {
+    const si_scene* scene;
+    const int32_t* oriented_idx;  /* device */
+    int64_t N;
+    si_params params;
+    float* images_out;            /* device, N x W x W */
+    uint32_t* counts_out;         /* device, N */
+} si_batch_item;
+
+/*
+ * Generate the images of many scenes in one persistent launch: one flattened
+ * schedule whose chunks never span two scenes.  use_graph = 1 captures the
+ * launch in a HIP graph that is cached and replayed while the item list
+ * (pointers, sizes, params) and schedule are unchanged.  sched->kind is any
+ * SI_SCHED_* (LEARNED uses sched->model on every scene).  Every item is
+ * validated as in si_generate; results are identical to one si_generate per
+ * item.  Items with N == 0 are skipped.
+ */
+si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
+                              const si_sched* sched, int32_t use_graph,
+                              si_stats* stats, void* hip_stream);
+
+/*
+ * Per-image cost features (12 float32 per image, device N x 12) of the
+ * oriented points, from the occupancy of the 3 x 3 x 3 block of cells of size
+ * close to the support radius around p and from n.  Used by the learned cost
+ * model; not part of any image.
+ */
+si_status si_features(const si_scene* scene, const int32_t* oriented_idx, int64_t N,
+                      const si_params* params, float* feats_out, void* hip_stream);
+
+/*
+ * Learned per-image cost model: an MLP 12 -> 64 -> 64 -> 1 (ReLU, float32)
+ * predicting log(1 + in-support count) from the features above.
+ */
+si_status si_cost_model_create(uint64_t seed, si_cost_model** out);
+void si_free_cost_model(si_cost_model* model);
+
+/*
+ * Train with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on mean squared error
+ * against log1p(counts), on the device.
+ *   feats   device n x 12 float32; counts device n uint32
+ *   epochs  passes over the data; batch: minibatch size (1..65536)
+ *   loss_curve_host  host array of `epochs` floats (mean loss per epoch) or
+ *                    NULL; when set the stream is synchronised
+ * Minibatches are contiguous slices of a per-epoch permutation drawn from the
+ * model's seed.
+ */
+si_status si_cost_model_train(si_cost_model* model, const float* feats, const uint32_t* counts,
+                              int64_t n, int32_t epochs, float lr, int32_t batch,
+                              float* loss_curve_host, void* hip_stream);
+
+/* Predicted in-support counts (expm1 of the network output), device n floats. */
+si_status si_cost_model_predict(const si_cost_model* model, const float* feats, int64_t n,
+                                float* pred_counts, void* hip_stream);
+
+/* Copy the 5,057 parameters (W1 64x12, b1 64, W2 64x64, b2 64, w3 64, b3 1, in
+ * that order, row-major) between the model and a host array. */
+si_status si_cost_model_get_params(const si_cost_model* model, float* host_params, int64_t n);
+si_status si_cost_model_set_params(si_cost_model* model, const float* host_params, int64_t n);
+
+/* Save / load the parameters to a file (little-endian header + float32). */
+si_status si_cost_model_save(const si_cost_model* model, const char* path);
+si_status si_cost_model_load(const char* path, si_cost_model** out);
+
+/*
+ * Host-only: the chunk table the generation launch uses for a schedule.
+ * Writes chunk starts (n_chunks + 1 entries, the last = N) to starts_out
+ * (host, capacity cap) and the count to *n_chunks.  STATIC gives P
+ * balanced blocks; SS, GSS and FAC follow Section 2.2 (FAC as FAC2 with
+ * divisor x).  Returns SI_E_INVALID when cap is too small.
+ */
+si_status si_chunk_table(int32_t kind, int64_t N, int32_t P, int32_t min_chunk,
+                         float fac_divisor, int64_t* starts_out, int64_t cap,
+                         int64_t* n_chunks);
+
+/*
+ * Host-only: the order and chunk table of the learned schedule for given
+ * per-unit predicted costs (units = groups of images).  perm_out (host, n)
+ * receives the units in descending predicted cost (ties by index); starts
+ * (host, cap) the chunk boundaries in that order.
+ */
+si_status si_learned_table(const float* unit_cost, int64_t n, int32_t P, float fac_divisor,
+                           int32_t* perm_out, int64_t* starts_out, int64_t cap,
+                           int64_t* n_chunks);
+
+const char* si_status_string(si_status status);
+const char* si_last_error(void);
+int32_t si_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SI_H */

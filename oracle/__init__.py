@@ -89,6 +89,13 @@ def generate(xyz, nrm, idx, W, bin, support_angle, mode=BILINEAR, eps=1e-6,
     return {"img": img, "cnt_sure": cs, "cnt_amb": ca, "touch": tch}
 
 
+def max_threads() -> int:
+    """OpenMP threads the oracle uses by default."""
+    lib = _load()
+    lib.sio_max_threads.restype = ctypes.c_int
+    return int(lib.sio_max_threads())
+
+
 def support_radius(W, bin, mode=BILINEAR) -> float:
     """Largest |x - p| of any pair that can be inside the image (closed form of
     the extent conditions in scene units)."""

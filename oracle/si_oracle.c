@@ -211,3 +211,13 @@ int sio_generate(const float* xyz, const float* nrm, int64_t M,
 }
 
 int sio_abi_version(void) { return 1; }
+
+/* threads an OpenMP parallel region of this library would use */
+int sio_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

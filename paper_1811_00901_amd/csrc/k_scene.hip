@@ -1,0 +1,244 @@
+// Scene-building kernels: bounding box, cell binning, exclusive scan and the
+// scatter of the oriented points (Section 2.1: OP, positions with normals)
+// into a cell-sorted structure-of-arrays of 32-byte records.  The cell of a
+// point is floor((x - origin) / h) per axis, evaluated in double precision so
+// that the conservative culling in the spin kernel can reproduce cell
+// boundaries exactly.
+#include "si_internal.h"
+
+namespace si {
+
+namespace {
+
+constexpr int kScanTile = 2048;        // elements per scan tile (256 threads x 8)
+constexpr int kBBoxBlocks = 1024;
+
+__global__ void __launch_bounds__(256) k_bbox_partial(const float* __restrict__ xyz, int64_t M,
+                                                      float* __restrict__ part) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float v = xyz[3 * i + a];
+            if (isfinite(v)) {
+                lo[a] = fminf(lo[a], v);
+                hi[a] = fmaxf(hi[a], v);
+            }
+        }
+    }
+    __shared__ float s[6][256];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s[a][threadIdx.x] = lo[a];
+        s[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + off]);
+                s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + off]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_bbox_final(const float* __restrict__ part, int n,
+                                                    float* __restrict__ out6) {
+    __shared__ float s[6][256];
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int i = threadIdx.x; i < n; i += 256) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = fminf(v[a], part[i * 6 + a]);
+            v[3 + a] = fmaxf(v[3 + a], part[i * 6 + 3 + a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) s[a][threadIdx.x] = v[a];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                s[a][threadIdx.x] = fminf(s[a][threadIdx.x], s[a][threadIdx.x + off]);
+                s[3 + a][threadIdx.x] = fmaxf(s[3 + a][threadIdx.x], s[3 + a][threadIdx.x + off]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out6[threadIdx.x] = s[threadIdx.x][0];
+}
+
+struct GridDesc {
+    double origin[3];
+    double h;
+    int32_t dims[3];
+};
+
+__device__ __forceinline__ int cell_of_point(const GridDesc& g, float x, float y, float z) {
+    const float v[3] = {x, y, z};
+    int c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double t = floor(((double)v[a] - g.origin[a]) / g.h);
+        // non-finite coordinates (never in support of anything) go to cell 0
+        c[a] = (t >= 0.0 && t < (double)g.dims[a]) ? (int)t : 0;
+    }
+    return (c[2] * g.dims[1] + c[1]) * g.dims[0] + c[0];
+}
+
+__global__ void __launch_bounds__(256) k_bin_points(const float* __restrict__ xyz, int64_t M,
+                                                    GridDesc g, int32_t* __restrict__ cell_of,
+                                                    int32_t* __restrict__ rank,
+                                                    int32_t* __restrict__ counts) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int c = cell_of_point(g, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+    cell_of[i] = c;
+    rank[i] = atomicAdd(counts + c, 1);
+}
+
+// Tile sums of the input.
+__global__ void __launch_bounds__(256) k_scan_tiles(const int32_t* __restrict__ in, int64_t n,
+                                                    int32_t* __restrict__ tile_sum) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanTile / 256; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    __shared__ int red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = red[0];
+}
+
+// Exclusive block scan of 256 values; returns the exclusive prefix, *total.
+__device__ int block_excl_scan(int v, int* s, int* total) {
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const int incl = s[threadIdx.x];
+    *total = s[255];
+    __syncthreads();
+    return incl - v;
+}
+
+// Exclusive scan of the tile sums in place (one workgroup).
+__global__ void __launch_bounds__(256) k_scan_tile_sums(int32_t* __restrict__ t, int64_t n_tiles) {
+    __shared__ int s[256];
+    const int64_t per = (n_tiles + 255) / 256;
+    const int64_t b = threadIdx.x * per;
+    int sum = 0;
+    for (int64_t k = 0; k < per; ++k)
+        if (b + k < n_tiles) sum += t[b + k];
+    int total;
+    int run = block_excl_scan(sum, s, &total);
+    for (int64_t k = 0; k < per; ++k) {
+        if (b + k < n_tiles) {
+            const int v = t[b + k];
+            t[b + k] = run;
+            run += v;
+        }
+    }
+}
+
+// Exclusive scan of each tile plus its offset; out[n] = total.
+__global__ void __launch_bounds__(256) k_scan_apply(const int32_t* __restrict__ in, int64_t n,
+                                                    const int32_t* __restrict__ tile_off,
+                                                    int32_t* __restrict__ out) {
+    __shared__ int s[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * (kScanTile / 256);
+    int v[kScanTile / 256];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanTile / 256; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        sum += v[k];
+    }
+    int total;
+    int run = block_excl_scan(sum, s, &total) + tile_off[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanTile / 256; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = tile_off[blockIdx.x] + total;
+}
+
+__global__ void __launch_bounds__(256) k_scatter(const float* __restrict__ xyz,
+                                                 const float* __restrict__ nrm, int64_t M,
+                                                 const int32_t* __restrict__ cell_of,
+                                                 const int32_t* __restrict__ rank,
+                                                 const int32_t* __restrict__ cell_start,
+                                                 float4* __restrict__ pos, float4* __restrict__ nr,
+                                                 int32_t* __restrict__ inv) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int c = cell_of[i];
+    const int s = cell_start[c] + rank[i];
+    pos[s] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], __int_as_float(c));
+    nr[s] = make_float4(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2], __int_as_float((int)i));
+    inv[i] = s;
+}
+
+}  // namespace
+
+hipError_t launch_bbox(const float* xyz, int64_t M, float* out6, hipStream_t s) {
+    // out6 holds 6 floats followed by scratch for kBBoxBlocks * 6 partials
+    const int nb = (int)std::min<int64_t>(kBBoxBlocks, (M + 255) / 256);
+    float* part = out6 + 8;
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(256), 0, s, xyz, M, part);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, nb, out6);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32_t* cell_of,
+                             int32_t* rank, int32_t* counts, hipStream_t s) {
+    GridDesc g;
+    for (int a = 0; a < 3; ++a) {
+        g.origin[a] = (double)sc.origin[a];
+        g.dims[a] = sc.dims[a];
+    }
+    g.h = sc.h;
+    hipLaunchKernelGGL(k_bin_points, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, xyz, M,
+                       g, cell_of, rank, counts);
+    return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t,
+                       hipStream_t s) {
+    const int64_t nt = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(256), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(256), 0, s, tmp, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(256), 0, s, in, n, tmp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* cell_of,
+                          const int32_t* rank, const int32_t* cell_start, Scene& sc,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, xyz, nrm,
+                       M, cell_of, rank, cell_start, sc.pos, sc.nrm, sc.inv);
+    return hipGetLastError();
+}
+
+}  // namespace si

@@ -1,0 +1,487 @@
+// Spin-image generation kernel for gfx950 (CDNA4).
+//
+// One persistent launch executes the DOALL loop over images (Section 2.1,
+// Algorithm 1).  Each workgroup repeatedly claims a chunk [start, end) of the
+// loop (Algorithm 2 is exactly the body run for a claimed chunk): STATIC gives
+// workgroup k chunk k; the dynamic techniques of Section 2.2 hand out the
+// chunks of a precomputed table through one global atomic counter, which
+// replaces the master of the paper's master-worker protocol (Section 3).
+//
+// Inside a chunk, up to G consecutive images whose grid cells lie close
+// together form a group that shares one pass over their common candidate
+// points: every candidate point is loaded once (coalesced float4 records of a
+// cell-sorted scene) and tested against all G images.  Candidates are the
+// points of the grid rows whose cells can hold a point within the support
+// radius of some image of the group; rows and their x-extent are culled
+// against the support sphere in double precision so that no in-support point
+// is ever skipped.
+//
+// Per pair (beta, alpha as in Algorithm 1):
+//   beta = n.(x-p), alpha^2 = |x-p|^2 - beta^2, c = n.n_x
+//   bilinear: in = beta <= B W/2  &&  beta > B(1-W/2)  &&  alpha^2 < (B(W-1))^2  [&& c >= cos S]
+//   ceil:     in = beta <  B(W/2+1) && beta >= B(1-W/2) && alpha^2 <= (B(W-1))^2 [&& c >= cos S]
+// which are the extent conditions 0 <= v < W-1, u < W-1 (bilinear) and
+// 0 <= ceil(v), ceil(u) < W (ceil) of v = W/2 - beta/B, u = alpha/B written in
+// scene units.  Images accumulate in LDS as unsigned 16.16 fixed point with
+// integer atomics: each in-support pair adds exactly 65536 (its four bilinear
+// weights are rounded so that they sum to 65536), so an image is a sum of
+// integers and does not depend on the order in which pairs arrive.  An image
+// whose in-support count reaches 65536 could wrap a 32-bit bin; it is redone
+// with 64-bit LDS accumulators.
+#include "si_internal.h"
+
+namespace si {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kInfo = 64;     // images whose descriptors are staged at once
+constexpr int kMaxRows = 64;  // candidate rows per group (one lane each)
+
+struct __attribute__((aligned(16))) ImgInfo {
+    float px, py, pz;
+    int32_t out;      // output position, -1 = invalid index
+    float nx, ny, nz;
+    int32_t cell;     // linear cell id
+};
+
+__device__ __forceinline__ float rfl(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ void cell_xyz(int cell, const int* dims, int& cx, int& cy, int& cz) {
+    cx = cell % dims[0];
+    int t = cell / dims[0];
+    cy = t % dims[1];
+    cz = t / dims[1];
+}
+
+// Accumulate one in-support pair (bilinear) into a u32 or u64 LDS image.
+template <typename Acc>
+__device__ __forceinline__ void add_bilinear(Acc* img, int W, float v, float u) {
+    int i0 = (int)floorf(v);
+    int j0 = (int)floorf(u);
+    i0 = min(max(i0, 0), W - 2);
+    j0 = min(max(j0, 0), W - 2);
+    const float a = fminf(fmaxf(v - (float)i0, 0.0f), 1.0f);
+    const float b = fminf(fmaxf(u - (float)j0, 0.0f), 1.0f);
+    const uint32_t qa = (uint32_t)rintf(a * 65536.0f);
+    const uint32_t qb = (uint32_t)rintf(b * 65536.0f);
+    const uint32_t q11 = (uint32_t)(((uint64_t)qa * qb + 32768u) >> 16);
+    const uint32_t q10 = qa - q11;
+    const uint32_t q01 = qb - q11;
+    const uint32_t q00 = 65536u - qa - qb + q11;
+    Acc* r0 = img + i0 * W + j0;
+    atomicAdd(r0, (Acc)q00);
+    atomicAdd(r0 + 1, (Acc)q01);
+    atomicAdd(r0 + W, (Acc)q10);
+    atomicAdd(r0 + W + 1, (Acc)q11);
+}
+
+template <typename Acc>
+__device__ __forceinline__ void add_ceil(Acc* img, int W, float v, float u) {
+    int k = (int)ceilf(v);
+    int l = (int)ceilf(u);
+    k = min(max(k, 0), W - 1);
+    l = min(max(l, 0), W - 1);
+    atomicAdd(img + k * W + l, (Acc)65536u);
+}
+
+struct GroupImg {
+    float px, py, pz, nx, ny, nz;
+};
+
+// Test every candidate of the group's rows against `ng` images.
+// acc: ng images of W*W accumulators.  cnt: per-thread in-support counts.
+template <int MODE, int G, typename Acc>
+__device__ __forceinline__ void candidate_pass(const SceneView& sc, const SpinParams& p,
+                                               const GroupImg* gi, int ng, Acc* acc,
+                                               const int* row_start, const int* row_pref,
+                                               int n_rows, uint32_t* cnt) {
+    const int W = p.W;
+    const int w2 = W * W;
+    const int total = row_pref[n_rows];
+    int r = 0;
+    for (int k = threadIdx.x; k < total; k += kBlock) {
+        while (row_pref[r + 1] <= k) ++r;
+        const int j = row_start[r] + (k - row_pref[r]);
+        const float4 x = sc.pos[j];
+        const float4 m = sc.nrm[j];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g < ng) {
+                const float dx = x.x - gi[g].px;
+                const float dy = x.y - gi[g].py;
+                const float dz = x.z - gi[g].pz;
+                const float beta = fmaf(gi[g].nz, dz, fmaf(gi[g].ny, dy, gi[g].nx * dx));
+                const float dd = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const float a2 = fmaf(-beta, beta, dd);
+                bool in;
+                if (MODE == SI_BIN_BILINEAR)
+                    in = (beta <= p.beta_hi) & (beta > p.beta_lo) & (a2 < p.alpha2_max);
+                else
+                    in = (beta < p.beta_hi) & (beta >= p.beta_lo) & (a2 <= p.alpha2_max);
+                if (p.angle_on) {
+                    const float c = fmaf(gi[g].nz, m.z, fmaf(gi[g].ny, m.y, gi[g].nx * m.x));
+                    in = in & (c >= p.cos_s);
+                }
+                if (in) {
+                    const float v = fmaf(-beta, p.inv_bin, p.half);
+                    const float u = sqrtf(fmaxf(a2, 0.0f)) * p.inv_bin;
+                    if (MODE == SI_BIN_BILINEAR)
+                        add_bilinear(acc + g * w2, W, v, u);
+                    else
+                        add_ceil(acc + g * w2, W, v, u);
+                    cnt[g] += 1;
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Rows (z, y) of grid cells that may hold candidates of the group, with the
+// contiguous x-run of cells of each row, culled against the support sphere of
+// every image (double precision, radius inflated by 1e-6 relative).
+// Executed by wave 0; lane l handles row l.  Writes row_start/row_pref.
+__device__ __forceinline__ void build_rows(const SceneView& sc, const SpinParams& p, const GroupImg* gi,
+                           const int* gcell, int ng, int lo[3], int hi[3], int* row_start,
+                           int* row_pref, int* n_rows_out) {
+    const int lane = threadIdx.x;  // caller guarantees threadIdx.x < 64
+    const int ny_rows = hi[1] - lo[1] + 1;
+    const int nz_rows = hi[2] - lo[2] + 1;
+    const int n_rows = ny_rows * nz_rows;  // <= kMaxRows by construction
+    int len = 0, start = 0;
+    if (lane < n_rows) {
+        const int cy = lo[1] + lane % ny_rows;
+        const int cz = lo[2] + lane / ny_rows;
+        const double h = sc.h;
+        const double R = (double)p.radius;
+        const double R2 = R * R;
+        const double ylo = (double)sc.origin[1] + cy * h, yhi = ylo + h;
+        const double zlo = (double)sc.origin[2] + cz * h, zhi = zlo + h;
+        int x0 = 0x7fffffff, x1 = -1;
+#pragma unroll
+        for (int g = 0; g < kMaxGroup; ++g) {
+            if (g >= ng) break;
+            const double py = gi[g].py, pz = gi[g].pz, px = gi[g].px;
+            if (!(py == py) || !(pz == pz) || !(px == px)) continue;  // invalid image
+            const double dy = fmax(0.0, fmax(ylo - py, py - yhi));
+            const double dz = fmax(0.0, fmax(zlo - pz, pz - zhi));
+            const double d2 = dy * dy + dz * dz;
+            if (d2 > R2) continue;
+            const double wx = sqrt(R2 - d2);
+            const double fa = floor((px - wx - (double)sc.origin[0]) / h);
+            const double fb = floor((px + wx - (double)sc.origin[0]) / h);
+            int a = (int)fmax(-1.0, fmin(fa, 1.0e9));
+            int b = (int)fmax(-1.0, fmin(fb, 1.0e9));
+            int gx, gy, gz;
+            cell_xyz(gcell[g], sc.dims, gx, gy, gz);
+            a = max(a, gx - p.reach);
+            b = min(b, gx + p.reach);
+            x0 = min(x0, a);
+            x1 = max(x1, b);
+        }
+        x0 = max(x0, 0);
+        x1 = min(x1, sc.dims[0] - 1);
+        if (x1 >= x0) {
+            const int base = (cz * sc.dims[1] + cy) * sc.dims[0];
+            start = sc.cell_start[base + x0];
+            len = sc.cell_start[base + x1 + 1] - start;
+        }
+    }
+    // inclusive scan of len over the wave
+    int incl = len;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane < n_rows) {
+        row_start[lane] = start;
+        row_pref[lane + 1] = incl;
+    }
+    if (lane == 0) {
+        row_pref[0] = 0;
+        *n_rows_out = n_rows;
+    }
+}
+
+template <int G>
+__device__ void run_group_pass(int mode, const SceneView& sc, const SpinParams& p,
+                               const GroupImg* gi, int ng, uint32_t* acc, const int* row_start,
+                               const int* row_pref, int n_rows, uint32_t* cnt) {
+    if (mode == SI_BIN_BILINEAR)
+        candidate_pass<SI_BIN_BILINEAR, G, uint32_t>(sc, p, gi, ng, acc, row_start, row_pref,
+                                                     n_rows, cnt);
+    else
+        candidate_pass<SI_BIN_CEIL, G, uint32_t>(sc, p, gi, ng, acc, row_start, row_pref, n_rows,
+                                                 cnt);
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
+    extern __shared__ uint4 acc_lds[];
+    uint32_t* acc = reinterpret_cast<uint32_t*>(acc_lds);
+    __shared__ ImgInfo s_info[kInfo];
+    __shared__ int s_row_start[kMaxRows];
+    __shared__ int s_row_pref[kMaxRows + 1];
+    __shared__ int s_n_rows;
+    __shared__ uint32_t s_cnt[kMaxGroup];
+    __shared__ int s_step;
+
+    const int tid = threadIdx.x;
+    const uint64_t t_begin = wall_clock64();
+    unsigned long long my_tested = 0, my_support = 0;
+    uint32_t my_invalid = 0, my_overflow = 0;
+    bool first = true;
+
+    for (;;) {
+        if (tid == 0) {
+            int step;
+            if (d.dynamic)
+                step = (int)atomicAdd(d.counter, 1u);
+            else
+                step = first ? (int)blockIdx.x : d.n_chunks;
+            s_step = step;
+        }
+        first = false;
+        __syncthreads();
+        const int step = rfl(s_step);
+        if (step >= d.n_chunks) break;
+        const Chunk ch = d.chunks[step];
+        const int item_id = rfl(ch.item);
+        const int c_start = rfl(ch.start);
+        const int c_end = rfl(ch.end);
+        const Item& it = d.items ? d.items[item_id] : d.single;
+        const SceneView sc = it.scene;
+        const SpinParams p = it.p;
+        const int W = p.W;
+        const int w2 = W * W;
+        // images per group: keep the LDS footprint of the launch (group x max_w2)
+        const int G_item = min(kMaxGroup, max(1, (d.group * d.max_w2) / w2));
+        // cells a group may span per axis beyond the first, and rows available
+        const int span_lim = max(0, min(1, 7 - 2 * p.reach));
+
+        for (int b0 = c_start; b0 < c_end; b0 += kInfo) {
+            const int nb = min(kInfo, c_end - b0);
+            __syncthreads();  // s_info reuse
+            if (tid < nb) {
+                const int w = b0 + tid;
+                const int out = it.perm ? it.perm[w] : w;
+                const int o = it.oriented[out];
+                ImgInfo inf;
+                if (o >= 0 && o < sc.M) {
+                    const int sp = sc.inv[o];
+                    const float4 a = sc.pos[sp];
+                    const float4 n = sc.nrm[sp];
+                    inf.px = a.x; inf.py = a.y; inf.pz = a.z;
+                    inf.nx = n.x; inf.ny = n.y; inf.nz = n.z;
+                    inf.cell = __float_as_int(a.w);
+                    inf.out = out;
+                } else {
+                    const float qnan = __int_as_float(0x7fc00000);
+                    inf.px = inf.py = inf.pz = qnan;
+                    inf.nx = inf.ny = inf.nz = qnan;
+                    inf.cell = -1;
+                    inf.out = -1 - out;  // invalid: encode the output position
+                }
+                s_info[tid] = inf;
+            }
+            __syncthreads();
+
+            int cur = 0;
+            while (cur < nb) {
+                // ---- form a group (every thread computes the same answer) ----
+                int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
+                int hi[3] = {-1, -1, -1};
+                int ng = 0;
+                while (ng < G_item && cur + ng < nb) {
+                    const int cell = s_info[cur + ng].cell;
+                    if (cell >= 0) {
+                        int c[3];
+                        cell_xyz(cell, sc.dims, c[0], c[1], c[2]);
+                        int nlo[3], nhi[3];
+                        bool ok = true;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            nlo[a] = min(lo[a], c[a]);
+                            nhi[a] = max(hi[a], c[a]);
+                            if (nhi[a] - nlo[a] > span_lim) ok = false;
+                        }
+                        if (!ok && ng > 0) break;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) { lo[a] = nlo[a]; hi[a] = nhi[a]; }
+                    }
+                    ++ng;
+                }
+                int gcell[kMaxGroup];
+                GroupImg gi[kMaxGroup];
+#pragma unroll
+                for (int g = 0; g < kMaxGroup; ++g) {
+                    const ImgInfo inf = s_info[cur + (g < ng ? g : 0)];
+                    gcell[g] = inf.cell >= 0 ? inf.cell : 0;
+                    gi[g].px = rfl(inf.px); gi[g].py = rfl(inf.py); gi[g].pz = rfl(inf.pz);
+                    gi[g].nx = rfl(inf.nx); gi[g].ny = rfl(inf.ny); gi[g].nz = rfl(inf.nz);
+                }
+                ng = rfl(ng);
+                const bool any_valid = hi[0] >= 0;
+                int rlo[3], rhi[3];
+                for (int a = 0; a < 3; ++a) {
+                    rlo[a] = any_valid ? max(lo[a] - p.reach, 0) : 0;
+                    rhi[a] = any_valid ? min(hi[a] + p.reach, sc.dims[a] - 1) : -1;
+                }
+
+                // ---- zero accumulators + counts; wave 0 builds the rows ----
+                {
+                    uint4* a4 = reinterpret_cast<uint4*>(acc);
+                    const int n4 = (ng * w2 + 3) / 4;
+                    for (int i = tid; i < n4; i += kBlock) a4[i] = make_uint4(0, 0, 0, 0);
+                    if (tid < kMaxGroup) s_cnt[tid] = 0;
+                }
+                if (tid < 64) {
+                    if (any_valid) {
+                        build_rows(sc, p, gi, gcell, ng, rlo, rhi, s_row_start, s_row_pref,
+                                   &s_n_rows);
+                    } else if (tid == 0) {
+                        s_row_pref[0] = 0;
+                        s_n_rows = 0;
+                    }
+                }
+                __syncthreads();
+                const int n_rows = rfl(s_n_rows);
+
+                // ---- candidate pass ----
+                uint32_t cnt[kMaxGroup];
+#pragma unroll
+                for (int g = 0; g < kMaxGroup; ++g) cnt[g] = 0;
+                if (ng > 4)
+                    run_group_pass<8>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
+                                      n_rows, cnt);
+                else if (ng > 2)
+                    run_group_pass<4>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
+                                      n_rows, cnt);
+                else if (ng > 1)
+                    run_group_pass<2>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
+                                      n_rows, cnt);
+                else
+                    run_group_pass<1>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
+                                      n_rows, cnt);
+#pragma unroll
+                for (int g = 0; g < kMaxGroup; ++g) {
+                    if (g < ng) {
+                        const uint32_t s = wave_sum(cnt[g]);
+                        if ((tid & 63) == 0 && s) atomicAdd(&s_cnt[g], s);
+                    }
+                }
+                if (tid == 0) my_tested += (unsigned long long)s_row_pref[n_rows] * ng;
+                __syncthreads();
+
+                // ---- write the group's images and counts ----
+                int redo_mask = 0;
+                for (int g = 0; g < ng; ++g) {
+                    const int out_code = s_info[cur + g].out;
+                    const uint32_t c = s_cnt[g];
+                    const bool valid = out_code >= 0;
+                    const int out = valid ? out_code : -1 - out_code;
+                    float* img = it.images + (size_t)out * w2;
+                    const uint32_t* a = acc + g * w2;
+                    if ((w2 & 3) == 0 && ((reinterpret_cast<uintptr_t>(img) & 15) == 0)) {
+                        for (int i = tid; i < w2 / 4; i += kBlock) {
+                            const uint4 q = reinterpret_cast<const uint4*>(a)[i];
+                            f32x4 f;
+                            f[0] = (float)q.x * (1.0f / 65536.0f);
+                            f[1] = (float)q.y * (1.0f / 65536.0f);
+                            f[2] = (float)q.z * (1.0f / 65536.0f);
+                            f[3] = (float)q.w * (1.0f / 65536.0f);
+                            __builtin_nontemporal_store(f, reinterpret_cast<f32x4*>(img) + i);
+                        }
+                    } else {
+                        for (int i = tid; i < w2; i += kBlock)
+                            __builtin_nontemporal_store((float)a[i] * (1.0f / 65536.0f), img + i);
+                    }
+                    if (tid == 0) {
+                        it.counts[out] = valid ? c : 0xFFFFFFFFu;
+                        if (valid) my_support += c; else ++my_invalid;
+                    }
+                    if (valid && c >= d.ovf_limit) redo_mask |= 1 << g;
+                }
+                // ---- rare: an image with >= 65536 pairs may have wrapped a bin ----
+                if (redo_mask) {
+                    for (int g = 0; g < ng; ++g) {
+                        if (!(redo_mask & (1 << g))) continue;
+                        __syncthreads();
+                        unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(acc);
+                        for (int i = tid; i < w2; i += kBlock) acc64[i] = 0ull;
+                        __syncthreads();
+                        uint32_t c1[1] = {0};
+                        const ImgInfo inf = s_info[cur + g];
+                        GroupImg one;
+                        one.px = rfl(inf.px); one.py = rfl(inf.py); one.pz = rfl(inf.pz);
+                        one.nx = rfl(inf.nx); one.ny = rfl(inf.ny); one.nz = rfl(inf.nz);
+                        if (p.mode == SI_BIN_BILINEAR)
+                            candidate_pass<SI_BIN_BILINEAR, 1, unsigned long long>(
+                                sc, p, &one, 1, acc64, s_row_start, s_row_pref, n_rows, c1);
+                        else
+                            candidate_pass<SI_BIN_CEIL, 1, unsigned long long>(
+                                sc, p, &one, 1, acc64, s_row_start, s_row_pref, n_rows, c1);
+                        __syncthreads();
+                        const int out = s_info[cur + g].out;
+                        float* img = it.images + (size_t)out * w2;
+                        for (int i = tid; i < w2; i += kBlock)
+                            img[i] = (float)acc64[i] * (1.0f / 65536.0f);
+                        if (tid == 0) ++my_overflow;
+                    }
+                }
+                __syncthreads();
+                cur += ng;
+            }
+        }
+    }
+
+    if (tid == 0) {
+        if (d.stat_tested && my_tested) atomicAdd(d.stat_tested, my_tested);
+        if (d.stat_support && my_support) atomicAdd(d.stat_support, my_support);
+        if (d.stat_invalid && my_invalid) atomicAdd(d.stat_invalid, my_invalid);
+        if (d.stat_overflow && my_overflow) atomicAdd(d.stat_overflow, my_overflow);
+        if (d.wg_ns) d.wg_ns[blockIdx.x] = (unsigned long long)(wall_clock64() - t_begin);
+        if (d.dynamic) {
+            // the last workgroup to finish leaves the counter at zero for the next launch
+            __threadfence();
+            const uint32_t done = atomicAdd(d.counter + 1, 1u);
+            if (done == gridDim.x - 1) {
+                atomicExch(d.counter, 0u);
+                atomicExch(d.counter + 1, 0u);
+            }
+        }
+    }
+}
+
+size_t spin_lds_bytes(int max_w2, int group) {
+    const int slots = group < 2 ? 2 : group;  // room for one 64-bit image
+    return (size_t)slots * (size_t)max_w2 * sizeof(uint32_t) + 16;
+}
+
+int spin_max_wg_per_cu(int max_w2, int group) {
+    int n = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &n, reinterpret_cast<const void*>(k_spin), kBlock, spin_lds_bytes(max_w2, group));
+    if (e != hipSuccess || n < 1) n = 1;
+    return n;
+}
+
+hipError_t launch_spin(const LaunchDesc& d, int n_wg, hipStream_t s) {
+    const size_t lds = spin_lds_bytes(d.max_w2, d.group);
+    hipLaunchKernelGGL(k_spin, dim3(n_wg), dim3(kBlock), lds, s, d);
+    return hipGetLastError();
+}
+
+}  // namespace si

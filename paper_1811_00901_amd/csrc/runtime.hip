@@ -1,0 +1,560 @@
+// Host runtime of the spin-image library: the C ABI of include/si.h.
+//
+// Scene construction, parameter validation, schedule (chunk-table) caching,
+// the generation launch and its statistics.  The paper's master process
+// (Section 3, the master's algorithm) becomes host code that computes a chunk
+// table once per schedule, plus a device-global counter that the persistent
+// workgroups of the spin kernel advance to claim chunks.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "si_internal.h"
+
+namespace si {
+
+// ---------------------------------------------------------------- errors --
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+si_status fail(si_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+si_status hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? SI_E_OOM : SI_E_DEVICE;
+}
+
+// --------------------------------------------------------- device state --
+namespace {
+
+constexpr int kCounterSlots = 64;
+constexpr int kCounterStride = 32;  // u32 words between slots (128 bytes)
+
+}  // namespace
+
+static std::mutex g_mu;
+static std::map<int, DeviceState> g_dev;
+
+si_status device_state(DeviceState** out) {
+    int dev = 0;
+    SI_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceState& st = g_dev[dev];
+    if (!st.ready) {
+        SI_HIP(hipDeviceGetAttribute(&st.n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+            khz > 0)
+            st.wall_khz = khz;
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess && lds > 0)
+            st.max_lds = std::min(lds, 65536);
+        SI_HIP(hipMalloc(&st.counters, sizeof(uint32_t) * kCounterSlots * kCounterStride));
+        SI_HIP(hipMemset(st.counters, 0, sizeof(uint32_t) * kCounterSlots * kCounterStride));
+        SI_HIP(hipDeviceSynchronize());
+        st.ready = true;
+    }
+    *out = &st;
+    return SI_OK;
+}
+
+uint32_t* take_counter(DeviceState* st) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const uint32_t k = st->next_slot++ % kCounterSlots;
+    return st->counters + (size_t)k * kCounterStride;
+}
+
+static bool finite_f(float v) { return isfinite(v); }
+
+// ------------------------------------------------------------ parameters --
+si_status make_params(const si_params* prm, SpinParams* out, double* radius) {
+    if (!prm) return fail(SI_E_INVALID, "params is NULL");
+    if (prm->W < 2 || prm->W > 64) return fail(SI_E_INVALID, "W must be in [2, 64]");
+    if (!finite_f(prm->bin) || !(prm->bin > 0.0f))
+        return fail(SI_E_INVALID, "bin must be finite and > 0");
+    if (!finite_f(prm->support_angle) || !(prm->support_angle >= 0.0f))
+        return fail(SI_E_INVALID, "support_angle must be finite and >= 0");
+    if (prm->mode != SI_BIN_BILINEAR && prm->mode != SI_BIN_CEIL)
+        return fail(SI_E_INVALID, "mode must be SI_BIN_BILINEAR or SI_BIN_CEIL");
+    const double B = prm->bin;
+    const double half = 0.5 * prm->W;
+    const double hi = prm->mode == SI_BIN_CEIL ? B * (half + 1.0) : B * half;
+    const double lo = B * (1.0 - half);
+    const double amax = B * (prm->W - 1.0);
+    SpinParams p;
+    p.W = prm->W;
+    p.mode = prm->mode;
+    p.half = (float)half;
+    p.inv_bin = (float)(1.0 / B);
+    p.beta_lo = (float)lo;
+    p.beta_hi = (float)hi;
+    p.alpha2_max = (float)(amax * amax);
+    const double S = prm->support_angle;
+    p.angle_on = S < M_PI ? 1 : 0;
+    p.cos_s = (float)cos(S);
+    const double R = sqrt(std::max(fabs(hi), fabs(lo)) * std::max(fabs(hi), fabs(lo)) + amax * amax);
+    *radius = R;
+    // culling radius: any pair the float32 test can accept lies within it
+    p.radius = (float)(R * (1.0 + 1e-5));
+    p.reach = 0;
+    *out = p;
+    return SI_OK;
+}
+
+// ----------------------------------------------------------- chunk tables --
+int64_t chunk_sizes(int kind, int64_t N, int P, int min_chunk, float divisor, int64_t* starts,
+                    int64_t cap) {
+    // Returns the number of chunks; writes starts[0..n] when cap allows (n+1 entries).
+    int64_t n = 0, pos = 0;
+    auto put = [&](int64_t c) {
+        if (starts && n < cap) starts[n] = pos;
+        pos += c;
+        ++n;
+    };
+    const int64_t mc = std::max(1, min_chunk);
+    if (kind == SI_SCHED_STATIC) {
+        const int64_t q = N / P, r = N % P;
+        for (int k = 0; k < P; ++k) put(q + (k < r ? 1 : 0));
+    } else if (kind == SI_SCHED_SS) {
+        for (int64_t R = N; R > 0;) {
+            const int64_t c = std::min(mc, R);
+            put(c);
+            R -= c;
+        }
+    } else if (kind == SI_SCHED_GSS) {
+        for (int64_t R = N; R > 0;) {
+            const int64_t c = std::min(std::max((R + P - 1) / P, mc), R);
+            put(c);
+            R -= c;
+        }
+    } else {  // FAC / LEARNED tables over equal-cost units
+        const double x = divisor > 0.0f ? (double)divisor : 2.0;
+        for (int64_t R = N; R > 0;) {
+            const int64_t c = std::max((int64_t)ceil((double)R / (x * (double)P)), mc);
+            for (int k = 0; k < P && R > 0; ++k) {
+                const int64_t cc = std::min(c, R);
+                put(cc);
+                R -= cc;
+            }
+        }
+    }
+    if (starts && n < cap) starts[n] = pos;
+    return n;
+}
+
+si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk,
+                           float divisor, Chunk** out, int* n_out) {
+    uint32_t dbits;
+    const float dv = divisor > 0.0f ? divisor : 2.0f;
+    memcpy(&dbits, &dv, 4);
+    const int kk = kind == SI_SCHED_FAC ? SI_SCHED_FAC : kind;
+    auto key = std::make_tuple(kk, N, P, kind == SI_SCHED_STATIC ? 0 : std::max(1, min_chunk),
+                               kk == SI_SCHED_FAC ? dbits : 0u);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = st->tables.find(key);
+        if (it != st->tables.end()) {
+            *out = it->second.first;
+            *n_out = it->second.second;
+            return SI_OK;
+        }
+    }
+    const int64_t n = chunk_sizes(kind, N, P, min_chunk, dv, nullptr, 0);
+    if (n > INT32_MAX) return fail(SI_E_INVALID, "schedule has too many chunks");
+    std::vector<int64_t> starts(n + 1);
+    chunk_sizes(kind, N, P, min_chunk, dv, starts.data(), n + 1);
+    std::vector<Chunk> h(n);
+    for (int64_t i = 0; i < n; ++i) {
+        h[i].item = 0;
+        h[i].start = (int32_t)starts[i];
+        h[i].end = (int32_t)starts[i + 1];
+    }
+    Chunk* dptr = nullptr;
+    SI_HIP(hipMalloc(&dptr, sizeof(Chunk) * std::max<int64_t>(n, 1)));
+    if (n) SI_HIP(hipMemcpy(dptr, h.data(), sizeof(Chunk) * n, hipMemcpyHostToDevice));
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (st->tables.size() >= 64) {  // keep the cache small
+        for (auto& kv : st->tables) (void)hipFree(kv.second.first);
+        st->tables.clear();
+    }
+    st->tables[key] = {dptr, (int)n};
+    *out = dptr;
+    *n_out = (int)n;
+    return SI_OK;
+}
+
+// ------------------------------------------------------------------ scene --
+SceneView view_of(const Scene& s) {
+    SceneView v;
+    v.pos = s.pos;
+    v.nrm = s.nrm;
+    v.cell_start = s.cell_start;
+    v.inv = s.inv;
+    for (int a = 0; a < 3; ++a) {
+        v.dims[a] = s.dims[a];
+        v.origin[a] = s.origin[a];
+    }
+    v.h = s.h;
+    v.M = (int32_t)s.M;
+    return v;
+}
+
+static void free_scene_mem(Scene* s) {
+    if (!s) return;
+    (void)hipFree(s->pos);
+    (void)hipFree(s->nrm);
+    (void)hipFree(s->cell_start);
+    (void)hipFree(s->inv);
+    s->pos = s->nrm = nullptr;
+    s->cell_start = s->inv = nullptr;
+}
+
+}  // namespace si
+
+using namespace si;
+
+extern "C" {
+
+si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int64_t M,
+                         float max_support_radius, void* hip_stream, si_scene** out) {
+    if (!out) return fail(SI_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!points_xyz || !normals_xyz) return fail(SI_E_INVALID, "points or normals is NULL");
+    if (M <= 0 || M >= INT32_MAX) return fail(SI_E_INVALID, "M must be in [1, 2^31 - 1)");
+    if (!isfinite(max_support_radius)) return fail(SI_E_INVALID, "max_support_radius not finite");
+    hipStream_t s = (hipStream_t)hip_stream;
+    DeviceState* st;
+    si_status rc = device_state(&st);
+    if (rc != SI_OK) return rc;
+
+    si_scene* sc = new (std::nothrow) si_scene();
+    if (!sc) return fail(SI_E_OOM, "host allocation failed");
+    sc->M = M;
+    SI_HIP(hipGetDevice(&sc->device));
+
+    // ---- bounding box (one synchronisation) ----
+    float* bb = nullptr;
+    hipError_t e = hipMalloc(&bb, sizeof(float) * (8 + 6 * 1024));
+    if (e != hipSuccess) { delete sc; return hip_fail(e, "hipMalloc(bbox)"); }
+    float hb[6];
+    e = launch_bbox(points_xyz, M, bb, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hb, bb, sizeof(hb), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(bb);
+    if (e != hipSuccess) { delete sc; return hip_fail(e, "scene bounding box"); }
+
+    double lo[3], ext[3];
+    bool any = true;
+    for (int a = 0; a < 3; ++a) {
+        if (!(hb[a] <= hb[3 + a])) any = false;
+        lo[a] = any ? (double)hb[a] : 0.0;
+    }
+    for (int a = 0; a < 3; ++a) ext[a] = any ? (double)hb[3 + a] - lo[a] : 0.0;
+    for (int a = 0; a < 3; ++a) sc->origin[a] = any ? hb[a] : 0.0f;
+
+    if (max_support_radius > 0.0f && any) {
+        // margin 2e-5 > the 1e-5 of the culling radius: reach stays <= kSub
+        double h = (double)max_support_radius * (1.0 + 2e-5) / kSub;
+        for (;;) {
+            int64_t cells = 1;
+            for (int a = 0; a < 3; ++a) {
+                const int64_t d = (int64_t)floor(ext[a] / h) + 1;
+                sc->dims[a] = (int32_t)d;
+                cells *= d;
+            }
+            if (cells <= kMaxCells) {
+                sc->n_cells = cells;
+                break;
+            }
+            h *= std::cbrt((double)cells / (double)kMaxCells) * 1.01;
+        }
+        sc->h = h;
+        sc->max_radius = max_support_radius;
+    } else {
+        sc->h = std::max({ext[0], ext[1], ext[2], 0.0}) + 1.0;
+        sc->dims[0] = sc->dims[1] = sc->dims[2] = 1;
+        sc->n_cells = 1;
+        sc->max_radius = 0.0f;
+    }
+
+    // ---- bin, scan, scatter ----
+    int32_t *cell_of = nullptr, *rank = nullptr, *counts = nullptr, *tmp = nullptr;
+    const int64_t ntmp = scan_tmp_elems(sc->n_cells);
+    auto cleanup = [&]() {
+        (void)hipFree(cell_of);
+        (void)hipFree(rank);
+        (void)hipFree(counts);
+        (void)hipFree(tmp);
+    };
+    e = hipMalloc(&sc->pos, sizeof(float4) * M);
+    if (e == hipSuccess) e = hipMalloc(&sc->nrm, sizeof(float4) * M);
+    if (e == hipSuccess) e = hipMalloc(&sc->inv, sizeof(int32_t) * M);
+    if (e == hipSuccess) e = hipMalloc(&sc->cell_start, sizeof(int32_t) * (sc->n_cells + 1));
+    if (e == hipSuccess) e = hipMalloc(&cell_of, sizeof(int32_t) * M);
+    if (e == hipSuccess) e = hipMalloc(&rank, sizeof(int32_t) * M);
+    if (e == hipSuccess) e = hipMalloc(&counts, sizeof(int32_t) * sc->n_cells);
+    if (e == hipSuccess) e = hipMalloc(&tmp, sizeof(int32_t) * ntmp);
+    if (e == hipSuccess) e = hipMemsetAsync(counts, 0, sizeof(int32_t) * sc->n_cells, s);
+    if (e == hipSuccess) e = launch_bin_points(points_xyz, M, *sc, cell_of, rank, counts, s);
+    if (e == hipSuccess) e = launch_scan(counts, sc->cell_start, sc->n_cells, tmp, ntmp, s);
+    if (e == hipSuccess)
+        e = launch_scatter(points_xyz, normals_xyz, M, cell_of, rank, sc->cell_start, *sc, s);
+    // temporaries are released once the stream has used them
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) {
+        free_scene_mem(sc);
+        delete sc;
+        return hip_fail(e, "scene build");
+    }
+    *out = sc;
+    return SI_OK;
+}
+
+void si_free_scene(si_scene* scene) {
+    if (!scene) return;
+    free_scene_mem(scene);
+    delete scene;
+}
+
+si_status si_scene_info_get(const si_scene* scene, si_scene_info* out) {
+    if (!scene || !out) return fail(SI_E_INVALID, "NULL argument");
+    out->M = scene->M;
+    out->cell_size = (float)scene->h;
+    out->max_support_radius = scene->max_radius;
+    for (int a = 0; a < 3; ++a) {
+        out->dims[a] = scene->dims[a];
+        out->origin[a] = scene->origin[a];
+    }
+    out->n_cells = scene->n_cells;
+    return SI_OK;
+}
+
+si_status si_support_radius(const si_params* params, float* radius) {
+    if (!radius) return fail(SI_E_INVALID, "radius is NULL");
+    SpinParams p;
+    double R;
+    si_status rc = make_params(params, &p, &R);
+    if (rc != SI_OK) return rc;
+    float r = (float)R;
+    if ((double)r < R) r = nextafterf(r, INFINITY);  // never below the true radius
+    *radius = r;
+    return SI_OK;
+}
+
+si_status si_chunk_table(int32_t kind, int64_t N, int32_t P, int32_t min_chunk,
+                         float fac_divisor, int64_t* starts_out, int64_t cap,
+                         int64_t* n_chunks) {
+    if (kind < SI_SCHED_STATIC || kind > SI_SCHED_FAC) return fail(SI_E_INVALID, "bad kind");
+    if (N < 0 || P < 1) return fail(SI_E_INVALID, "N must be >= 0 and P >= 1");
+    if (fac_divisor < 0.0f || !isfinite(fac_divisor)) return fail(SI_E_INVALID, "bad divisor");
+    const int64_t n = chunk_sizes(kind, N, P, min_chunk, fac_divisor, nullptr, 0);
+    if (n_chunks) *n_chunks = n;
+    if (starts_out) {
+        if (cap < n + 1) return fail(SI_E_INVALID, "starts_out capacity too small");
+        chunk_sizes(kind, N, P, min_chunk, fac_divisor, starts_out, cap);
+    }
+    return SI_OK;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------- generate --
+namespace si {
+
+int default_group(int W) { return W >= 64 ? 2 : 4; }
+
+// Largest group <= the requested one whose accumulators fit the LDS limit.
+int fit_group(DeviceState* st, int group, int max_w2) {
+    const size_t static_lds = 4096;  // kernel's own shared arrays, rounded up
+    while (group > 1 && spin_lds_bytes(max_w2, group) + static_lds > (size_t)st->max_lds) --group;
+    return group;
+}
+
+si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_stats* stats,
+                     hipStream_t s, int sched_used) {
+    d.max_w2 = max_w2;
+    d.counter = take_counter(st);
+    d.ovf_limit = 65536u;
+    if (const char* lim = getenv("SI_TEST_OVERFLOW_LIMIT")) d.ovf_limit = (uint32_t)atol(lim);
+    unsigned long long* dev_stats = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (stats) {
+        const size_t words = 4 + (size_t)n_wg;
+        SI_HIP(hipMalloc(&dev_stats, sizeof(unsigned long long) * words));
+        SI_HIP(hipMemsetAsync(dev_stats, 0, sizeof(unsigned long long) * words, s));
+        d.stat_tested = dev_stats;
+        d.stat_support = dev_stats + 1;
+        d.stat_invalid = reinterpret_cast<uint32_t*>(dev_stats + 2);
+        d.stat_overflow = reinterpret_cast<uint32_t*>(dev_stats + 3);
+        d.wg_ns = dev_stats + 4;
+        SI_HIP(hipEventCreate(&ev0));
+        SI_HIP(hipEventCreate(&ev1));
+        SI_HIP(hipEventRecord(ev0, s));
+    } else {
+        d.stat_tested = d.stat_support = nullptr;
+        d.stat_invalid = d.stat_overflow = nullptr;
+        d.wg_ns = nullptr;
+    }
+    hipError_t e = launch_spin(d, n_wg, s);
+    if (e != hipSuccess) {
+        (void)hipFree(dev_stats);
+        return hip_fail(e, "spin-image launch");
+    }
+    if (!stats) return SI_OK;
+    SI_HIP(hipEventRecord(ev1, s));
+    std::vector<unsigned long long> h(4 + (size_t)n_wg);
+    SI_HIP(hipMemcpyAsync(h.data(), dev_stats, sizeof(unsigned long long) * h.size(),
+                          hipMemcpyDeviceToHost, s));
+    SI_HIP(hipStreamSynchronize(s));
+    float ms = 0.0f;
+    SI_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    (void)hipFree(dev_stats);
+    stats->kernel_ms = ms;
+    stats->pairs_tested = h[0];
+    stats->pairs_in_support = h[1];
+    stats->n_invalid = (int32_t)(uint32_t)h[2];
+    stats->n_overflow = (int32_t)(uint32_t)h[3];
+    stats->sched_used = sched_used;
+    stats->n_wg = n_wg;
+    stats->n_chunks = d.n_chunks;
+    if (stats->wg_busy_ns) {
+        const int n = std::min(stats->wg_busy_cap, n_wg);
+        for (int i = 0; i < n; ++i)
+            stats->wg_busy_ns[i] = (uint64_t)((double)h[4 + i] * 1e6 / (double)st->wall_khz);
+    }
+    if (stats->n_invalid) return fail(SI_E_INVALID, "oriented_idx holds indices outside [0, M)");
+    return SI_OK;
+}
+
+si_status check_sched(const si_sched* sc) {
+    if (!sc) return fail(SI_E_INVALID, "sched is NULL");
+    if (sc->kind < SI_SCHED_STATIC || sc->kind > SI_SCHED_LEARNED)
+        return fail(SI_E_INVALID, "unknown schedule kind");
+    if (sc->num_workgroups < 0) return fail(SI_E_INVALID, "num_workgroups must be >= 0");
+    if (sc->min_chunk < 0) return fail(SI_E_INVALID, "min_chunk must be >= 0");
+    if (!isfinite(sc->fac_divisor) || sc->fac_divisor < 0.0f)
+        return fail(SI_E_INVALID, "fac_divisor must be finite and >= 0");
+    if (sc->fac_divisor > 0.0f && sc->fac_divisor < 1.0f)
+        return fail(SI_E_INVALID, "fac_divisor must be >= 1");
+    if (sc->group < 0 || sc->group > kMaxGroup) return fail(SI_E_INVALID, "group must be in [0, 8]");
+    return SI_OK;
+}
+
+int auto_workgroups(DeviceState* st, int max_w2, int group) {
+    const int per_cu = std::min(8, spin_max_wg_per_cu(max_w2, group));
+    return std::max(1, st->n_cu * per_cu);
+}
+
+}  // namespace si
+
+extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_idx, int64_t N,
+                                 const si_params* params, const si_sched* sched,
+                                 float* images_out, uint32_t* counts_out, si_stats* stats,
+                                 void* hip_stream) {
+    if (!scene) return fail(SI_E_INVALID, "scene is NULL");
+    si_status rc = check_sched(sched);
+    if (rc != SI_OK) return rc;
+    SpinParams p;
+    double R;
+    rc = make_params(params, &p, &R);
+    if (rc != SI_OK) return rc;
+    if (N < 0 || N >= INT32_MAX) return fail(SI_E_INVALID, "N must be in [0, 2^31 - 1)");
+    if (N == 0) {
+        if (stats) {
+            stats->kernel_ms = 0;
+            stats->pairs_in_support = stats->pairs_tested = 0;
+            stats->sched_used = sched->kind;
+            stats->n_wg = stats->n_chunks = stats->n_invalid = stats->n_overflow = 0;
+        }
+        return SI_OK;
+    }
+    if (!oriented_idx || !images_out || !counts_out)
+        return fail(SI_E_INVALID, "oriented_idx, images_out and counts_out must be non-NULL");
+    // the grid keeps a 2e-5 relative margin, so 1e-6 of slack stays conservative
+    if (scene->max_radius > 0.0f && R > (double)scene->max_radius * (1.0 + 1e-6))
+        return fail(SI_E_INVALID, "support radius of params exceeds the scene's max_support_radius");
+    int cur_dev = 0;
+    SI_HIP(hipGetDevice(&cur_dev));
+    if (cur_dev != scene->device) return fail(SI_E_INVALID, "scene lives on another device");
+    hipStream_t s = (hipStream_t)hip_stream;
+    DeviceState* st;
+    rc = device_state(&st);
+    if (rc != SI_OK) return rc;
+
+    p.reach = scene->max_radius > 0.0f ? (int)floor((double)p.radius / scene->h) + 1 : 0;
+    if (p.reach > kSub + 1) return fail(SI_E_INVALID, "support radius too large for the grid");
+    const int w2 = p.W * p.W;
+    const int group = fit_group(st, sched->group > 0 ? sched->group : default_group(p.W), w2);
+    const int n_wg = sched->num_workgroups > 0 ? sched->num_workgroups
+                                               : auto_workgroups(st, w2, group);
+
+    LaunchDesc d;
+    memset(&d, 0, sizeof(d));
+    d.single.scene = view_of(*scene);
+    d.single.p = p;
+    d.single.oriented = oriented_idx;
+    d.single.images = images_out;
+    d.single.counts = counts_out;
+    d.single.N = N;
+    d.single.perm = nullptr;
+    d.items = nullptr;
+    d.group = group;
+
+    int kind = sched->kind;
+    Chunk* chunks = nullptr;
+    int n_chunks = 0;
+    if (kind == SI_SCHED_LEARNED) {
+        int32_t* perm = nullptr;
+        rc = learned_table(st, scene, oriented_idx, N, params, sched, n_wg, group, &chunks,
+                           &n_chunks, &perm, s);
+        if (rc == SI_E_UNSUPPORTED || (rc == SI_OK && !chunks)) {
+            if (!sched->fallback_to_fac)
+                return fail(SI_E_INVALID, "SI_SCHED_LEARNED needs a model (fallback disabled)");
+            kind = SI_SCHED_FAC;
+        } else if (rc != SI_OK) {
+            return rc;
+        } else {
+            d.single.perm = perm;
+        }
+    }
+    if (kind != SI_SCHED_LEARNED) {
+        rc = get_table(st, kind, N, n_wg, sched->min_chunk, sched->fac_divisor, &chunks, &n_chunks);
+        if (rc != SI_OK) return rc;
+    }
+    d.chunks = chunks;
+    d.n_chunks = n_chunks;
+    d.dynamic = kind == SI_SCHED_STATIC ? 0 : 1;
+    return run_launch(st, d, n_wg, w2, stats, s, kind);
+}
+
+extern "C" {
+
+const char* si_status_string(si_status status) {
+    switch (status) {
+        case SI_OK: return "SI_OK";
+        case SI_E_INVALID: return "SI_E_INVALID";
+        case SI_E_OOM: return "SI_E_OOM";
+        case SI_E_DEVICE: return "SI_E_DEVICE";
+        case SI_E_UNSUPPORTED: return "SI_E_UNSUPPORTED";
+    }
+    return "unknown si_status";
+}
+
+const char* si_last_error(void) { return g_last_error.c_str(); }
+
+int32_t si_abi_version(void) { return SI_ABI_VERSION; }
+
+}  // extern "C"

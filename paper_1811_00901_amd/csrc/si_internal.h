@@ -1,0 +1,162 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// the spin-image library.  Nothing here is part of the C ABI (include/si.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+
+#include "../../include/si.h"
+
+namespace si {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string& msg);
+si_status fail(si_status st, const std::string& msg);
+si_status hip_fail(hipError_t e, const char* what);
+
+#define SI_HIP(call)                                         \
+    do {                                                     \
+        hipError_t _e = (call);                              \
+        if (_e != hipSuccess) return ::si::hip_fail(_e, #call); \
+    } while (0)
+
+// ----------------------------------------------------------------- scene --
+// Grid cells per support radius: cell edge h = R_max (1 + 2e-5) / kSub.
+constexpr int kSub = 2;
+// Cap on the number of grid cells of one scene; a larger box gets bigger cells.
+constexpr int64_t kMaxCells = int64_t(1) << 25;
+
+struct Scene {
+    int64_t M = 0;
+    float4* pos = nullptr;       // sorted by cell: (x, y, z, bits(cell id))
+    float4* nrm = nullptr;       // sorted by cell: (nx, ny, nz, bits(original index))
+    int32_t* cell_start = nullptr;  // n_cells + 1
+    int32_t* inv = nullptr;      // original index -> sorted position
+    int32_t dims[3] = {1, 1, 1};
+    float origin[3] = {0, 0, 0};
+    double h = 0;                // cell edge (double, as used to bin the points)
+    float max_radius = 0;        // <= 0: brute force, single cell
+    int64_t n_cells = 1;
+    int device = 0;
+};
+
+// --------------------------------------------------------------- kernels --
+// Spin-image launch description (passed by value to the kernel).
+struct SpinParams {
+    int32_t W;
+    int32_t mode;            // SI_BIN_*
+    float half;              // W / 2
+    float inv_bin;           // 1 / B (float of the double quotient)
+    float beta_lo, beta_hi;  // extent in beta (mode dependent, see kernel)
+    float alpha2_max;        // (B (W - 1))^2
+    float cos_s;             // cos S
+    int32_t angle_on;        // S < pi
+    float radius;            // support radius R_s (with margin) for culling
+    int32_t reach;           // stencil reach in cells
+};
+
+struct SceneView {
+    const float4* pos;
+    const float4* nrm;
+    const int32_t* cell_start;
+    const int32_t* inv;
+    int32_t dims[3];
+    float origin[3];
+    double h;                // cell edge, as used to bin the points
+    int32_t M;
+};
+
+// One unit of a flattened (possibly batched) schedule.
+struct Chunk {
+    int32_t item;   // batch item (0 for single-scene launches)
+    int32_t start;  // [start, end) positions within the item's oriented_idx
+    int32_t end;
+};
+
+struct Item {
+    SceneView scene;
+    SpinParams p;
+    const int32_t* oriented;
+    float* images;
+    uint32_t* counts;
+    int64_t N;
+    const int32_t* perm;  // optional iteration -> output position map (learned order)
+};
+
+struct LaunchDesc {
+    Item single;              // the item of a single-scene launch (items == nullptr)
+    const Item* items;        // device array for batched launches, else nullptr
+    const Chunk* chunks;      // device array, n_chunks
+    int32_t n_chunks;
+    int32_t dynamic;          // 0: workgroup k runs chunk k; 1: atomic claims
+    uint32_t* counter;        // 2 words: claim counter, finished workgroups
+    int32_t group;            // images per shared candidate pass (1..kMaxGroup)
+    int32_t max_w2;           // largest W*W over items (LDS sizing)
+    uint32_t ovf_limit;       // in-support count at which an image is redone in 64 bits
+    unsigned long long* stat_tested;   // device counters (may be null)
+    unsigned long long* stat_support;
+    uint32_t* stat_invalid;
+    uint32_t* stat_overflow;
+    unsigned long long* wg_ns;         // per workgroup busy time (may be null)
+};
+
+constexpr int kMaxGroup = 8;
+constexpr int kBlock = 256;
+
+// Dynamic LDS bytes a launch needs.
+size_t spin_lds_bytes(int max_w2, int group);
+hipError_t launch_spin(const LaunchDesc& d, int n_wg, hipStream_t s);
+int spin_max_wg_per_cu(int max_w2, int group);
+
+// Scene-building kernels.
+hipError_t launch_bbox(const float* xyz, int64_t M, float* out6, hipStream_t s);
+hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32_t* cell_of,
+                             int32_t* rank, int32_t* counts, hipStream_t s);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t tmp_n,
+                       hipStream_t s);
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* cell_of,
+                          const int32_t* rank, const int32_t* cell_start, Scene& sc,
+                          hipStream_t s);
+
+// ------------------------------------------------------------ host state --
+struct DeviceState {
+    bool ready = false;
+    int n_cu = 0;
+    int wall_khz = 100000;
+    int max_lds = 65536;           // bytes of LDS one workgroup may allocate
+    uint32_t* counters = nullptr;  // work-counter slots, zero between launches
+    uint32_t next_slot = 0;
+    // chunk-table cache: (kind, N, P, min_chunk, divisor bits) -> device table
+    std::map<std::tuple<int, int64_t, int, int, uint32_t>, std::pair<Chunk*, int>> tables;
+};
+
+si_status device_state(DeviceState** out);
+uint32_t* take_counter(DeviceState* st);
+si_status make_params(const si_params* prm, SpinParams* out, double* radius);
+si_status check_sched(const si_sched* sc);
+SceneView view_of(const Scene& s);
+int default_group(int W);
+int fit_group(DeviceState* st, int group, int max_w2);
+int auto_workgroups(DeviceState* st, int max_w2, int group);
+si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk, float divisor,
+                    Chunk** out, int* n_out);
+si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_stats* stats,
+                     hipStream_t s, int sched_used);
+// Learned schedule: device chunk table and iteration->output permutation for
+// one scene; returns SI_E_UNSUPPORTED when no model is given.
+si_status learned_table(DeviceState* st, const Scene* scene, const int32_t* oriented, int64_t N,
+                        const si_params* params, const si_sched* sched, int n_wg, int group,
+                        Chunk** chunks, int* n_chunks, int32_t** perm, hipStream_t s);
+
+// Host chunk tables.
+int64_t chunk_sizes(int kind, int64_t N, int P, int min_chunk, float divisor,
+                    int64_t* starts, int64_t cap);
+
+}  // namespace si
+
+struct si_scene : si::Scene {};

@@ -1,0 +1,277 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Workloads are the seeded synthetic scenes of ``scenegen``: the unit sphere
+(2,000 points, W 16, bin 0.05, 60 degrees, brute force), the uneven-density
+primitives scene (100k points, W 32, bin 0.02, cell list) at reduced and full
+size, and the clustered 2M-point scene on sampled images.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+S60 = float(np.float32(math.pi / 3))
+SCHEDS = ["static", "ss", "gss", "fac"]
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import oracle
+    import paper_1811_00901_amd as si
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, si, oracle
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def run(env, xyz, nrm, idx, W, B, S, mode, sched="static", radius=None, **kw):
+    torch, si, _ = env
+    params = si.Params(W, B, S, mode)
+    if radius is None:
+        radius = si.si_support_radius(params)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), radius)
+    d_idx = to_dev(torch, np.asarray(idx, np.int32))
+    img, cnt, st = si.si_generate(scene, d_idx, params, si.Sched(sched, **kw), stats=True)
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), cnt.cpu().numpy().view(np.uint32), st
+
+
+def print_case(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+@pytest.mark.parametrize("mode", ["bilinear", "ceil"])
+def test_sphere2k_full_vs_oracle(env, mode):
+    """2,000 points on the unit sphere, every point oriented, brute force,
+    STATIC: every image against the oracle."""
+    print_case(f"sphere2k {mode}")
+    _, _, oracle = env
+    xyz, nrm = sg.config_scene("sphere2k")
+    idx = np.arange(2000)
+    img, cnt, st = run(env, xyz, nrm, idx, 16, 0.05, S60, mode, "static", radius=0.0)
+    ref = oracle.generate(xyz, nrm, idx, 16, 0.05, S60, mode=0 if mode == "bilinear" else 1)
+    info = parity.check(img, cnt, ref, 0 if mode == "bilinear" else 1, f"sphere2k-{mode}")
+    assert st["pairs_tested"] == 2000 * 2000
+    assert st["pairs_in_support"] == int(cnt.astype(np.int64).sum())
+    print(info)
+
+
+@pytest.mark.parametrize("mode", ["bilinear", "ceil"])
+def test_hand_scene_exact(env, mode):
+    """The hand-derived 15-point scene: exact images on the GPU as well."""
+    print_case(f"hand scene {mode}")
+    from tests.test_oracle import load_hand_scene, dense
+    pts, nrm, meta, bil, cei = load_hand_scene()
+    W = int(meta["W"])
+    for radius in (0.0, 1.0):
+        img, cnt, _ = run(env, pts, nrm, [0], W, meta["bin"], meta["angle"], mode, radius=radius)
+        exp = dense(W, bil if mode == "bilinear" else cei)
+        np.testing.assert_array_equal(img[0].astype(np.float64), exp)
+        assert cnt[0] == meta[f"{mode}_count"]
+
+
+def test_axis_law_gpu(env):
+    print_case("axis law")
+    for W in (2, 5, 16, 64):
+        B = 2.0 ** -4
+        ts = np.arange(-W - 2, W + 3)
+        pts = np.zeros((len(ts), 3), np.float32)
+        pts[:, 2] = ts * B
+        nrm = np.tile(np.array([0, 0, 1], np.float32), (len(ts), 1))
+        i0 = int(np.where(ts == 0)[0][0])
+        img, cnt, _ = run(env, pts, nrm, [i0], W, B, S60, "bilinear")
+        assert np.all(img[0][:, 1:] == 0)
+        col = img[0][:, 0]
+        for t in ts:
+            v = W / 2.0 - t
+            if 0 <= v < W - 1 and v == int(v):
+                assert col[int(v)] >= 1.0
+
+
+@pytest.mark.parametrize("mode", ["bilinear", "ceil"])
+def test_prims_small_all_schedules(env, mode):
+    """Uneven-density primitives recipe at 20,000 points, 4,000 images, cell
+    list: every image against the oracle, and the four schedules bit-identical."""
+    print_case(f"prims 20k {mode}")
+    _, _, oracle = env
+    xyz, nrm = sg.config_scene("prims100k", M=20000)
+    idx = np.arange(4000)
+    m = 0 if mode == "bilinear" else 1
+    ref = oracle.generate(xyz, nrm, idx, 32, 0.02, S60, mode=m)
+    base = None
+    for sched in SCHEDS:
+        img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, mode, sched, num_workgroups=97)
+        info = parity.check(img, cnt, ref, m, f"prims20k-{mode}-{sched}")
+        if base is None:
+            base = (img, cnt)
+            print(info, st["pairs_tested"], st["pairs_in_support"])
+        else:
+            np.testing.assert_array_equal(img, base[0])
+            np.testing.assert_array_equal(cnt, base[1])
+
+
+def test_cell_list_equals_brute_force(env):
+    print_case("cell list vs brute force")
+    xyz, nrm = sg.config_scene("prims100k", M=30000)
+    idx = np.arange(0, 30000, 7)
+    a = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "fac", radius=0.0)
+    b = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "fac")
+    c = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "fac", radius=1.3)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[0], c[0])
+    assert b[2]["pairs_tested"] < a[2]["pairs_tested"] / 5
+
+
+def test_prims100k_full_sampled(env):
+    """The full uneven-density workload (100k points, 65,536 images) in the
+    launch configuration of the benchmark; 1,200 sampled images against the
+    oracle; schedules bit-identical on all images."""
+    print_case("prims100k full")
+    _, _, oracle = env
+    xyz, nrm = sg.config_scene("prims100k")
+    idx = np.arange(65536)
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(65536, 1200, replace=False))
+    ref = oracle.generate(xyz, nrm, idx[sample], 32, 0.02, S60, mode=0)
+    base = None
+    for sched in SCHEDS:
+        img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", sched)
+        if base is None:
+            info = parity.check(img[sample], cnt[sample], ref, 0, f"prims100k-{sched}")
+            print(info, st)
+            base = (img, cnt)
+        else:
+            assert np.array_equal(img, base[0]), sched
+            assert np.array_equal(cnt, base[1]), sched
+
+
+def test_clustered2m_sampled(env):
+    """The 2M-point clustered workload, every point oriented, FAC: 300 sampled
+    images against the oracle (brute force over all 2M points per image)."""
+    print_case("clustered2m sampled")
+    _, _, oracle = env
+    xyz, nrm = sg.config_scene("clustered2m")
+    N = xyz.shape[0]
+    idx = np.arange(N)
+    rng = np.random.default_rng(1)
+    sample = np.sort(rng.choice(N, 300, replace=False))
+    img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "fac")
+    ref = oracle.generate(xyz, nrm, idx[sample], 32, 0.02, S60, mode=0)
+    info = parity.check(img[sample], cnt[sample], ref, 0, "clustered2m")
+    print(info, {k: v for k, v in st.items() if k != "wg_busy_ns"})
+    assert st["n_overflow"] == 0 or st["n_overflow"] > 0
+
+
+def test_edge_cases(env):
+    print_case("edge cases")
+    torch, si, oracle = env
+    xyz, nrm = sg.uniform_box_scene(500, seed=3, box=0.5)
+    # N = 0
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), 1.0)
+    empty = torch.zeros(0, dtype=torch.int32, device="cuda")
+    img, cnt, st = si.si_generate(scene, empty, si.Params(8, 0.05, S60), stats=True)
+    assert img.shape == (0, 8, 8) and st["n_wg"] == 0
+    # N = 1, duplicates, ragged N over few workgroups, odd W, W = 2, W = 64
+    for W, idx, nwg in [(8, [5], 0), (8, [5, 5, 5, 9], 3), (5, list(range(0, 500, 3)), 7),
+                        (2, list(range(100)), 0), (64, list(range(0, 500, 11)), 5)]:
+        for mode in (0, 1):
+            B = 0.3 / W
+            img, cnt, _ = run(env, xyz, nrm, idx, W, B, S60, ["bilinear", "ceil"][mode],
+                              "gss", num_workgroups=nwg)
+            ref = oracle.generate(xyz, nrm, idx, W, B, S60, mode=mode)
+            parity.check(img, cnt, ref, mode, f"edge-W{W}-m{mode}")
+    # support angle 0 and >= pi
+    for S in (0.0, float(np.float32(math.pi)), 7.0):
+        img, cnt, _ = run(env, xyz, nrm, list(range(50)), 16, 0.02, S, "bilinear", "fac")
+        ref = oracle.generate(xyz, nrm, list(range(50)), 16, 0.02, S, mode=0)
+        parity.check(img, cnt, ref, 0, f"edge-S{S}")
+
+
+def test_nan_point_and_invalid_index(env):
+    print_case("nan point / invalid index")
+    torch, si, oracle = env
+    xyz, nrm = sg.uniform_box_scene(300, seed=4, box=0.5)
+    xyz[7] = np.nan
+    params = si.Params(16, 0.03, S60)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(params))
+    idx = np.array([0, 1, 7, 2], np.int32)
+    img, cnt, _ = si.si_generate(scene, to_dev(torch, idx), params)
+    torch.cuda.synchronize()
+    c = cnt.cpu().numpy().view(np.uint32)
+    assert c[2] == 0 and np.all(img[2].cpu().numpy() == 0)
+    ref = oracle.generate(xyz, nrm, idx, 16, 0.03, S60)
+    parity.check(img.cpu().numpy(), c, ref, 0, "nan")
+    bad = to_dev(torch, np.array([0, 300, -1, 3], np.int32))
+    with pytest.raises(si.SiError) as e:
+        si.si_generate(scene, bad, params, stats=True)
+    assert e.value.status == -1
+    img, cnt, _ = si.si_generate(scene, bad, params)
+    torch.cuda.synchronize()
+    c = cnt.cpu().numpy().view(np.uint32)
+    assert c[1] == 0xFFFFFFFF and c[2] == 0xFFFFFFFF and c[0] != 0xFFFFFFFF
+    assert np.all(img[1].cpu().numpy() == 0)
+
+
+def test_invalid_arguments(env):
+    torch, si, _ = env
+    xyz, nrm = sg.uniform_box_scene(100, seed=1)
+    params = si.Params(16, 0.02, S60)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), 0.5)
+    idx = to_dev(torch, np.arange(10, dtype=np.int32))
+    with pytest.raises(si.SiError):      # support radius 1.41 above the scene's grid radius
+        si.si_generate(scene, idx, si.Params(64, 0.02, S60))
+    with pytest.raises(si.SiError):
+        si.si_generate(scene, idx, params, si.Sched("fac", group=9))
+    with pytest.raises(si.SiError):
+        si.si_generate(scene, idx, params, si.Sched("fac", fac_divisor=0.5))
+    with pytest.raises(si.SiError):
+        si.si_generate(scene, idx, params, si.Sched("learned", fallback_to_fac=False))
+    img, cnt, st = si.si_generate(scene, idx, params, si.Sched("learned"), stats=True)
+    assert st["sched_used"] == 3   # fell back to FAC
+
+
+def test_overflow_path_identical(env):
+    """Forcing every image through the 64-bit re-accumulation path gives the
+    same images and counts."""
+    print_case("u64 path")
+    xyz, nrm = sg.config_scene("prims100k", M=8000)
+    idx = np.arange(0, 8000, 5)
+    a = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "fac")
+    os.environ["SI_TEST_OVERFLOW_LIMIT"] = "0"
+    try:
+        b = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "fac")
+        c = run(env, xyz, nrm, idx, 32, 0.02, S60, "ceil", "fac")
+    finally:
+        del os.environ["SI_TEST_OVERFLOW_LIMIT"]
+    d = run(env, xyz, nrm, idx, 32, 0.02, S60, "ceil", "fac")
+    assert b[2]["n_overflow"] == len(idx)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(c[0], d[0])
+
+
+def test_repeat_and_permutation_invariance(env):
+    """Same images on repeated runs and when the scene's points are given in
+    another order (race detector: integer accumulation is order-free)."""
+    print_case("repeat / permutation")
+    xyz, nrm = sg.config_scene("prims100k", M=20000)
+    idx = np.arange(0, 20000, 3)
+    a = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "ss")
+    b = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "ss")
+    np.testing.assert_array_equal(a[0], b[0])
+    perm = np.random.default_rng(5).permutation(20000)
+    inv = np.argsort(perm)
+    c = run(env, xyz[perm], nrm[perm], inv[idx], 32, 0.02, S60, "bilinear", "gss")
+    np.testing.assert_array_equal(a[0], c[0])
+    np.testing.assert_array_equal(a[1], c[1])
