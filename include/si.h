@@ -102,6 +102,12 @@ typedef struct si_params {
  *   fallback_to_fac SI_SCHED_LEARNED without a model: 1 = run FAC, 0 = error
  *   group           images that share one pass over their common candidate
  *                   points (1..8); 0 = library default
+ *   order           SI_ORDER_CELL (0): the loop runs over the oriented points
+ *                   sorted by grid cell, so that neighbouring images share
+ *                   candidates (iterations of a DOALL loop may run in any
+ *                   order); SI_ORDER_GIVEN (1): in the order of oriented_idx,
+ *                   as the paper's loop i = 0..N-1.  Chunks are contiguous
+ *                   ranges of that order.  Images are the same either way.
  */
 typedef struct si_sched {
     int32_t kind;
@@ -111,7 +117,13 @@ typedef struct si_sched {
     const si_cost_model* model;
     int32_t fallback_to_fac;
     int32_t group;
+    int32_t order;
 } si_sched;
+
+enum {
+    SI_ORDER_CELL = 0,
+    SI_ORDER_GIVEN = 1
+};
 
 /*
  * Optional run statistics, filled after synchronising the stream.
@@ -153,7 +165,7 @@ typedef struct si_scene_info {
 
 /*
  * Build a scene: the list of oriented points OP (Section 2.1) in the layout
- * the kernels read -- a uniform grid of cells of edge h >= R / s (s = 2 cells
+ * the kernels read -- a uniform grid of cells of edge h >= R / 3 (three cells
  * per support radius), points sorted by cell into 32-byte float4 position and
  * normal records.  The grid is conservative for every pair with
  * |x - p| <= max_support_radius; max_support_radius <= 0 builds a single

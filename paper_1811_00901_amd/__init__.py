@@ -32,6 +32,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libspinimg.
 
 SCHED = {"static": 0, "ss": 1, "gss": 2, "fac": 3, "learned": 4}
 MODE = {"bilinear": 0, "ceil": 1}
+ORDER = {"cell": 0, "given": 1}
 STATUS = {0: "SI_OK", -1: "SI_E_INVALID", -2: "SI_E_OOM", -3: "SI_E_DEVICE", -4: "SI_E_UNSUPPORTED"}
 
 
@@ -50,7 +51,7 @@ class c_sched(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("num_workgroups", ctypes.c_int32),
                 ("min_chunk", ctypes.c_int32), ("fac_divisor", ctypes.c_float),
                 ("model", ctypes.c_void_p), ("fallback_to_fac", ctypes.c_int32),
-                ("group", ctypes.c_int32)]
+                ("group", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class c_stats(ctypes.Structure):
@@ -165,12 +166,13 @@ class Sched:
     model: "CostModel | None" = None
     fallback_to_fac: bool = True
     group: int = 0
+    order: str = "cell"   # "cell": loop over points sorted by grid cell; "given": oriented_idx order
 
     def c(self) -> c_sched:
         return c_sched(SCHED[self.kind], int(self.num_workgroups), int(self.min_chunk),
                        float(self.fac_divisor),
                        self.model.handle if self.model is not None else None,
-                       1 if self.fallback_to_fac else 0, int(self.group))
+                       1 if self.fallback_to_fac else 0, int(self.group), ORDER[self.order])
 
 
 def si_support_radius(params: Params) -> float:

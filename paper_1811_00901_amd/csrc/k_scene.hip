@@ -198,7 +198,58 @@ __global__ void __launch_bounds__(256) k_scatter(const float* __restrict__ xyz,
     inv[i] = s;
 }
 
+__global__ void __launch_bounds__(256) k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Key (cell of the oriented point) and rank within its cell for each iteration.
+__global__ void __launch_bounds__(256) k_order_keys(const int32_t* __restrict__ oriented, int64_t N,
+                                                    const int32_t* __restrict__ inv,
+                                                    const float4* __restrict__ pos, int64_t M,
+                                                    int32_t* __restrict__ key,
+                                                    int32_t* __restrict__ rank,
+                                                    int32_t* __restrict__ counts) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int o = oriented[i];
+    const int c = (o >= 0 && o < M) ? __float_as_int(pos[inv[o]].w) : 0;
+    key[i] = c;
+    rank[i] = atomicAdd(counts + c, 1);
+}
+
+__global__ void __launch_bounds__(256) k_order_scatter(const int32_t* __restrict__ key,
+                                                       const int32_t* __restrict__ rank, int64_t N,
+                                                       const int32_t* __restrict__ starts,
+                                                       int32_t* __restrict__ perm) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    perm[starts[key[i]] + rank[i]] = (int32_t)i;
+}
+
 }  // namespace
+
+hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_order(const int32_t* oriented, int64_t N, const Scene& sc, int32_t* key,
+                             int32_t* rank, int32_t* counts, int32_t* starts, int32_t* tmp,
+                             int32_t* perm, hipStream_t s) {
+    hipError_t e = launch_fill(counts, sc.n_cells, 0, s);
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(k_order_keys, dim3(nb), dim3(256), 0, s, oriented, N, sc.inv, sc.pos, sc.M,
+                       key, rank, counts);
+    e = launch_scan(counts, starts, sc.n_cells, tmp, scan_tmp_elems(sc.n_cells), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, key, rank, N, starts, perm);
+    return hipGetLastError();
+}
 
 hipError_t launch_bbox(const float* xyz, int64_t M, float* out6, hipStream_t s) {
     // out6 holds 6 floats followed by scratch for kBBoxBlocks * 6 partials

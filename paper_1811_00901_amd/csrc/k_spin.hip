@@ -141,6 +141,102 @@ __device__ __forceinline__ void candidate_pass(const SceneView& sc, const SpinPa
     }
 }
 
+// Queue of one wave's in-support pairs: (beta, alpha^2) and the image slot.
+constexpr int kQueue = 256;  // entries per wave
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Bin the queued pairs of this wave densely (lane e takes entries e, e+64, ...).
+template <int MODE>
+__device__ __forceinline__ void flush_queue(const SpinParams& p, uint32_t* acc, const float2* q_ba,
+                                            const uint8_t* q_g, int qn) {
+    const int lane = threadIdx.x & 63;
+    const int W = p.W;
+    const int w2 = W * W;
+    wave_sync_lds();
+    for (int e = lane; e < qn; e += 64) {
+        const float2 ba = q_ba[e];
+        const int g = q_g[e];
+        const float v = fmaf(-ba.x, p.inv_bin, p.half);
+        const float u = sqrtf(fmaxf(ba.y, 0.0f)) * p.inv_bin;
+        if (MODE == SI_BIN_BILINEAR)
+            add_bilinear(acc + g * w2, W, v, u);
+        else
+            add_ceil(acc + g * w2, W, v, u);
+    }
+    wave_sync_lds();
+}
+
+// Test every candidate of the group's rows against `ng` images; pairs in
+// support are appended to the wave's LDS queue and binned when it fills.
+// cnt: per-image in-support counts of this wave (wave-uniform).
+template <int MODE, int G>
+__device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const SpinParams& p,
+                                                 const GroupImg* gi, int ng, uint32_t* acc,
+                                                 const int* row_start, const int* row_pref,
+                                                 int n_rows, float2* q_ba, uint8_t* q_g,
+                                                 uint32_t* cnt) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int total = row_pref[n_rows];
+    int qn = 0;
+    int r = 0;
+    for (int kb = wave * 64; kb < total; kb += kBlock) {
+        const int k = kb + lane;
+        float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float4 m = x;
+        bool valid = k < total;
+        if (valid) {
+            while (row_pref[r + 1] <= k) ++r;
+            const int j = row_start[r] + (k - row_pref[r]);
+            x = sc.pos[j];
+            m = sc.nrm[j];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g < ng) {
+                const float dx = x.x - gi[g].px;
+                const float dy = x.y - gi[g].py;
+                const float dz = x.z - gi[g].pz;
+                const float beta = fmaf(gi[g].nz, dz, fmaf(gi[g].ny, dy, gi[g].nx * dx));
+                const float dd = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const float a2 = fmaf(-beta, beta, dd);
+                bool in;
+                if (MODE == SI_BIN_BILINEAR)
+                    in = (beta <= p.beta_hi) & (beta > p.beta_lo) & (a2 < p.alpha2_max);
+                else
+                    in = (beta < p.beta_hi) & (beta >= p.beta_lo) & (a2 <= p.alpha2_max);
+                if (p.angle_on) {
+                    const float c = fmaf(gi[g].nz, m.z, fmaf(gi[g].ny, m.y, gi[g].nx * m.x));
+                    in = in & (c >= p.cos_s);
+                }
+                in = in & valid;
+                const unsigned long long mask = __ballot(in);
+                if (mask) {
+                    const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                              (uint32_t)(mask >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    if (in) {
+                        q_ba[slot] = make_float2(beta, a2);
+                        q_g[slot] = (uint8_t)g;
+                    }
+                    const int c = __popcll(mask);
+                    qn += c;
+                    cnt[g] += c;
+                    if (qn > kQueue - 64) {
+                        flush_queue<MODE>(p, acc, q_ba, q_g, qn);
+                        qn = 0;
+                    }
+                }
+            }
+        }
+    }
+    if (qn) flush_queue<MODE>(p, acc, q_ba, q_g, qn);
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -165,6 +261,8 @@ __device__ __forceinline__ void build_rows(const SceneView& sc, const SpinParams
         const double h = sc.h;
         const double R = (double)p.radius;
         const double R2 = R * R;
+        // float32 beta is accurate to ~1e-6; the slab keeps a much wider margin
+        const double slab_eps = 1e-4 * fmax(1.0, R);
         const double ylo = (double)sc.origin[1] + cy * h, yhi = ylo + h;
         const double zlo = (double)sc.origin[2] + cz * h, zhi = zlo + h;
         int x0 = 0x7fffffff, x1 = -1;
@@ -177,9 +275,28 @@ __device__ __forceinline__ void build_rows(const SceneView& sc, const SpinParams
             const double dz = fmax(0.0, fmax(zlo - pz, pz - zhi));
             const double d2 = dy * dy + dz * dz;
             if (d2 > R2) continue;
-            const double wx = sqrt(R2 - d2);
-            const double fa = floor((px - wx - (double)sc.origin[0]) / h);
-            const double fb = floor((px + wx - (double)sc.origin[0]) / h);
+            double xa = px - sqrt(R2 - d2), xb = px + sqrt(R2 - d2);
+            // slab beta_lo < n.(x - p) <= beta_hi over the row's y-z box
+            {
+                const double nx = gi[g].nx, ny = gi[g].ny, nz = gi[g].nz;
+                const double ty0 = ny * (ylo - py), ty1 = ny * (yhi - py);
+                const double tz0 = nz * (zlo - pz), tz1 = nz * (zhi - pz);
+                const double tmin = fmin(ty0, ty1) + fmin(tz0, tz1);
+                const double tmax = fmax(ty0, ty1) + fmax(tz0, tz1);
+                const double A = (double)p.beta_lo - slab_eps - tmax;  // bound of nx (x - px)
+                const double Bv = (double)p.beta_hi + slab_eps - tmin;
+                if (fabs(nx) > 1e-12) {
+                    double s0 = A / nx, s1 = Bv / nx;
+                    if (s0 > s1) { const double t = s0; s0 = s1; s1 = t; }
+                    xa = fmax(xa, px + s0);
+                    xb = fmin(xb, px + s1);
+                } else if (A > 0.0 || Bv < 0.0) {
+                    continue;
+                }
+                if (!(xa <= xb)) continue;
+            }
+            const double fa = floor((xa - (double)sc.origin[0]) / h);
+            const double fb = floor((xb - (double)sc.origin[0]) / h);
             int a = (int)fmax(-1.0, fmin(fa, 1.0e9));
             int b = (int)fmax(-1.0, fmin(fb, 1.0e9));
             int gx, gy, gz;
@@ -215,15 +332,17 @@ __device__ __forceinline__ void build_rows(const SceneView& sc, const SpinParams
 }
 
 template <int G>
-__device__ void run_group_pass(int mode, const SceneView& sc, const SpinParams& p,
-                               const GroupImg* gi, int ng, uint32_t* acc, const int* row_start,
-                               const int* row_pref, int n_rows, uint32_t* cnt) {
+__device__ __forceinline__ void run_group_pass(int mode, const SceneView& sc, const SpinParams& p,
+                                               const GroupImg* gi, int ng, uint32_t* acc,
+                                               const int* row_start, const int* row_pref,
+                                               int n_rows, float2* q_ba, uint8_t* q_g,
+                                               uint32_t* cnt) {
     if (mode == SI_BIN_BILINEAR)
-        candidate_pass<SI_BIN_BILINEAR, G, uint32_t>(sc, p, gi, ng, acc, row_start, row_pref,
-                                                     n_rows, cnt);
+        candidate_pass_q<SI_BIN_BILINEAR, G>(sc, p, gi, ng, acc, row_start, row_pref, n_rows,
+                                             q_ba, q_g, cnt);
     else
-        candidate_pass<SI_BIN_CEIL, G, uint32_t>(sc, p, gi, ng, acc, row_start, row_pref, n_rows,
-                                                 cnt);
+        candidate_pass_q<SI_BIN_CEIL, G>(sc, p, gi, ng, acc, row_start, row_pref, n_rows, q_ba,
+                                         q_g, cnt);
 }
 
 }  // namespace
@@ -237,6 +356,8 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
     __shared__ int s_n_rows;
     __shared__ uint32_t s_cnt[kMaxGroup];
     __shared__ int s_step;
+    __shared__ float2 s_q_ba[kBlock / 64][kQueue];
+    __shared__ uint8_t s_q_g[kBlock / 64][kQueue];
 
     const int tid = threadIdx.x;
     const uint64_t t_begin = wall_clock64();
@@ -363,24 +484,23 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
                 uint32_t cnt[kMaxGroup];
 #pragma unroll
                 for (int g = 0; g < kMaxGroup; ++g) cnt[g] = 0;
+                float2* q_ba = s_q_ba[tid >> 6];
+                uint8_t* q_g = s_q_g[tid >> 6];
                 if (ng > 4)
                     run_group_pass<8>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
-                                      n_rows, cnt);
+                                      n_rows, q_ba, q_g, cnt);
                 else if (ng > 2)
                     run_group_pass<4>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
-                                      n_rows, cnt);
+                                      n_rows, q_ba, q_g, cnt);
                 else if (ng > 1)
                     run_group_pass<2>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
-                                      n_rows, cnt);
+                                      n_rows, q_ba, q_g, cnt);
                 else
                     run_group_pass<1>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
-                                      n_rows, cnt);
+                                      n_rows, q_ba, q_g, cnt);
 #pragma unroll
                 for (int g = 0; g < kMaxGroup; ++g) {
-                    if (g < ng) {
-                        const uint32_t s = wave_sum(cnt[g]);
-                        if ((tid & 63) == 0 && s) atomicAdd(&s_cnt[g], s);
-                    }
+                    if (g < ng && (tid & 63) == 0 && cnt[g]) atomicAdd(&s_cnt[g], cnt[g]);
                 }
                 if (tid == 0) my_tested += (unsigned long long)s_row_pref[n_rows] * ng;
                 __syncthreads();

@@ -59,6 +59,11 @@ si_status device_state(DeviceState** out) {
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
                 hipSuccess && lds > 0)
             st.max_lds = std::min(lds, 65536);
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;  // stream-ordered temporaries stay cached
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
         SI_HIP(hipMalloc(&st.counters, sizeof(uint32_t) * kCounterSlots * kCounterStride));
         SI_HIP(hipMemset(st.counters, 0, sizeof(uint32_t) * kCounterSlots * kCounterStride));
         SI_HIP(hipDeviceSynchronize());
@@ -304,7 +309,7 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     if (e == hipSuccess) e = hipMalloc(&rank, sizeof(int32_t) * M);
     if (e == hipSuccess) e = hipMalloc(&counts, sizeof(int32_t) * sc->n_cells);
     if (e == hipSuccess) e = hipMalloc(&tmp, sizeof(int32_t) * ntmp);
-    if (e == hipSuccess) e = hipMemsetAsync(counts, 0, sizeof(int32_t) * sc->n_cells, s);
+    if (e == hipSuccess) e = launch_fill(counts, sc->n_cells, 0, s);
     if (e == hipSuccess) e = launch_bin_points(points_xyz, M, *sc, cell_of, rank, counts, s);
     if (e == hipSuccess) e = launch_scan(counts, sc->cell_start, sc->n_cells, tmp, ntmp, s);
     if (e == hipSuccess)
@@ -392,7 +397,7 @@ si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_st
     if (stats) {
         const size_t words = 4 + (size_t)n_wg;
         SI_HIP(hipMalloc(&dev_stats, sizeof(unsigned long long) * words));
-        SI_HIP(hipMemsetAsync(dev_stats, 0, sizeof(unsigned long long) * words, s));
+        SI_HIP(launch_fill(reinterpret_cast<int32_t*>(dev_stats), (int64_t)(2 * words), 0, s));
         d.stat_tested = dev_stats;
         d.stat_support = dev_stats + 1;
         d.stat_invalid = reinterpret_cast<uint32_t*>(dev_stats + 2);
@@ -450,6 +455,32 @@ si_status check_sched(const si_sched* sc) {
     if (sc->fac_divisor > 0.0f && sc->fac_divisor < 1.0f)
         return fail(SI_E_INVALID, "fac_divisor must be >= 1");
     if (sc->group < 0 || sc->group > kMaxGroup) return fail(SI_E_INVALID, "group must be in [0, 8]");
+    if (sc->order != SI_ORDER_CELL && sc->order != SI_ORDER_GIVEN)
+        return fail(SI_E_INVALID, "order must be SI_ORDER_CELL or SI_ORDER_GIVEN");
+    return SI_OK;
+}
+
+// Iterations sorted by the cell of their oriented point, in stream-ordered
+// memory released (stream-ordered) by the caller after the launch.
+si_status cell_order(const Scene& sc, const int32_t* oriented, int64_t N, hipStream_t s,
+                     int32_t** mem_out, const int32_t** perm_out) {
+    const int64_t nt = scan_tmp_elems(sc.n_cells);
+    const int64_t words = 3 * N + sc.n_cells + (sc.n_cells + 1) + nt;
+    int32_t* mem = nullptr;
+    SI_HIP(hipMallocAsync((void**)&mem, sizeof(int32_t) * words, s));
+    int32_t* perm = mem;
+    int32_t* key = perm + N;
+    int32_t* rank = key + N;
+    int32_t* counts = rank + N;
+    int32_t* starts = counts + sc.n_cells;
+    int32_t* tmp = starts + sc.n_cells + 1;
+    hipError_t e = launch_cell_order(oriented, N, sc, key, rank, counts, starts, tmp, perm, s);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(mem, s);
+        return hip_fail(e, "cell order");
+    }
+    *mem_out = mem;
+    *perm_out = perm;
     return SI_OK;
 }
 
@@ -530,14 +561,21 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
             d.single.perm = perm;
         }
     }
+    int32_t* order_mem = nullptr;
     if (kind != SI_SCHED_LEARNED) {
         rc = get_table(st, kind, N, n_wg, sched->min_chunk, sched->fac_divisor, &chunks, &n_chunks);
         if (rc != SI_OK) return rc;
+        if (sched->order == SI_ORDER_CELL && scene->n_cells > 1) {
+            rc = cell_order(*scene, oriented_idx, N, s, &order_mem, &d.single.perm);
+            if (rc != SI_OK) return rc;
+        }
     }
     d.chunks = chunks;
     d.n_chunks = n_chunks;
     d.dynamic = kind == SI_SCHED_STATIC ? 0 : 1;
-    return run_launch(st, d, n_wg, w2, stats, s, kind);
+    rc = run_launch(st, d, n_wg, w2, stats, s, kind);
+    if (order_mem) (void)hipFreeAsync(order_mem, s);
+    return rc;
 }
 
 extern "C" {

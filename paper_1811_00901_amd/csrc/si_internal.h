@@ -26,7 +26,7 @@ si_status hip_fail(hipError_t e, const char* what);
 
 // ----------------------------------------------------------------- scene --
 // Grid cells per support radius: cell edge h = R_max (1 + 2e-5) / kSub.
-constexpr int kSub = 2;
+constexpr int kSub = 3;
 // Cap on the number of grid cells of one scene; a larger box gets bigger cells.
 constexpr int64_t kMaxCells = int64_t(1) << 25;
 
@@ -119,6 +119,13 @@ hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t tmp_n,
                        hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// perm: iterations sorted by the cell of their oriented point (counting sort;
+// order within a cell is arbitrary).  Temporaries: key, rank (N), counts
+// (n_cells), starts (n_cells + 1), tmp (scan_tmp_elems(n_cells)).
+hipError_t launch_cell_order(const int32_t* oriented, int64_t N, const Scene& sc, int32_t* key,
+                             int32_t* rank, int32_t* counts, int32_t* starts, int32_t* tmp,
+                             int32_t* perm, hipStream_t s);
 hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* cell_of,
                           const int32_t* rank, const int32_t* cell_start, Scene& sc,
                           hipStream_t s);
@@ -143,6 +150,8 @@ SceneView view_of(const Scene& s);
 int default_group(int W);
 int fit_group(DeviceState* st, int group, int max_w2);
 int auto_workgroups(DeviceState* st, int max_w2, int group);
+si_status cell_order(const Scene& sc, const int32_t* oriented, int64_t N, hipStream_t s,
+                     int32_t** mem_out, const int32_t** perm_out);
 si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk, float divisor,
                     Chunk** out, int* n_out);
 si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_stats* stats,

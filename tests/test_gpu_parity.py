@@ -118,6 +118,11 @@ def test_prims_small_all_schedules(env, mode):
         else:
             np.testing.assert_array_equal(img, base[0])
             np.testing.assert_array_equal(cnt, base[1])
+    # the paper's loop order (oriented_idx as given) and other group sizes
+    for kw in (dict(order="given"), dict(group=1), dict(group=3, order="given")):
+        img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, mode, "fac", **kw)
+        np.testing.assert_array_equal(img, base[0])
+        np.testing.assert_array_equal(cnt, base[1])
 
 
 def test_cell_list_equals_brute_force(env):
