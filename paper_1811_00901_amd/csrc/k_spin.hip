@@ -58,35 +58,40 @@ __device__ __forceinline__ void cell_xyz(int cell, const int* dims, int& cx, int
     cz = t / dims[1];
 }
 
-// Accumulate one in-support pair (bilinear) into a u32 or u64 LDS image.
-template <typename Acc>
-__device__ __forceinline__ void add_bilinear(Acc* img, int W, float v, float u) {
-    int i0 = (int)floorf(v);
-    int j0 = (int)floorf(u);
-    i0 = min(max(i0, 0), W - 2);
-    j0 = min(max(j0, 0), W - 2);
-    const float a = fminf(fmaxf(v - (float)i0, 0.0f), 1.0f);
-    const float b = fminf(fmaxf(u - (float)j0, 0.0f), 1.0f);
-    const uint32_t qa = (uint32_t)rintf(a * 65536.0f);
-    const uint32_t qb = (uint32_t)rintf(b * 65536.0f);
-    const uint32_t q11 = (uint32_t)(((uint64_t)qa * qb + 32768u) >> 16);
-    const uint32_t q10 = qa - q11;
-    const uint32_t q01 = qb - q11;
-    const uint32_t q00 = 65536u - qa - qb + q11;
-    Acc* r0 = img + i0 * W + j0;
-    atomicAdd(r0, (Acc)q00);
-    atomicAdd(r0 + 1, (Acc)q01);
-    atomicAdd(r0 + W, (Acc)q10);
-    atomicAdd(r0 + W + 1, (Acc)q11);
-}
-
-template <typename Acc>
-__device__ __forceinline__ void add_ceil(Acc* img, int W, float v, float u) {
-    int k = (int)ceilf(v);
-    int l = (int)ceilf(u);
-    k = min(max(k, 0), W - 1);
-    l = min(max(l, 0), W - 1);
-    atomicAdd(img + k * W + l, (Acc)65536u);
+// Accumulate one in-support pair, given beta and alpha^2, into a u32 or u64
+// LDS image.  Bilinear: the four 16.16 weights are rounded so that they sum
+// to exactly 65536; they tolerate the 1-ulp hardware square root (a one-ulp
+// change of u moves at most one quantisation step).  Ceil: bin += 65536, with
+// the correctly rounded square root since ceil(alpha/B) jumps at integers.
+// Every path that bins a pair uses this function, so results do not depend
+// on which path ran.
+template <int MODE, typename Acc>
+__device__ __forceinline__ void bin_pair(Acc* img, const SpinParams& p, float beta, float a2) {
+    const int W = p.W;
+    const float v = fmaf(-beta, p.inv_bin, p.half);
+    a2 = fmaxf(a2, 0.0f);
+    if (MODE == SI_BIN_BILINEAR) {
+        const float u = __builtin_amdgcn_sqrtf(a2) * p.inv_bin;
+        const float fi = fminf(fmaxf(floorf(v), 0.0f), (float)(W - 2));
+        const float fj = fminf(fmaxf(floorf(u), 0.0f), (float)(W - 2));
+        const float a = __saturatef(v - fi);
+        const float b = __saturatef(u - fj);
+        const uint32_t qa = (uint32_t)rintf(a * 65536.0f);
+        const uint32_t qb = (uint32_t)rintf(b * 65536.0f);
+        const uint32_t q11 = (uint32_t)(((uint64_t)qa * qb + 32768u) >> 16);
+        Acc* r0 = img + __umul24((uint32_t)fi, (uint32_t)W) + (uint32_t)fj;
+        atomicAdd(r0, (Acc)(65536u - qa - qb + q11));
+        atomicAdd(r0 + 1, (Acc)(qb - q11));
+        atomicAdd(r0 + W, (Acc)(qa - q11));
+        atomicAdd(r0 + W + 1, (Acc)q11);
+    } else {
+        const float u = sqrtf(a2) * p.inv_bin;
+        int k = (int)ceilf(v);
+        int l = (int)ceilf(u);
+        k = min(max(k, 0), W - 1);
+        l = min(max(l, 0), W - 1);
+        atomicAdd(img + k * W + l, (Acc)65536u);
+    }
 }
 
 struct GroupImg {
@@ -128,12 +133,7 @@ __device__ __forceinline__ void candidate_pass(const SceneView& sc, const SpinPa
                     in = in & (c >= p.cos_s);
                 }
                 if (in) {
-                    const float v = fmaf(-beta, p.inv_bin, p.half);
-                    const float u = sqrtf(fmaxf(a2, 0.0f)) * p.inv_bin;
-                    if (MODE == SI_BIN_BILINEAR)
-                        add_bilinear(acc + g * w2, W, v, u);
-                    else
-                        add_ceil(acc + g * w2, W, v, u);
+                    bin_pair<MODE>(acc + g * w2, p, beta, a2);
                     cnt[g] += 1;
                 }
             }
@@ -144,6 +144,8 @@ __device__ __forceinline__ void candidate_pass(const SceneView& sc, const SpinPa
 // Queue of one wave's in-support pairs: (beta, alpha^2) and the image slot.
 constexpr int kQueue = 256;  // entries per wave
 
+typedef __attribute__((address_space(1))) const f32x4 gf32x4;
+
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -152,55 +154,62 @@ __device__ __forceinline__ void wave_sync_lds() {
 // Bin the queued pairs of this wave densely (lane e takes entries e, e+64, ...).
 template <int MODE>
 __device__ __forceinline__ void flush_queue(const SpinParams& p, uint32_t* acc, const float2* q_ba,
-                                            const uint8_t* q_g, int qn) {
+                                            const uint32_t* q_g, int qn) {
     const int lane = threadIdx.x & 63;
-    const int W = p.W;
-    const int w2 = W * W;
+    const uint32_t w2 = (uint32_t)(p.W * p.W);
     wave_sync_lds();
     for (int e = lane; e < qn; e += 64) {
         const float2 ba = q_ba[e];
-        const int g = q_g[e];
-        const float v = fmaf(-ba.x, p.inv_bin, p.half);
-        const float u = sqrtf(fmaxf(ba.y, 0.0f)) * p.inv_bin;
-        if (MODE == SI_BIN_BILINEAR)
-            add_bilinear(acc + g * w2, W, v, u);
-        else
-            add_ceil(acc + g * w2, W, v, u);
+        bin_pair<MODE>(acc + __umul24(q_g[e], w2), p, ba.x, ba.y);
     }
     wave_sync_lds();
 }
 
 // Test every candidate of the group's rows against `ng` images; pairs in
 // support are appended to the wave's LDS queue and binned when it fills.
+// Each lane walks candidates k = wave*64 + lane, +256, ... with the next
+// candidate's loads issued before the current one is tested.
 // cnt: per-image in-support counts of this wave (wave-uniform).
 template <int MODE, int G>
 __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const SpinParams& p,
                                                  const GroupImg* gi, int ng, uint32_t* acc,
                                                  const int* row_start, const int* row_pref,
-                                                 int n_rows, float2* q_ba, uint8_t* q_g,
+                                                 int n_rows, float2* q_ba, uint32_t* q_g,
                                                  uint32_t* cnt) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int total = row_pref[n_rows];
-    int qn = 0;
-    int r = 0;
-    for (int kb = wave * 64; kb < total; kb += kBlock) {
-        const int k = kb + lane;
-        float4 x = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float4 m = x;
-        bool valid = k < total;
-        if (valid) {
-            while (row_pref[r + 1] <= k) ++r;
-            const int j = row_start[r] + (k - row_pref[r]);
-            x = sc.pos[j];
-            m = sc.nrm[j];
+    gf32x4* gpos = (gf32x4*)sc.pos;
+    gf32x4* gnrm = (gf32x4*)sc.nrm;
+    // row cursor: rows [r_lo, r_hi) of the flattened candidate list start at r_st
+    int r = 0, r_lo = 0, r_hi = row_pref[1], r_st = row_start[0];
+    auto fetch = [&](int k, f32x4& x, f32x4& m) {
+        while (k >= r_hi) {
+            ++r;
+            r_lo = r_hi;
+            r_hi = row_pref[r + 1];
+            r_st = row_start[r];
         }
+        const int j = r_st + (k - r_lo);
+        x = gpos[j];
+        m = gnrm[j];
+    };
+    int qn = 0;
+    f32x4 xn = {0.0f, 0.0f, 0.0f, 0.0f}, mn = xn;
+    int kb = wave * 64;
+    bool vn = kb + lane < total;
+    if (vn) fetch(kb + lane, xn, mn);
+    for (; kb < total; kb += kBlock) {
+        const f32x4 x = xn, m = mn;
+        const bool valid = vn;
+        vn = kb + kBlock + lane < total;
+        if (vn) fetch(kb + kBlock + lane, xn, mn);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (g < ng) {
-                const float dx = x.x - gi[g].px;
-                const float dy = x.y - gi[g].py;
-                const float dz = x.z - gi[g].pz;
+                const float dx = x[0] - gi[g].px;
+                const float dy = x[1] - gi[g].py;
+                const float dz = x[2] - gi[g].pz;
                 const float beta = fmaf(gi[g].nz, dz, fmaf(gi[g].ny, dy, gi[g].nx * dx));
                 const float dd = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                 const float a2 = fmaf(-beta, beta, dd);
@@ -210,18 +219,18 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
                 else
                     in = (beta < p.beta_hi) & (beta >= p.beta_lo) & (a2 <= p.alpha2_max);
                 if (p.angle_on) {
-                    const float c = fmaf(gi[g].nz, m.z, fmaf(gi[g].ny, m.y, gi[g].nx * m.x));
+                    const float c = fmaf(gi[g].nz, m[2], fmaf(gi[g].ny, m[1], gi[g].nx * m[0]));
                     in = in & (c >= p.cos_s);
                 }
                 in = in & valid;
-                const unsigned long long mask = __ballot(in);
+                const uint64_t mask = __builtin_amdgcn_ballot_w64(in);
                 if (mask) {
-                    const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                              (uint32_t)(mask >> 32),
-                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                     if (in) {
+                        const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                  (uint32_t)(mask >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                         q_ba[slot] = make_float2(beta, a2);
-                        q_g[slot] = (uint8_t)g;
+                        q_g[slot] = (uint32_t)g;
                     }
                     const int c = __popcll(mask);
                     qn += c;
@@ -335,7 +344,7 @@ template <int G>
 __device__ __forceinline__ void run_group_pass(int mode, const SceneView& sc, const SpinParams& p,
                                                const GroupImg* gi, int ng, uint32_t* acc,
                                                const int* row_start, const int* row_pref,
-                                               int n_rows, float2* q_ba, uint8_t* q_g,
+                                               int n_rows, float2* q_ba, uint32_t* q_g,
                                                uint32_t* cnt) {
     if (mode == SI_BIN_BILINEAR)
         candidate_pass_q<SI_BIN_BILINEAR, G>(sc, p, gi, ng, acc, row_start, row_pref, n_rows,
@@ -357,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
     __shared__ uint32_t s_cnt[kMaxGroup];
     __shared__ int s_step;
     __shared__ float2 s_q_ba[kBlock / 64][kQueue];
-    __shared__ uint8_t s_q_g[kBlock / 64][kQueue];
+    __shared__ uint32_t s_q_g[kBlock / 64][kQueue];
 
     const int tid = threadIdx.x;
     const uint64_t t_begin = wall_clock64();
@@ -485,7 +494,7 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
 #pragma unroll
                 for (int g = 0; g < kMaxGroup; ++g) cnt[g] = 0;
                 float2* q_ba = s_q_ba[tid >> 6];
-                uint8_t* q_g = s_q_g[tid >> 6];
+                uint32_t* q_g = s_q_g[tid >> 6];
                 if (ng > 4)
                     run_group_pass<8>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
                                       n_rows, q_ba, q_g, cnt);

@@ -377,7 +377,7 @@ si_status si_chunk_table(int32_t kind, int64_t N, int32_t P, int32_t min_chunk,
 // --------------------------------------------------------------- generate --
 namespace si {
 
-int default_group(int W) { return W >= 64 ? 2 : 4; }
+int default_group(int W) { return W >= 64 ? 2 : 8; }
 
 // Largest group <= the requested one whose accumulators fit the LDS limit.
 int fit_group(DeviceState* st, int group, int max_w2) {
