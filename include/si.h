@@ -298,6 +298,15 @@ si_status si_learned_table(const float* unit_cost, int64_t n, int32_t P, float f
                            int32_t* perm_out, int64_t* starts_out, int64_t cap,
                            int64_t* n_chunks);
 
+/*
+ * Host-only: from now on, on the calling thread, si_generate and
+ * si_generate_batched record begin_event (a hipEvent_t) on their stream
+ * immediately before the spin-image kernel launch and end_event immediately
+ * after it, so a caller can time that kernel alone without synchronising.
+ * NULL, NULL turns this off.  The events are owned by the caller.
+ */
+si_status si_set_kernel_events(void* begin_event, void* end_event);
+
 const char* si_status_string(si_status status);
 const char* si_last_error(void);
 int32_t si_abi_version(void);

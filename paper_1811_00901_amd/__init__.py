@@ -25,6 +25,7 @@ __all__ = [
     "si_build_scene", "si_generate", "si_generate_batched", "si_features",
     "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
     "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
+    "si_set_kernel_events",
     "SCHED", "MODE",
 ]
 
@@ -105,6 +106,7 @@ def lib():
             "si_cost_model_load": (I32, [ctypes.c_char_p, ctypes.POINTER(P)]),
             "si_chunk_table": (I32, [I32, I64, I32, I32, F, P, I64, ctypes.POINTER(I64)]),
             "si_learned_table": (I32, [P, I64, I32, F, P, P, I64, ctypes.POINTER(I64)]),
+            "si_set_kernel_events": (I32, [P, P]),
             "si_status_string": (ctypes.c_char_p, [I32]),
             "si_last_error": (ctypes.c_char_p, []),
             "si_abi_version": (I32, []),
@@ -138,6 +140,17 @@ def _dev_ptr(t: torch.Tensor, dtype, name: str, shape=None) -> ctypes.c_void_p:
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def si_set_kernel_events(begin, end):
+    """Record torch.cuda.Event objects around every following spin-kernel
+    launch on this thread (None, None to stop)."""
+    for ev in (begin, end):
+        if ev is not None and not ev.cuda_event:
+            ev.record()  # torch creates the underlying event lazily, on first record
+    b = ctypes.c_void_p(begin.cuda_event) if begin is not None else None
+    e = ctypes.c_void_p(end.cuda_event) if end is not None else None
+    _check(lib().si_set_kernel_events(b, e))
 
 
 def si_abi_version() -> int:

@@ -33,6 +33,10 @@ si_status hip_fail(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? SI_E_OOM : SI_E_DEVICE;
 }
 
+// caller-supplied events recorded around spin-kernel launches (this thread)
+static thread_local hipEvent_t g_ev_begin = nullptr;
+static thread_local hipEvent_t g_ev_end = nullptr;
+
 // --------------------------------------------------------- device state --
 namespace {
 
@@ -411,7 +415,9 @@ si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_st
         d.stat_invalid = d.stat_overflow = nullptr;
         d.wg_ns = nullptr;
     }
+    if (g_ev_begin) SI_HIP(hipEventRecord(g_ev_begin, s));
     hipError_t e = launch_spin(d, n_wg, s);
+    if (e == hipSuccess && g_ev_end) e = hipEventRecord(g_ev_end, s);
     if (e != hipSuccess) {
         (void)hipFree(dev_stats);
         return hip_fail(e, "spin-image launch");
@@ -592,6 +598,14 @@ const char* si_status_string(si_status status) {
 }
 
 const char* si_last_error(void) { return g_last_error.c_str(); }
+
+si_status si_set_kernel_events(void* begin_event, void* end_event) {
+    if ((begin_event == nullptr) != (end_event == nullptr))
+        return fail(SI_E_INVALID, "give both events or neither");
+    g_ev_begin = (hipEvent_t)begin_event;
+    g_ev_end = (hipEvent_t)end_event;
+    return SI_OK;
+}
 
 int32_t si_abi_version(void) { return SI_ABI_VERSION; }
 
