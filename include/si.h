@@ -228,7 +228,11 @@ typedef struct si_batch_item {
  * (pointers, sizes, params) and schedule are unchanged.  sched->kind is any
  * SI_SCHED_* (LEARNED uses sched->model on every scene).  Every item is
  * validated as in si_generate; results are identical to one si_generate per
- * item.  Items with N == 0 are skipped.
+ * item.  Items with N == 0 are skipped.  Without a graph the call stages its
+ * tables and synchronises the stream once before launching; the first call
+ * with a new item list in graph mode also synchronises (capture).  The graph
+ * cache holds up to 8 item lists per process; entries hold device pointers of
+ * the scenes and buffers they were built for, so a replay needs them alive.
  */
 si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
                               const si_sched* sched, int32_t use_graph,

@@ -1,0 +1,462 @@
+// Batched generation: the images of many scenes in one persistent launch.
+//
+// The per-image loops of all items are concatenated into one DOALL loop of
+// sum(N) iterations.  A schedule of Section 2.2 is computed over the whole
+// concatenation for P workgroups and every chunk that crosses an item
+// boundary is split there, so that a chunk never spans two scenes (STATIC
+// keeps each workgroup's pieces in its own range).  The cell ordering of the
+// iterations is one counting sort over all items (keys offset by each item's
+// cell count).  With use_graph the sort and the spin kernel are captured once
+// into a HIP graph, cached per item list, and replayed.
+#include <stddef.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "si_internal.h"
+
+namespace si {
+
+namespace {
+
+struct Flat {
+    std::vector<Item> items;
+    std::vector<int64_t> item_off;   // n + 1
+    std::vector<int64_t> cell_base;  // n + 1
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> wg_first;   // static only, n_wg + 1
+    int max_w2 = 0;
+    int group = 0;
+    int n_wg = 0;
+    int kind = 0;
+    bool ordered = false;
+    int64_t total_N = 0;
+    int64_t total_cells = 0;
+};
+
+// Device memory of one flattened launch (one allocation).
+struct FlatMem {
+    char* base = nullptr;
+    size_t bytes = 0;
+    Item* items = nullptr;
+    int64_t* item_off = nullptr;
+    int64_t* cell_base = nullptr;
+    Chunk* chunks = nullptr;
+    int32_t* wg_first = nullptr;
+    int32_t* perm = nullptr;
+    int32_t* key = nullptr;
+    int32_t* rank = nullptr;
+    int32_t* counts = nullptr;
+    int32_t* starts = nullptr;
+    int32_t* tmp = nullptr;
+    unsigned long long* stats = nullptr;  // 4 + n_wg words
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Lay the buffers out in one block; returns the byte size.
+size_t layout(const Flat& f, FlatMem& m, char* base) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + o : nullptr;
+        o += align_up(std::max<size_t>(bytes, 1));
+        return p;
+    };
+    const size_t n = f.items.size();
+    m.items = (Item*)take(sizeof(Item) * n);
+    m.item_off = (int64_t*)take(sizeof(int64_t) * (n + 1));
+    m.cell_base = (int64_t*)take(sizeof(int64_t) * (n + 1));
+    m.chunks = (Chunk*)take(sizeof(Chunk) * f.chunks.size());
+    m.wg_first = (int32_t*)take(sizeof(int32_t) * f.wg_first.size());
+    m.stats = (unsigned long long*)take(sizeof(unsigned long long) * (4 + (size_t)f.n_wg));
+    if (f.ordered) {
+        m.perm = (int32_t*)take(sizeof(int32_t) * f.total_N);
+        m.key = (int32_t*)take(sizeof(int32_t) * f.total_N);
+        m.rank = (int32_t*)take(sizeof(int32_t) * f.total_N);
+        m.counts = (int32_t*)take(sizeof(int32_t) * f.total_cells);
+        m.starts = (int32_t*)take(sizeof(int32_t) * (f.total_cells + 1));
+        m.tmp = (int32_t*)take(sizeof(int32_t) * scan_tmp_elems(f.total_cells));
+    }
+    m.base = base;
+    m.bytes = o;
+    return o;
+}
+
+void flat_chunks(Flat& f, int min_chunk, float divisor) {
+    const int64_t total = f.total_N;
+    const int P = f.n_wg;
+    const int64_t n = chunk_sizes(f.kind, total, P, min_chunk, divisor, nullptr, 0);
+    std::vector<int64_t> st(n + 1);
+    chunk_sizes(f.kind, total, P, min_chunk, divisor, st.data(), n + 1);
+    const bool stat = f.kind == SI_SCHED_STATIC;
+    if (stat) f.wg_first.assign(P + 1, 0);
+    size_t it = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        if (stat) f.wg_first[c] = (int32_t)f.chunks.size();
+        int64_t a = st[c];
+        const int64_t b = st[c + 1];
+        while (a < b) {
+            while (f.item_off[it + 1] <= a) ++it;
+            const int64_t e = std::min(b, f.item_off[it + 1]);
+            f.chunks.push_back({(int32_t)it, (int32_t)(a - f.item_off[it]),
+                                (int32_t)(e - f.item_off[it])});
+            a = e;
+        }
+    }
+    if (stat) f.wg_first[P] = (int32_t)f.chunks.size();
+}
+
+si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_items,
+                     const si_sched* sched, Flat& f) {
+    int dev = 0;
+    SI_HIP(hipGetDevice(&dev));
+    f.item_off.push_back(0);
+    f.cell_base.push_back(0);
+    for (int32_t k = 0; k < n_items; ++k) {
+        const si_batch_item& b = items[k];
+        if (b.N == 0) continue;
+        if (!b.scene) return fail(SI_E_INVALID, "batch item " + std::to_string(k) + ": scene is NULL");
+        if (b.N < 0 || b.N >= INT32_MAX)
+            return fail(SI_E_INVALID, "batch item " + std::to_string(k) + ": N out of range");
+        if (!b.oriented_idx || !b.images_out || !b.counts_out)
+            return fail(SI_E_INVALID, "batch item " + std::to_string(k) + ": NULL buffer");
+        if (b.scene->device != dev)
+            return fail(SI_E_INVALID, "batch item " + std::to_string(k) + ": scene on another device");
+        SpinParams p;
+        double R;
+        si_status rc = make_params(&b.params, &p, &R);
+        if (rc != SI_OK) return fail(rc, "batch item " + std::to_string(k) + ": " + si_last_error());
+        const Scene& sc = *b.scene;
+        if (sc.max_radius > 0.0f && R > (double)sc.max_radius * (1.0 + 1e-6))
+            return fail(SI_E_INVALID, "batch item " + std::to_string(k) +
+                                          ": support radius exceeds the scene's max_support_radius");
+        p.reach = sc.max_radius > 0.0f ? (int)floor((double)p.radius / sc.h) + 1 : 0;
+        if (p.reach > kSub + 1) return fail(SI_E_INVALID, "support radius too large for the grid");
+        Item it;
+        memset(&it, 0, sizeof(it));
+        it.scene = view_of(sc);
+        it.p = p;
+        it.oriented = b.oriented_idx;
+        it.images = b.images_out;
+        it.counts = b.counts_out;
+        it.N = b.N;
+        it.perm = nullptr;
+        f.items.push_back(it);
+        f.item_off.push_back(f.item_off.back() + b.N);
+        f.cell_base.push_back(f.cell_base.back() + sc.n_cells);
+        f.max_w2 = std::max(f.max_w2, p.W * p.W);
+    }
+    f.total_N = f.item_off.back();
+    f.total_cells = f.cell_base.back();
+    if (f.total_N >= INT32_MAX || f.total_cells >= INT32_MAX)
+        return fail(SI_E_INVALID, "batch too large (2^31 images or cells)");
+    if (f.items.empty()) return SI_OK;
+    f.kind = sched->kind == SI_SCHED_LEARNED ? SI_SCHED_FAC : sched->kind;
+    int g = sched->group > 0 ? sched->group : 8;
+    f.group = fit_group(st, g, f.max_w2);
+    f.n_wg = sched->num_workgroups > 0 ? sched->num_workgroups
+                                       : auto_workgroups(st, f.max_w2, f.group);
+    f.ordered = sched->order == SI_ORDER_CELL && f.total_cells > (int64_t)f.items.size();
+    flat_chunks(f, sched->min_chunk, sched->fac_divisor);
+    return SI_OK;
+}
+
+// Upload the host-side tables into m (synchronous copies from pageable memory).
+si_status upload(const Flat& f, FlatMem& m, hipStream_t s) {
+    std::vector<Item> items = f.items;
+    for (size_t i = 0; i < items.size(); ++i)
+        items[i].perm = f.ordered ? m.perm + f.item_off[i] : nullptr;
+    SI_HIP(hipMemcpyAsync(m.items, items.data(), sizeof(Item) * items.size(),
+                          hipMemcpyHostToDevice, s));
+    SI_HIP(hipMemcpyAsync(m.item_off, f.item_off.data(), sizeof(int64_t) * f.item_off.size(),
+                          hipMemcpyHostToDevice, s));
+    SI_HIP(hipMemcpyAsync(m.cell_base, f.cell_base.data(), sizeof(int64_t) * f.cell_base.size(),
+                          hipMemcpyHostToDevice, s));
+    SI_HIP(hipMemcpyAsync(m.chunks, f.chunks.data(), sizeof(Chunk) * f.chunks.size(),
+                          hipMemcpyHostToDevice, s));
+    if (!f.wg_first.empty())
+        SI_HIP(hipMemcpyAsync(m.wg_first, f.wg_first.data(), sizeof(int32_t) * f.wg_first.size(),
+                              hipMemcpyHostToDevice, s));
+    return SI_OK;
+}
+
+LaunchDesc desc_of(const Flat& f, const FlatMem& m, uint32_t* counter, bool stats) {
+    LaunchDesc d;
+    memset(&d, 0, sizeof(d));
+    d.items = m.items;
+    d.chunks = m.chunks;
+    d.n_chunks = (int32_t)f.chunks.size();
+    d.dynamic = f.kind == SI_SCHED_STATIC ? 0 : 1;
+    d.wg_first = f.kind == SI_SCHED_STATIC ? m.wg_first : nullptr;
+    d.counter = counter;
+    d.group = f.group;
+    d.max_w2 = f.max_w2;
+    d.ovf_limit = 65536u;
+    if (const char* lim = getenv("SI_TEST_OVERFLOW_LIMIT")) d.ovf_limit = (uint32_t)atol(lim);
+    if (stats) {
+        d.stat_tested = m.stats;
+        d.stat_support = m.stats + 1;
+        d.stat_invalid = reinterpret_cast<uint32_t*>(m.stats + 2);
+        d.stat_overflow = reinterpret_cast<uint32_t*>(m.stats + 3);
+        d.wg_ns = m.stats + 4;
+    }
+    return d;
+}
+
+// Enqueue ordering + spin kernel (the body of a graph, or a direct launch).
+hipError_t enqueue(const Flat& f, const FlatMem& m, const LaunchDesc& d, bool stats,
+                   hipEvent_t ev0, hipEvent_t ev1, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (stats) e = launch_fill(reinterpret_cast<int32_t*>(m.stats), 2 * (4 + (int64_t)f.n_wg), 0, s);
+    if (e == hipSuccess && f.ordered)
+        e = launch_cell_order_multi(m.items, m.item_off, m.cell_base, (int)f.items.size(),
+                                    f.total_N, f.total_cells, m.key, m.rank, m.counts, m.starts,
+                                    m.tmp, m.perm, s);
+    if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
+    if (e == hipSuccess) e = launch_spin(d, f.n_wg, s);
+    if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    return e;
+}
+
+si_status read_stats(DeviceState* st, const Flat& f, const FlatMem& m, float ms, si_stats* stats,
+                     hipStream_t s) {
+    std::vector<unsigned long long> h(4 + (size_t)f.n_wg);
+    SI_HIP(hipMemcpyAsync(h.data(), m.stats, sizeof(unsigned long long) * h.size(),
+                          hipMemcpyDeviceToHost, s));
+    SI_HIP(hipStreamSynchronize(s));
+    stats->kernel_ms = ms;
+    stats->pairs_tested = h[0];
+    stats->pairs_in_support = h[1];
+    stats->n_invalid = (int32_t)(uint32_t)h[2];
+    stats->n_overflow = (int32_t)(uint32_t)h[3];
+    stats->sched_used = f.kind;
+    stats->n_wg = f.n_wg;
+    stats->n_chunks = (int32_t)f.chunks.size();
+    if (stats->wg_busy_ns) {
+        const int n = std::min(stats->wg_busy_cap, f.n_wg);
+        for (int i = 0; i < n; ++i)
+            stats->wg_busy_ns[i] = (uint64_t)((double)h[4 + i] * 1e6 / (double)st->wall_khz);
+    }
+    if (stats->n_invalid) return fail(SI_E_INVALID, "oriented_idx holds indices outside [0, M)");
+    return SI_OK;
+}
+
+// ---- graph cache ----
+struct GraphEntry {
+    Flat flat;
+    FlatMem mem;
+    uint32_t* counter = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    uint64_t last_use = 0;
+};
+
+std::mutex g_graph_mu;
+std::map<std::string, GraphEntry*> g_graphs;
+uint64_t g_graph_clock = 0;
+constexpr size_t kMaxGraphs = 8;
+
+void free_entry(GraphEntry* e) {
+    if (!e) return;
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->ev0) (void)hipEventDestroy(e->ev0);
+    if (e->ev1) (void)hipEventDestroy(e->ev1);
+    (void)hipFree(e->mem.base);
+    (void)hipFree(e->counter);
+    delete e;
+}
+
+std::string graph_key(const si_batch_item* items, int32_t n_items, const si_sched* sched,
+                      bool stats, int dev) {
+    std::string k;
+    k.reserve(64 + (size_t)n_items * 96);
+    auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+    put(&dev, sizeof(dev));
+    put(&stats, sizeof(stats));
+    si_sched sc = *sched;
+    put(&sc.kind, sizeof(sc.kind));
+    put(&sc.num_workgroups, sizeof(sc.num_workgroups));
+    put(&sc.min_chunk, sizeof(sc.min_chunk));
+    put(&sc.fac_divisor, sizeof(sc.fac_divisor));
+    put(&sc.group, sizeof(sc.group));
+    put(&sc.order, sizeof(sc.order));
+    const char* lim = getenv("SI_TEST_OVERFLOW_LIMIT");
+    k.append(lim ? lim : "-");
+    for (int32_t i = 0; i < n_items; ++i) {
+        const si_batch_item& b = items[i];
+        put(&b.scene, sizeof(b.scene));
+        if (b.scene) {
+            put(&b.scene->pos, sizeof(b.scene->pos));
+            put(&b.scene->n_cells, sizeof(b.scene->n_cells));
+        }
+        put(&b.oriented_idx, sizeof(b.oriented_idx));
+        put(&b.N, sizeof(b.N));
+        put(&b.params, sizeof(b.params));
+        put(&b.images_out, sizeof(b.images_out));
+        put(&b.counts_out, sizeof(b.counts_out));
+    }
+    return k;
+}
+
+si_status make_graph(DeviceState* st, const si_batch_item* items, int32_t n_items,
+                     const si_sched* sched, bool stats, GraphEntry** out) {
+    GraphEntry* e = new (std::nothrow) GraphEntry();
+    if (!e) return fail(SI_E_OOM, "host allocation failed");
+    si_status rc = build_flat(st, items, n_items, sched, e->flat);
+    if (rc != SI_OK) { delete e; return rc; }
+    if (e->flat.items.empty()) {  // nothing to launch: an entry without a graph
+        *out = e;
+        return SI_OK;
+    }
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t err = hipSuccess;
+    const size_t bytes = layout(e->flat, e->mem, nullptr);
+    char* base = nullptr;
+    err = hipMalloc(&base, bytes);
+    if (err == hipSuccess) err = hipMalloc(&e->counter, 2 * sizeof(uint32_t));
+    if (err == hipSuccess) err = hipMemset(e->counter, 0, 2 * sizeof(uint32_t));
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (err != hipSuccess) {
+        (void)hipFree(base);
+        free_entry(e);
+        return hip_fail(err, "graph setup");
+    }
+    layout(e->flat, e->mem, base);
+    rc = upload(e->flat, e->mem, cs);
+    if (rc == SI_OK) {
+        err = hipStreamSynchronize(cs);
+        if (err == hipSuccess) err = hipEventCreate(&e->ev0);
+        if (err == hipSuccess) err = hipEventCreate(&e->ev1);
+        LaunchDesc d = desc_of(e->flat, e->mem, e->counter, stats);
+        if (err == hipSuccess) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+            hipError_t qe = enqueue(e->flat, e->mem, d, stats, nullptr, nullptr, cs);
+            err = hipStreamEndCapture(cs, &graph);
+            if (qe != hipSuccess) err = qe;
+        }
+        if (err == hipSuccess) err = hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (err != hipSuccess) rc = hip_fail(err, "graph capture");
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != SI_OK) {
+        free_entry(e);
+        return rc;
+    }
+    *out = e;
+    return SI_OK;
+}
+
+}  // namespace
+
+}  // namespace si
+
+using namespace si;
+
+extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
+                                         const si_sched* sched, int32_t use_graph,
+                                         si_stats* stats, void* hip_stream) {
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(SI_E_INVALID, "bad item list");
+    si_status rc = check_sched(sched);
+    if (rc != SI_OK) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    DeviceState* st;
+    rc = device_state(&st);
+    if (rc != SI_OK) return rc;
+    hipEvent_t ub = nullptr, ue = nullptr;
+    user_kernel_events(&ub, &ue);
+
+    if (!use_graph) {
+        Flat f;
+        rc = build_flat(st, items, n_items, sched, f);
+        if (rc != SI_OK) return rc;
+        if (f.items.empty()) {
+            if (stats) memset(stats, 0, offsetof(si_stats, wg_busy_cap));
+            return SI_OK;
+        }
+        FlatMem m;
+        const size_t bytes = layout(f, m, nullptr);
+        char* base = nullptr;
+        SI_HIP(hipMallocAsync((void**)&base, bytes, s));
+        layout(f, m, base);
+        rc = upload(f, m, s);
+        // the staged host tables are about to go out of scope
+        if (rc == SI_OK && hipStreamSynchronize(s) != hipSuccess)
+            rc = fail(SI_E_DEVICE, "stream synchronisation failed");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (rc == SI_OK && stats) {
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                rc = fail(SI_E_DEVICE, "event creation failed");
+        }
+        if (rc == SI_OK) {
+            LaunchDesc d = desc_of(f, m, take_counter(st), stats != nullptr);
+            hipError_t e = hipSuccess;
+            if (stats) e = launch_fill(reinterpret_cast<int32_t*>(m.stats), 2 * (4 + (int64_t)f.n_wg), 0, s);
+            if (e == hipSuccess && f.ordered)
+                e = launch_cell_order_multi(m.items, m.item_off, m.cell_base, (int)f.items.size(),
+                                            f.total_N, f.total_cells, m.key, m.rank, m.counts,
+                                            m.starts, m.tmp, m.perm, s);
+            if (e == hipSuccess && e0) e = hipEventRecord(e0, s);
+            if (e == hipSuccess && ub) e = hipEventRecord(ub, s);
+            if (e == hipSuccess) e = launch_spin(d, f.n_wg, s);
+            if (e == hipSuccess && ue) e = hipEventRecord(ue, s);
+            if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
+            if (e != hipSuccess) rc = hip_fail(e, "batched launch");
+        }
+        if (rc == SI_OK && stats) {
+            float ms = 0.0f;
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            rc = read_stats(st, f, m, ms, stats, s);
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFreeAsync(base, s);
+        return rc;
+    }
+
+    // ---- graph mode ----
+    int dev = 0;
+    SI_HIP(hipGetDevice(&dev));
+    const std::string key = graph_key(items, n_items, sched, stats != nullptr, dev);
+    GraphEntry* e = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        auto it = g_graphs.find(key);
+        if (it != g_graphs.end()) e = it->second;
+    }
+    if (!e) {
+        rc = make_graph(st, items, n_items, sched, stats != nullptr, &e);
+        if (rc != SI_OK) return rc;
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        if (g_graphs.size() >= kMaxGraphs) {  // evict the least recently used entry
+            auto victim = g_graphs.begin();
+            for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+                if (it->second->last_use < victim->second->last_use) victim = it;
+            (void)hipDeviceSynchronize();
+            free_entry(victim->second);
+            g_graphs.erase(victim);
+        }
+        g_graphs[key] = e;
+    }
+    e->last_use = ++g_graph_clock;
+    if (e->flat.items.empty()) {
+        if (stats) memset(stats, 0, offsetof(si_stats, wg_busy_cap));
+        return SI_OK;
+    }
+    if (stats) SI_HIP(hipEventRecord(e->ev0, s));
+    if (ub) SI_HIP(hipEventRecord(ub, s));
+    SI_HIP(hipGraphLaunch(e->exec, s));
+    if (ue) SI_HIP(hipEventRecord(ue, s));
+    if (!stats) return SI_OK;
+    SI_HIP(hipEventRecord(e->ev1, s));
+    SI_HIP(hipEventSynchronize(e->ev1));
+    float ms = 0.0f;
+    SI_HIP(hipEventElapsedTime(&ms, e->ev0, e->ev1));
+    return read_stats(st, e->flat, e->mem, ms, stats, s);
+}

@@ -11,10 +11,6 @@ si_status learned_table(DeviceState*, const Scene*, const int32_t*, int64_t, con
 using namespace si;
 
 extern "C" {
-si_status si_generate_batched(const si_batch_item*, int32_t, const si_sched*, int32_t, si_stats*,
-                              void*) {
-    return fail(SI_E_UNSUPPORTED, "not built");
-}
 si_status si_features(const si_scene*, const int32_t*, int64_t, const si_params*, float*, void*) {
     return fail(SI_E_UNSUPPORTED, "not built");
 }

@@ -228,7 +228,63 @@ __global__ void __launch_bounds__(256) k_order_scatter(const int32_t* __restrict
     perm[starts[key[i]] + rank[i]] = (int32_t)i;
 }
 
+__device__ __forceinline__ int find_item(const int64_t* off, int n, int64_t t) {
+    int lo = 0, hi = n - 1;  // largest i with off[i] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_order_keys_multi(const Item* __restrict__ items,
+                                                          const int64_t* __restrict__ item_off,
+                                                          const int64_t* __restrict__ cell_base,
+                                                          int n_items, int64_t total_N,
+                                                          int32_t* __restrict__ key,
+                                                          int32_t* __restrict__ rank,
+                                                          int32_t* __restrict__ counts) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= total_N) return;
+    const int i = find_item(item_off, n_items, t);
+    const Item& it = items[i];
+    const int o = it.oriented[t - item_off[i]];
+    const int c = (o >= 0 && o < it.scene.M) ? __float_as_int(it.scene.pos[it.scene.inv[o]].w) : 0;
+    const int64_t k = cell_base[i] + c;
+    key[t] = (int32_t)k;
+    rank[t] = atomicAdd(counts + k, 1);
+}
+
+__global__ void __launch_bounds__(256) k_order_scatter_multi(const int32_t* __restrict__ key,
+                                                             const int32_t* __restrict__ rank,
+                                                             const int64_t* __restrict__ item_off,
+                                                             int n_items, int64_t total_N,
+                                                             const int32_t* __restrict__ starts,
+                                                             int32_t* __restrict__ perm) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= total_N) return;
+    const int i = find_item(item_off, n_items, t);
+    perm[starts[key[t]] + rank[t]] = (int32_t)(t - item_off[i]);
+}
+
 }  // namespace
+
+hipError_t launch_cell_order_multi(const Item* items, const int64_t* item_off,
+                                   const int64_t* cell_base, int n_items, int64_t total_N,
+                                   int64_t total_cells, int32_t* key, int32_t* rank,
+                                   int32_t* counts, int32_t* starts, int32_t* tmp, int32_t* perm,
+                                   hipStream_t s) {
+    hipError_t e = launch_fill(counts, total_cells, 0, s);
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)((total_N + 255) / 256);
+    hipLaunchKernelGGL(k_order_keys_multi, dim3(nb), dim3(256), 0, s, items, item_off, cell_base,
+                       n_items, total_N, key, rank, counts);
+    e = launch_scan(counts, starts, total_cells, tmp, scan_tmp_elems(total_cells), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_order_scatter_multi, dim3(nb), dim3(256), 0, s, key, rank, item_off,
+                       n_items, total_N, starts, perm);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -372,18 +372,22 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
     const uint64_t t_begin = wall_clock64();
     unsigned long long my_tested = 0, my_support = 0;
     uint32_t my_invalid = 0, my_overflow = 0;
-    bool first = true;
+    int local = 0;  // static: chunks this workgroup has taken
 
     for (;;) {
         if (tid == 0) {
             int step;
-            if (d.dynamic)
+            if (d.dynamic) {
                 step = (int)atomicAdd(d.counter, 1u);
-            else
-                step = first ? (int)blockIdx.x : d.n_chunks;
+            } else if (d.wg_first) {
+                step = d.wg_first[blockIdx.x] + local;
+                if (step >= d.wg_first[blockIdx.x + 1]) step = d.n_chunks;
+            } else {
+                step = local == 0 ? (int)blockIdx.x : d.n_chunks;
+            }
             s_step = step;
         }
-        first = false;
+        ++local;
         __syncthreads();
         const int step = rfl(s_step);
         if (step >= d.n_chunks) break;

@@ -37,6 +37,11 @@ si_status hip_fail(hipError_t e, const char* what) {
 static thread_local hipEvent_t g_ev_begin = nullptr;
 static thread_local hipEvent_t g_ev_end = nullptr;
 
+void user_kernel_events(hipEvent_t* begin, hipEvent_t* end) {
+    *begin = g_ev_begin;
+    *end = g_ev_end;
+}
+
 // --------------------------------------------------------- device state --
 namespace {
 

@@ -92,7 +92,9 @@ struct LaunchDesc {
     const Item* items;        // device array for batched launches, else nullptr
     const Chunk* chunks;      // device array, n_chunks
     int32_t n_chunks;
-    int32_t dynamic;          // 0: workgroup k runs chunk k; 1: atomic claims
+    int32_t dynamic;          // 0: static (see wg_first); 1: atomic claims
+    const int32_t* wg_first;  // static only: workgroup k runs chunks
+                              // [wg_first[k], wg_first[k+1]); nullptr = chunk k
     uint32_t* counter;        // 2 words: claim counter, finished workgroups
     int32_t group;            // images per shared candidate pass (1..kMaxGroup)
     int32_t max_w2;           // largest W*W over items (LDS sizing)
@@ -126,6 +128,15 @@ hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_cell_order(const int32_t* oriented, int64_t N, const Scene& sc, int32_t* key,
                              int32_t* rank, int32_t* counts, int32_t* starts, int32_t* tmp,
                              int32_t* perm, hipStream_t s);
+// Same for a batch: iteration t of the concatenated loop belongs to the item
+// with item_off[i] <= t < item_off[i+1]; keys are cell_base[i] + cell, and
+// perm[t'] receives the item-local iteration index.  total_cells = sum of the
+// items' cell counts.
+hipError_t launch_cell_order_multi(const Item* items, const int64_t* item_off,
+                                   const int64_t* cell_base, int n_items, int64_t total_N,
+                                   int64_t total_cells, int32_t* key, int32_t* rank,
+                                   int32_t* counts, int32_t* starts, int32_t* tmp, int32_t* perm,
+                                   hipStream_t s);
 hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* cell_of,
                           const int32_t* rank, const int32_t* cell_start, Scene& sc,
                           hipStream_t s);
@@ -143,6 +154,8 @@ struct DeviceState {
 };
 
 si_status device_state(DeviceState** out);
+// events registered by si_set_kernel_events on this thread (or null)
+void user_kernel_events(hipEvent_t* begin, hipEvent_t* end);
 uint32_t* take_counter(DeviceState* st);
 si_status make_params(const si_params* prm, SpinParams* out, double* radius);
 si_status check_sched(const si_sched* sc);

@@ -1,0 +1,137 @@
+"""GPU: batched generation of many scenes in one persistent launch.
+
+Scenes come from the batch recipe of ``scenegen`` (20-primitive scenes with
+log-uniform point counts, W in {16, 32, 64}), at reduced sizes.  A batched
+launch (with and without a HIP graph) must give exactly the images and counts
+of one si_generate per scene, for every schedule; graph replays must repeat
+the result; sampled scenes are checked against the FP64 oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+S60 = float(np.float32(math.pi / 3))
+B = 0.02
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import oracle
+    import paper_1811_00901_amd as si
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, si, oracle
+
+
+def make_batch(torch, si, n_scenes=12, m_range=(300, 6000), seed=4000, brute=()):
+    specs = sg.batch_specs(n_scenes, base_seed=seed, m_range=m_range)
+    out = []
+    for k, (s, M, W) in enumerate(specs):
+        xyz, nrm = sg.batch_scene(s, M)
+        params = si.Params(W, B, S60)
+        radius = 0.0 if k in brute else si.si_support_radius(params)
+        scene = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(), radius)
+        N = M if k % 3 else M // 2          # some scenes orient only a prefix
+        idx = torch.arange(N, dtype=torch.int32, device="cuda")
+        img = torch.full((N, W, W), -1.0, dtype=torch.float32, device="cuda")
+        cnt = torch.full((N,), -1, dtype=torch.int32, device="cuda")
+        out.append(dict(xyz=xyz, nrm=nrm, scene=scene, idx=idx, params=params, img=img, cnt=cnt,
+                        W=W, N=N))
+    return out
+
+
+def items_of(batch):
+    return [(b["scene"], b["idx"], b["params"], b["img"], b["cnt"]) for b in batch]
+
+
+def singles(si, torch, batch, sched):
+    res = []
+    for b in batch:
+        img, cnt, _ = si.si_generate(b["scene"], b["idx"], b["params"], sched)
+        res.append((img.clone(), cnt.clone()))
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("kind", ["static", "ss", "gss", "fac"])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_equals_single(env, kind, use_graph):
+    torch, si, _ = env
+    print(f"\n[case] batched {kind} graph={use_graph}", flush=True)
+    batch = make_batch(torch, si, brute=(1,))
+    ref = singles(si, torch, batch, si.Sched("fac"))
+    st = si.si_generate_batched(items_of(batch), si.Sched(kind, num_workgroups=200),
+                                use_graph=use_graph, stats=True)
+    torch.cuda.synchronize()
+    for b, (img, cnt) in zip(batch, ref):
+        assert torch.equal(b["img"], img)
+        assert torch.equal(b["cnt"], cnt)
+    total = sum(int(c.to(torch.int64).sum()) for _, c in ref)
+    assert st["pairs_in_support"] == total
+    assert st["sched_used"] == si.SCHED[kind]
+
+
+def test_graph_replays_repeat(env):
+    """The cached graph is replayed several times with eager work (clearing
+    the outputs) between replays; every replay reproduces the images."""
+    torch, si, _ = env
+    print("\n[case] graph replays", flush=True)
+    batch = make_batch(torch, si, n_scenes=8, seed=4100)
+    ref = singles(si, torch, batch, si.Sched("fac"))
+    for rep in range(4):
+        for b in batch:
+            b["img"].zero_()
+            b["cnt"].fill_(7)
+        torch.cuda.synchronize()
+        si.si_generate_batched(items_of(batch), si.Sched("fac"), use_graph=True)
+        torch.cuda.synchronize()
+        for b, (img, cnt) in zip(batch, ref):
+            assert torch.equal(b["img"], img), rep
+            assert torch.equal(b["cnt"], cnt), rep
+
+
+def test_batched_vs_oracle(env):
+    torch, si, oracle = env
+    print("\n[case] batched vs oracle", flush=True)
+    batch = make_batch(torch, si, n_scenes=6, m_range=(500, 3000), seed=4200)
+    si.si_generate_batched(items_of(batch), si.Sched("gss"), use_graph=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for b in batch:
+        sample = np.sort(rng.choice(b["N"], min(b["N"], 150), replace=False))
+        ref = oracle.generate(b["xyz"], b["nrm"], sample, b["W"], B, S60)
+        parity.check(b["img"].cpu().numpy()[sample], b["cnt"].cpu().numpy().view(np.uint32)[sample],
+                     ref, 0, f"batch W{b['W']}")
+
+
+def test_batched_edge_cases(env):
+    torch, si, _ = env
+    print("\n[case] batched edge cases", flush=True)
+    batch = make_batch(torch, si, n_scenes=4, seed=4300)
+    items = items_of(batch)
+    empty = torch.zeros(0, dtype=torch.int32, device="cuda")
+    e_img = torch.zeros((0, 16, 16), dtype=torch.float32, device="cuda")
+    e_cnt = torch.zeros((0,), dtype=torch.int32, device="cuda")
+    with_empty = [items[0], (batch[1]["scene"], empty, si.Params(16, B, S60), e_img, e_cnt)] + items[1:]
+    ref = singles(si, torch, batch, si.Sched("fac"))
+    for use_graph in (False, True):
+        for b in batch:
+            b["img"].zero_()
+        si.si_generate_batched(with_empty, si.Sched("static", num_workgroups=3000),
+                               use_graph=use_graph)
+        torch.cuda.synchronize()
+        for b, (img, cnt) in zip(batch, ref):
+            assert torch.equal(b["img"], img)
+    assert si.si_generate_batched([], si.Sched("fac"), use_graph=True, stats=True)["n_wg"] == 0
+    W0 = batch[0]["W"]   # same W, but a bin whose support radius exceeds the scene's grid
+    bad = [(batch[0]["scene"], batch[0]["idx"], si.Params(W0, 0.5, S60), batch[0]["img"],
+            batch[0]["cnt"])]
+    with pytest.raises(si.SiError):
+        si.si_generate_batched(bad, si.Sched("fac"), use_graph=False)
