@@ -239,6 +239,26 @@ si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
                               si_stats* stats, void* hip_stream);
 
 /*
+ * Autotuner: picks the launch parameters of a workload (the items as for
+ * si_generate_batched; one item for a single scene) for scheduling technique
+ * `kind`.  Tuned: group (images per shared candidate pass), num_workgroups,
+ * fac_divisor (FAC and LEARNED) and min_chunk (dynamic techniques), by
+ * coordinate descent from the defaults, at most max_trials timed candidates
+ * (each the median of two launches after a warm-up).  Every candidate's
+ * images and counts must give the same 64-bit checksum as the first one,
+ * else SI_E_DEVICE.  The winner is written to *best (kind and order filled,
+ * model NULL) and its time to *best_ms (host, may be NULL).  Winners are
+ * cached per (device, kind, use_graph, image widths, size class) in memory
+ * and, when the environment variable SI_AUTOTUNE_CACHE names a file, in that
+ * file (one JSON object per line; unreadable lines are ignored).  A cached
+ * winner is returned without running unless force = 1.  The items' output
+ * buffers are overwritten.  Synchronises the stream.
+ */
+si_status si_autotune(const si_batch_item* items, int32_t n_items, int32_t kind,
+                      int32_t use_graph, int32_t max_trials, int32_t force, si_sched* best,
+                      double* best_ms, void* hip_stream);
+
+/*
  * Per-image cost features (12 float32 per image, device N x 12) of the
  * oriented points, from the occupancy of the 3 x 3 x 3 block of cells of size
  * close to the support radius around p and from n.  Used by the learned cost

@@ -25,7 +25,7 @@ __all__ = [
     "si_build_scene", "si_generate", "si_generate_batched", "si_features",
     "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
     "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
-    "si_set_kernel_events",
+    "si_set_kernel_events", "si_autotune",
     "SCHED", "MODE",
 ]
 
@@ -107,6 +107,8 @@ def lib():
             "si_chunk_table": (I32, [I32, I64, I32, I32, F, P, I64, ctypes.POINTER(I64)]),
             "si_learned_table": (I32, [P, I64, I32, F, P, P, I64, ctypes.POINTER(I64)]),
             "si_set_kernel_events": (I32, [P, P]),
+            "si_autotune": (I32, [ctypes.POINTER(c_batch_item), I32, I32, I32, I32, I32,
+                                  ctypes.POINTER(c_sched), ctypes.POINTER(ctypes.c_double), P]),
             "si_status_string": (ctypes.c_char_p, [I32]),
             "si_last_error": (ctypes.c_char_p, []),
             "si_abi_version": (I32, []),
@@ -283,10 +285,7 @@ def si_generate(scene: Scene, oriented_idx: torch.Tensor, params: Params, sched:
     return images_out, counts_out, (_stats_dict(st, busy) if st is not None else None)
 
 
-def si_generate_batched(items, sched: Sched | None = None, use_graph: bool = True,
-                        stats: bool = False, stream=None):
-    """items: list of (scene, oriented_idx, params, images_out, counts_out)."""
-    sched = sched or Sched()
+def _batch_array(items):
     arr = (c_batch_item * max(1, len(items)))()
     for k, (scene, idx, params, img, cnt) in enumerate(items):
         N = int(idx.shape[0])
@@ -297,11 +296,34 @@ def si_generate_batched(items, sched: Sched | None = None, use_graph: bool = Tru
         arr[k].images_out = (_dev_ptr(img, torch.float32, "images_out", (N, params.W, params.W)).value
                              if N else None)
         arr[k].counts_out = cnt.data_ptr() if N else None
+    return arr
+
+
+def si_generate_batched(items, sched: Sched | None = None, use_graph: bool = True,
+                        stats: bool = False, stream=None):
+    """items: list of (scene, oriented_idx, params, images_out, counts_out)."""
+    sched = sched or Sched()
+    arr = _batch_array(items)
     st, busy = _new_stats(stats, 65536)
     rc = lib().si_generate_batched(arr, len(items), ctypes.byref(sched.c()), 1 if use_graph else 0,
                                    ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc)
     return _stats_dict(st, busy) if st is not None else None
+
+
+def si_autotune(items, kind: str = "fac", use_graph: bool = True, max_trials: int = 16,
+                force: bool = False, stream=None):
+    """Tuned Sched for the workload ``items`` (list as for si_generate_batched)
+    and the time of its launch in ms.  Overwrites the items' outputs."""
+    arr = _batch_array(items)
+    best = c_sched()
+    ms = ctypes.c_double()
+    _check(lib().si_autotune(arr, len(items), SCHED[kind], 1 if use_graph else 0, int(max_trials),
+                             1 if force else 0, ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
+    inv = {v: k for k, v in SCHED.items()}
+    sched = Sched(inv[best.kind], best.num_workgroups, best.min_chunk, best.fac_divisor,
+                  None, True, best.group, "cell" if best.order == 0 else "given")
+    return sched, float(ms.value)
 
 
 def si_features(scene: Scene, oriented_idx: torch.Tensor, params: Params, stream=None) -> torch.Tensor:

@@ -1,0 +1,279 @@
+// Autotuner for the launch parameters of spin-image generation.
+//
+// The scheduling technique is the caller's choice (Section 2.2); what is tuned
+// here are the knobs of this implementation that do not change any image:
+// images per shared candidate pass (group), persistent workgroups (P), the
+// factoring divisor x and the minimum chunk.  The search is coordinate descent
+// from the defaults, each candidate timed with HIP events on the caller's
+// workload; every candidate's images and counts must hash to the same 64-bit
+// checksum as the first one.  Winners are cached per (device, technique,
+// image widths, size class), in memory and optionally in a JSON file.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "si_internal.h"
+
+namespace si {
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_checksum(const uint32_t* __restrict__ a, int64_t n,
+                                                  uint64_t salt,
+                                                  unsigned long long* __restrict__ out) {
+    uint64_t acc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        // order-free: a sum of per-element mixes of (value, position)
+        uint64_t h = ((uint64_t)a[i] << 32) ^ (uint64_t)(i + 1) ^ salt;
+        h ^= h >> 33;
+        h *= 0xff51afd7ed558ccdull;
+        h ^= h >> 33;
+        acc += h;
+    }
+    __shared__ unsigned long long red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+struct Tuned {
+    int group = 0, num_workgroups = 0, min_chunk = 0;
+    float divisor = 0.0f;
+    double ms = 0.0;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, Tuned> g_tuned;
+bool g_loaded = false;
+
+const char* cache_path() { return getenv("SI_AUTOTUNE_CACHE"); }
+
+// One entry per line: {"key": "...", "group": g, "workgroups": p, "divisor": x, "min_chunk": m, "ms": t}
+void load_cache() {
+    if (g_loaded) return;
+    g_loaded = true;
+    const char* path = cache_path();
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[1024];
+    while (fgets(line, sizeof(line), f)) {
+        char key[512];
+        Tuned t;
+        if (sscanf(line,
+                   " {\"key\": \"%511[^\"]\", \"group\": %d, \"workgroups\": %d, \"divisor\": %f, "
+                   "\"min_chunk\": %d, \"ms\": %lf}",
+                   key, &t.group, &t.num_workgroups, &t.divisor, &t.min_chunk, &t.ms) == 6) {
+            if (t.group >= 1 && t.group <= kMaxGroup && t.num_workgroups >= 1 &&
+                t.divisor >= 0.0f && t.min_chunk >= 0)
+                g_tuned[key] = t;  // malformed lines are ignored
+        }
+    }
+    fclose(f);
+}
+
+void save_cache() {
+    const char* path = cache_path();
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (auto& kv : g_tuned)
+        fprintf(f,
+                "{\"key\": \"%s\", \"group\": %d, \"workgroups\": %d, \"divisor\": %.3f, "
+                "\"min_chunk\": %d, \"ms\": %.4f}\n",
+                kv.first.c_str(), kv.second.group, kv.second.num_workgroups, kv.second.divisor,
+                kv.second.min_chunk, kv.second.ms);
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+std::string tune_key(const si_batch_item* items, int32_t n_items, int32_t kind, int32_t use_graph) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    char arch[64] = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+        cus = prop.multiProcessorCount;
+    }
+    std::set<int> widths;
+    int64_t total = 0;
+    int n = 0;
+    for (int32_t i = 0; i < n_items; ++i) {
+        if (items[i].N <= 0) continue;
+        widths.insert(items[i].params.W);
+        total += items[i].N;
+        ++n;
+    }
+    std::string k = std::string(arch) + "/cu" + std::to_string(cus) + "/kind" +
+                    std::to_string(kind) + "/graph" + std::to_string(use_graph ? 1 : 0) + "/W";
+    for (int w : widths) k += std::to_string(w) + ",";
+    k += "/logN" + std::to_string(total > 0 ? (int)floor(log2((double)total)) : 0);
+    k += "/items" + std::to_string(n <= 1 ? 1 : (int)ceil(log2((double)n)));
+    return k;
+}
+
+si_status checksum(const si_batch_item* items, int32_t n_items, unsigned long long* dsum,
+                   hipStream_t s, uint64_t* out) {
+    SI_HIP(launch_fill(reinterpret_cast<int32_t*>(dsum), 2, 0, s));
+    for (int32_t i = 0; i < n_items; ++i) {
+        const si_batch_item& b = items[i];
+        if (b.N <= 0) continue;
+        const int64_t ni = b.N * (int64_t)b.params.W * b.params.W;
+        hipLaunchKernelGGL(k_checksum, dim3(512), dim3(256), 0, s,
+                           reinterpret_cast<const uint32_t*>(b.images_out), ni,
+                           (uint64_t)(2 * i + 1), dsum);
+        hipLaunchKernelGGL(k_checksum, dim3(64), dim3(256), 0, s, b.counts_out, b.N,
+                           (uint64_t)(2 * i + 2) << 40, dsum);
+    }
+    SI_HIP(hipGetLastError());
+    unsigned long long h = 0;
+    SI_HIP(hipMemcpyAsync(&h, dsum, sizeof(h), hipMemcpyDeviceToHost, s));
+    SI_HIP(hipStreamSynchronize(s));
+    *out = h;
+    return SI_OK;
+}
+
+}  // namespace
+
+}  // namespace si
+
+using namespace si;
+
+extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, int32_t kind,
+                                 int32_t use_graph, int32_t max_trials, int32_t force,
+                                 si_sched* best, double* best_ms, void* hip_stream) {
+    if (!best) return fail(SI_E_INVALID, "best is NULL");
+    if (n_items <= 0 || !items) return fail(SI_E_INVALID, "empty item list");
+    if (kind < SI_SCHED_STATIC || kind > SI_SCHED_LEARNED) return fail(SI_E_INVALID, "bad kind");
+    if (max_trials < 1) max_trials = 1;
+    hipStream_t s = (hipStream_t)hip_stream;
+    DeviceState* st;
+    si_status rc = device_state(&st);
+    if (rc != SI_OK) return rc;
+
+    si_sched base;
+    memset(&base, 0, sizeof(base));
+    base.kind = kind;
+    base.fallback_to_fac = 1;
+    base.order = SI_ORDER_CELL;
+    const std::string key = tune_key(items, n_items, kind, use_graph);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_cache();
+        auto it = g_tuned.find(key);
+        if (!force && it != g_tuned.end()) {
+            *best = base;
+            best->group = it->second.group;
+            best->num_workgroups = it->second.num_workgroups;
+            best->fac_divisor = it->second.divisor;
+            best->min_chunk = it->second.min_chunk;
+            if (best_ms) *best_ms = it->second.ms;
+            return SI_OK;
+        }
+    }
+
+    unsigned long long* dsum = nullptr;
+    SI_HIP(hipMalloc(&dsum, 16));
+    uint64_t ref_sum = 0;
+    bool have_ref = false;
+    int trials = 0;
+    auto measure = [&](const si_sched& c, double* ms) -> si_status {
+        si_stats sts;
+        std::vector<double> t;
+        for (int r = 0; r < 3; ++r) {
+            memset(&sts, 0, sizeof(sts));
+            si_status e = si_generate_batched(items, n_items, &c, use_graph, &sts, s);
+            if (e != SI_OK) return e;
+            if (r) t.push_back(sts.kernel_ms);
+        }
+        std::sort(t.begin(), t.end());
+        *ms = t[t.size() / 2];
+        uint64_t h = 0;
+        si_status e = checksum(items, n_items, dsum, s, &h);
+        if (e != SI_OK) return e;
+        if (!have_ref) {
+            ref_sum = h;
+            have_ref = true;
+        } else if (h != ref_sum) {
+            return fail(SI_E_DEVICE, "autotune candidate changed the images (checksum mismatch)");
+        }
+        ++trials;
+        return SI_OK;
+    };
+
+    si_sched cur = base;
+    cur.group = 8;
+    double cur_ms = 0.0;
+    rc = measure(cur, &cur_ms);
+    auto try_set = [&](si_sched cand) -> si_status {
+        if (trials >= max_trials) return SI_OK;
+        double ms = 0.0;
+        si_status e = measure(cand, &ms);
+        if (e != SI_OK) return e;
+        if (ms < cur_ms) {
+            cur = cand;
+            cur_ms = ms;
+        }
+        return SI_OK;
+    };
+    // images per shared pass
+    for (int g : {4, 6, 2}) {
+        if (rc != SI_OK) break;
+        si_sched c = cur;
+        c.group = g;
+        rc = try_set(c);
+    }
+    // persistent workgroups per CU
+    for (int per_cu : {2, 4, 3, 6}) {
+        if (rc != SI_OK) break;
+        si_sched c = cur;
+        c.num_workgroups = st->n_cu * per_cu;
+        rc = try_set(c);
+    }
+    if (kind == SI_SCHED_FAC || kind == SI_SCHED_LEARNED) {
+        for (float x : {1.5f, 3.0f, 4.0f}) {
+            if (rc != SI_OK) break;
+            si_sched c = cur;
+            c.fac_divisor = x;
+            rc = try_set(c);
+        }
+    }
+    if (kind != SI_SCHED_STATIC) {
+        for (int mc : {4, 16}) {
+            if (rc != SI_OK) break;
+            si_sched c = cur;
+            c.min_chunk = mc;
+            rc = try_set(c);
+        }
+    }
+    (void)hipFree(dsum);
+    if (rc != SI_OK) return rc;
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    Tuned t;
+    t.group = cur.group;
+    t.num_workgroups = cur.num_workgroups;
+    t.divisor = cur.fac_divisor;
+    t.min_chunk = cur.min_chunk;
+    t.ms = cur_ms;
+    g_tuned[key] = t;
+    save_cache();
+    return SI_OK;
+}

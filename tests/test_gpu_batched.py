@@ -135,3 +135,39 @@ def test_batched_edge_cases(env):
             batch[0]["cnt"])]
     with pytest.raises(si.SiError):
         si.si_generate_batched(bad, si.Sched("fac"), use_graph=False)
+
+
+def test_autotune(env, tmp_path):
+    """The autotuner returns launch parameters whose images are bit-identical
+    to the defaults (it checks every candidate's checksum itself), persists
+    the winner, and answers from the cache afterwards."""
+    import os
+    torch, si, _ = env
+    print("\n[case] autotune", flush=True)
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text("not json at all\n")             # unreadable lines are ignored
+    os.environ["SI_AUTOTUNE_CACHE"] = str(cache)
+    try:
+        batch = make_batch(torch, si, n_scenes=6, seed=4400)
+        ref = singles(si, torch, batch, si.Sched("fac"))
+        sched, ms = si.si_autotune(items_of(batch), "fac", use_graph=True, max_trials=8)
+        assert 1 <= sched.group <= 8 and ms > 0
+        for b in batch:
+            b["img"].zero_()
+        si.si_generate_batched(items_of(batch), sched, use_graph=True)
+        torch.cuda.synchronize()
+        for b, (img, cnt) in zip(batch, ref):
+            assert torch.equal(b["img"], img)
+            assert torch.equal(b["cnt"], cnt)
+        text = cache.read_text()
+        assert '"group"' in text and "kind3" in text
+        sched2, ms2 = si.si_autotune(items_of(batch), "fac", use_graph=True, max_trials=8)
+        assert (sched2.group, sched2.num_workgroups, sched2.min_chunk) == \
+            (sched.group, sched.num_workgroups, sched.min_chunk)
+        assert abs(ms2 - ms) < 1e-3
+        # a single scene, static technique
+        one = items_of(batch)[:1]
+        s1, _ = si.si_autotune(one, "static", use_graph=False, max_trials=4, force=True)
+        assert s1.kind == "static"
+    finally:
+        del os.environ["SI_AUTOTUNE_CACHE"]
