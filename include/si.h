@@ -288,6 +288,17 @@ si_status si_cost_model_train(si_cost_model* model, const float* feats, const ui
                               int64_t n, int32_t epochs, float lr, int32_t batch,
                               float* loss_curve_host, void* hip_stream);
 
+/*
+ * Gradient of the mean squared error over all n samples with respect to the
+ * 5,057 parameters (layout as in si_cost_model_get_params), computed on the
+ * device with the training kernels, copied to grad_host (host, 5,057
+ * floats); the loss to *loss_host (may be NULL).  Does not change the model.
+ * Synchronises the stream.
+ */
+si_status si_cost_model_gradient(const si_cost_model* model, const float* feats,
+                                 const uint32_t* counts, int64_t n, float* grad_host,
+                                 float* loss_host, void* hip_stream);
+
 /* Predicted in-support counts (expm1 of the network output), device n floats. */
 si_status si_cost_model_predict(const si_cost_model* model, const float* feats, int64_t n,
                                 float* pred_counts, void* hip_stream);
@@ -313,10 +324,14 @@ si_status si_chunk_table(int32_t kind, int64_t N, int32_t P, int32_t min_chunk,
                          int64_t* n_chunks);
 
 /*
- * Host-only: the order and chunk table of the learned schedule for given
- * per-unit predicted costs (units = groups of images).  perm_out (host, n)
- * receives the units in descending predicted cost (ties by index); starts
- * (host, cap) the chunk boundaries in that order.
+ * Host-only: the order and cutting of the learned schedule for given
+ * per-unit costs (a unit = 16 consecutive iterations of the cell-ordered loop;
+ * costs are rounded to integers >= 1).  perm_out (host, n) receives the units
+ * in descending cost on a logarithmic key (32 steps per doubling; ties keep
+ * unit order); starts_out (host, cap) the chunk boundaries in units of that
+ * order, n_chunks + 1 entries: factoring on cost, batch b cutting P chunks of
+ * ceil(R_b / (x P)) cost from the R_b left.  This is the host statement of
+ * what si_generate computes on the device for SI_SCHED_LEARNED.
  */
 si_status si_learned_table(const float* unit_cost, int64_t n, int32_t P, float fac_divisor,
                            int32_t* perm_out, int64_t* starts_out, int64_t cap,

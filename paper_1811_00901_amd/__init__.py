@@ -23,7 +23,7 @@ import torch
 __all__ = [
     "SiError", "Params", "Sched", "Scene", "CostModel", "lib",
     "si_build_scene", "si_generate", "si_generate_batched", "si_features",
-    "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
+    "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict", "si_cost_model_gradient",
     "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
     "si_set_kernel_events", "si_autotune",
     "SCHED", "MODE",
@@ -100,6 +100,7 @@ def lib():
             "si_free_cost_model": (None, [P]),
             "si_cost_model_train": (I32, [P, P, P, I64, I32, F, I32, P, P]),
             "si_cost_model_predict": (I32, [P, P, I64, P, P]),
+            "si_cost_model_gradient": (I32, [P, P, P, I64, P, P, P]),
             "si_cost_model_get_params": (I32, [P, P, I64]),
             "si_cost_model_set_params": (I32, [P, P, I64]),
             "si_cost_model_save": (I32, [P, ctypes.c_char_p]),
@@ -395,6 +396,18 @@ def si_cost_model_train(model: CostModel, feats: torch.Tensor, counts: torch.Ten
                                      curve.ctypes.data if curve is not None else None,
                                      _stream(stream)))
     return curve
+
+
+def si_cost_model_gradient(model: CostModel, feats: torch.Tensor, counts: torch.Tensor,
+                           stream=None):
+    """(gradient (5057,) float32, mean loss) of the model on (feats, counts)."""
+    n = int(feats.shape[0])
+    fp = _dev_ptr(feats, torch.float32, "feats", (n, 12))
+    g = np.zeros(N_MODEL_PARAMS, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(lib().si_cost_model_gradient(model.handle, fp, ctypes.c_void_p(counts.data_ptr()), n,
+                                        g.ctypes.data, ctypes.byref(loss), _stream(stream)))
+    return g, float(loss.value)
 
 
 def si_cost_model_predict(model: CostModel, feats: torch.Tensor, stream=None) -> torch.Tensor:

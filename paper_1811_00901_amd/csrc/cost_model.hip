@@ -1,46 +1,805 @@
-// Learned per-image cost model and batched launches (placeholder until built).
+// Learned per-image cost model and the learned schedule.
+//
+// The earlier PSIA balanced CPU and co-processor work statically from per-image
+// timings measured on each architecture (Section 2.3); here a small network
+// predicts each image's cost from the occupancy of the grid around its
+// oriented point, and the schedule orders and sizes chunks by the prediction:
+//
+//   features (12 per image) -> MLP 12-64-64-1 (ReLU, float32) -> log1p(count)
+//   units of kUnit consecutive iterations of the cell-ordered loop, costed by
+//   the sum of their predicted counts (+1 per image), taken in descending
+//   cost (longest-processing-time first; a stable counting sort on a
+//   logarithmic key), cut into chunks by factoring on predicted cost: batch b
+//   has P chunks of ceil(R_b / (x P)) predicted cost each, R_b the cost left.
+//
+// Everything runs on the device, in the caller's stream.  Training uses
+// hand-written forward/backward kernels whose reductions have a fixed order
+// (per-block partial gradients, then a fixed-order sum over blocks), so a
+// training run is reproducible, and Adam.  With no model the schedule falls
+// back to FAC.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "si_internal.h"
 
+struct si_cost_model {
+    int device = 0;
+    uint64_t seed = 0;
+    int64_t step = 0;        // Adam steps taken
+    float* params = nullptr; // device, kNP
+    float* m = nullptr;      // Adam first moment (device)
+    float* v = nullptr;      // Adam second moment (device)
+};
+
 namespace si {
-si_status learned_table(DeviceState*, const Scene*, const int32_t*, int64_t, const si_params*,
-                        const si_sched*, int, int, Chunk**, int*, int32_t**, hipStream_t) {
-    return fail(SI_E_UNSUPPORTED, "learned schedule not built");
+
+namespace {
+
+constexpr int kNF = 12;                  // features
+constexpr int kH = 64;                   // hidden width
+constexpr int kNP = kH * kNF + kH + kH * kH + kH + kH + 1;  // 5057
+constexpr int oW1 = 0, oB1 = kH * kNF, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
+              oB3 = oW3 + kH;
+constexpr int kGradSamples = 32;         // samples per gradient block (8 threads each)
+constexpr int kUnit = 16;                // iterations per learned-schedule unit
+constexpr int kKeys = 1024;              // LPT key buckets (32 per octave of cost)
+constexpr int kTile = 256;               // units per sort tile
+
+// ---------------------------------------------------------------- features --
+__global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* __restrict__ oriented,
+                                                  int64_t N, float f11, float* __restrict__ feats) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    float* f = feats + kNF * i;
+    const int o = oriented[i];
+    if (o < 0 || o >= sc.M) {
+        for (int k = 0; k < kNF; ++k) f[k] = 0.0f;
+        return;
+    }
+    const int sp = sc.inv[o];
+    const float4 pa = sc.pos[sp];
+    const float4 na = sc.nrm[sp];
+    const int cell = __float_as_int(pa.w);
+    const int c[3] = {cell % sc.dims[0], (cell / sc.dims[0]) % sc.dims[1],
+                      cell / (sc.dims[0] * sc.dims[1])};
+    const int half = kSub / 2;
+    float shell[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float tot = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f, s8 = 0.0f, s9 = 0.0f;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z0 = max(c[2] + kSub * dz - half, 0), z1 = min(c[2] + kSub * dz + half, sc.dims[2] - 1);
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y0 = max(c[1] + kSub * dy - half, 0), y1 = min(c[1] + kSub * dy + half, sc.dims[1] - 1);
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x0 = max(c[0] + kSub * dx - half, 0), x1 = min(c[0] + kSub * dx + half, sc.dims[0] - 1);
+                int cnt = 0;
+                if (x1 >= x0)
+                    for (int z = z0; z <= z1; ++z)
+                        for (int y = y0; y <= y1; ++y) {
+                            const int row = (z * sc.dims[1] + y) * sc.dims[0];
+                            cnt += sc.cell_start[row + x1 + 1] - sc.cell_start[row + x0];
+                        }
+                const float o_ = (float)cnt;
+                shell[abs(dx) + abs(dy) + abs(dz)] += o_;
+                tot += o_;
+                mx += o_ * dx;
+                my += o_ * dy;
+                mz += o_ * dz;
+                const float dn = dx * na.x + dy * na.y + dz * na.z;
+                s8 += o_ * dn * dn;
+                const float ex = dx - dn * na.x, ey = dy - dn * na.y, ez = dz - dn * na.z;
+                s9 += o_ * (ex * ex + ey * ey + ez * ez);
+            }
+        }
+    }
+    const float inv = tot > 0.0f ? 1.0f / tot : 0.0f;
+    for (int k = 0; k < 4; ++k) f[k] = log1pf(shell[k]);
+    f[4] = mx * inv;
+    f[5] = my * inv;
+    f[6] = mz * inv;
+    f[7] = f[4] * na.x + f[5] * na.y + f[6] * na.z;
+    f[8] = s8 * inv;
+    f[9] = s9 * inv;
+    f[10] = log1pf(tot);
+    f[11] = f11;
 }
+
+// ------------------------------------------------------------- MLP forward --
+// pred[i] = max(expm1(net(feats[i])), 0); with `out_raw` the raw network
+// output is written instead.
+__global__ void __launch_bounds__(256) k_mlp_predict(const float* __restrict__ params,
+                                                     const float* __restrict__ feats, int64_t n,
+                                                     float* __restrict__ pred, int out_raw) {
+    __shared__ float P[kNP];
+    for (int k = threadIdx.x; k < kNP; k += blockDim.x) P[k] = params[k];
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x[kNF];
+    for (int k = 0; k < kNF; ++k) x[k] = feats[kNF * i + k];
+    float h1[kH];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+        float z = P[oB1 + j];
+#pragma unroll
+        for (int k = 0; k < kNF; ++k) z = fmaf(P[oW1 + j * kNF + k], x[k], z);
+        h1[j] = fmaxf(z, 0.0f);
+    }
+    float out = P[oB3];
+    for (int j = 0; j < kH; ++j) {
+        float z = P[oB2 + j];
+#pragma unroll
+        for (int k = 0; k < kH; ++k) z = fmaf(P[oW2 + j * kH + k], h1[k], z);
+        out = fmaf(P[oW3 + j], fmaxf(z, 0.0f), out);
+    }
+    pred[i] = out_raw ? out : fmaxf(expm1f(out), 0.0f);
+}
+
+// ---------------------------------------------------------------- gradient --
+// One block: kGradSamples samples (8 threads each).  Samples are
+// sel[start + s] (or start + s without sel), s < count.  Writes this block's
+// gradient of sum_s (out_s - y_s)^2 * scale, and the block's summed squared
+// error in slot kNP, to partial[blockIdx.x * (kNP + 1) ...].
+__global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ params,
+                                                  const float* __restrict__ feats,
+                                                  const uint32_t* __restrict__ counts,
+                                                  const int32_t* __restrict__ sel, int64_t start,
+                                                  int64_t count, float scale,
+                                                  float* __restrict__ partial) {
+    __shared__ float X[kGradSamples][kNF];
+    __shared__ float H1[kGradSamples][kH];
+    __shared__ float H2[kGradSamples][kH];
+    __shared__ float D2[kGradSamples][kH];
+    __shared__ float D1[kGradSamples][kH];
+    __shared__ float Dout[kGradSamples];
+    __shared__ float Loss[kGradSamples];
+    const int tid = threadIdx.x;
+    const int s = tid >> 3, q = tid & 7;
+    const int64_t b0 = start + (int64_t)blockIdx.x * kGradSamples;
+    const int64_t my = b0 + s;
+    const bool valid = (my - start) < count;
+    int64_t row = 0;
+    if (valid) row = sel ? sel[my] : my;
+    for (int k = q; k < kNF; k += 8) X[s][k] = valid ? feats[kNF * row + k] : 0.0f;
+    __syncthreads();
+    for (int jj = 0; jj < 8; ++jj) {
+        const int j = q * 8 + jj;
+        float z = params[oB1 + j];
+        for (int k = 0; k < kNF; ++k) z = fmaf(params[oW1 + j * kNF + k], X[s][k], z);
+        H1[s][j] = fmaxf(z, 0.0f);
+    }
+    __syncthreads();
+    for (int jj = 0; jj < 8; ++jj) {
+        const int j = q * 8 + jj;
+        float z = params[oB2 + j];
+        for (int k = 0; k < kH; ++k) z = fmaf(params[oW2 + j * kH + k], H1[s][k], z);
+        H2[s][j] = fmaxf(z, 0.0f);
+    }
+    __syncthreads();
+    if (q == 0) {
+        float out = params[oB3];
+        for (int j = 0; j < kH; ++j) out = fmaf(params[oW3 + j], H2[s][j], out);
+        const float y = valid ? log1pf((float)counts[row]) : 0.0f;
+        const float r = out - y;
+        Dout[s] = valid ? 2.0f * r * scale : 0.0f;
+        Loss[s] = valid ? r * r : 0.0f;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < 8; ++jj) {
+        const int j = q * 8 + jj;
+        D2[s][j] = H2[s][j] > 0.0f ? Dout[s] * params[oW3 + j] : 0.0f;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 8; ++kk) {
+        const int k = q * 8 + kk;
+        float g = 0.0f;
+        for (int j = 0; j < kH; ++j) g = fmaf(params[oW2 + j * kH + k], D2[s][j], g);
+        D1[s][k] = H1[s][k] > 0.0f ? g : 0.0f;
+    }
+    __syncthreads();
+    float* out = partial + (size_t)blockIdx.x * (kNP + 1);
+    for (int p = tid; p < kNP; p += blockDim.x) {
+        float g = 0.0f;
+        if (p < oB1) {
+            const int j = p / kNF, i = p % kNF;
+            for (int t = 0; t < kGradSamples; ++t) g = fmaf(D1[t][j], X[t][i], g);
+        } else if (p < oW2) {
+            const int j = p - oB1;
+            for (int t = 0; t < kGradSamples; ++t) g += D1[t][j];
+        } else if (p < oB2) {
+            const int r = p - oW2, j = r / kH, k = r % kH;
+            for (int t = 0; t < kGradSamples; ++t) g = fmaf(D2[t][j], H1[t][k], g);
+        } else if (p < oW3) {
+            const int j = p - oB2;
+            for (int t = 0; t < kGradSamples; ++t) g += D2[t][j];
+        } else if (p < oB3) {
+            const int j = p - oW3;
+            for (int t = 0; t < kGradSamples; ++t) g = fmaf(Dout[t], H2[t][j], g);
+        } else {
+            for (int t = 0; t < kGradSamples; ++t) g += Dout[t];
+        }
+        out[p] = g;
+    }
+    if (tid == 0) {
+        float l = 0.0f;
+        for (int t = 0; t < kGradSamples; ++t) l += Loss[t];
+        out[kNP] = l;
+    }
+}
+
+// grad[p] = sum over blocks (fixed order); loss_acc[0] += summed loss.
+__global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ partial, int nblk,
+                                                    float* __restrict__ grad,
+                                                    float* __restrict__ loss_acc) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > kNP) return;
+    float g = 0.0f;
+    for (int b = 0; b < nblk; ++b) g += partial[(size_t)b * (kNP + 1) + p];
+    if (p < kNP) grad[p] = g;
+    else if (loss_acc) loss_acc[0] += g;
+}
+
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ params, const float* __restrict__ grad,
+                                              float* __restrict__ m, float* __restrict__ v, float lr,
+                                              float bc1, float bc2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNP) return;
+    const float g = grad[p];
+    const float mm = 0.9f * m[p] + 0.1f * g;
+    const float vv = 0.999f * v[p] + 0.001f * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    params[p] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+}
+
+// ------------------------------------------------------- learned schedule --
+// Unit u covers iterations [u*kUnit, min(N, (u+1)*kUnit)) of the work order;
+// its integer cost is round(sum over its images of (pred + 1)); its key puts
+// larger costs first.
+__global__ void __launch_bounds__(256) k_unit_cost(const float* __restrict__ pred,
+                                                   const int32_t* __restrict__ perm0, int64_t N,
+                                                   int64_t n_units, uint32_t* __restrict__ qcost,
+                                                   int32_t* __restrict__ key) {
+    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (u >= n_units) return;
+    const int64_t a = u * kUnit, b = min((int64_t)N, a + kUnit);
+    float c = 0.0f;
+    for (int64_t t = a; t < b; ++t) {
+        const float pv = pred[perm0 ? perm0[t] : t];
+        c += (pv == pv) ? fminf(pv, 1e7f) + 1.0f : 1.0f;  // a non-finite prediction costs 1
+    }
+    const uint32_t q = (uint32_t)fmaxf(rintf(c), 1.0f);
+    qcost[u] = q;
+    const int k = (int)floorf(log2f((float)q) * 32.0f);
+    key[u] = kKeys - 1 - min(max(k, 0), kKeys - 1);
+}
+
+// Per tile of kTile units: key histogram and each unit's rank among the
+// earlier units of its tile with the same key (a stable order).
+__global__ void __launch_bounds__(kTile) k_unit_hist(const int32_t* __restrict__ key, int64_t n_units,
+                                                     int32_t* __restrict__ tile_hist,
+                                                     int32_t* __restrict__ rank) {
+    __shared__ int hist[kKeys];
+    __shared__ int keys[kTile];
+    for (int k = threadIdx.x; k < kKeys; k += kTile) hist[k] = 0;
+    const int64_t u = (int64_t)blockIdx.x * kTile + threadIdx.x;
+    const int my = u < n_units ? key[u] : -1;
+    keys[threadIdx.x] = my;
+    __syncthreads();
+    if (my >= 0) {
+        atomicAdd(&hist[my], 1);
+        int r = 0;
+        for (int t = 0; t < (int)threadIdx.x; ++t) r += keys[t] == my;
+        rank[u] = r;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kKeys; k += kTile)
+        tile_hist[(size_t)blockIdx.x * kKeys + k] = hist[k];
+}
+
+// Exclusive offsets: tile_hist[t][k] <- units of key k in tiles < t, plus the
+// units of all smaller keys.  One block of kKeys threads.
+__global__ void __launch_bounds__(kKeys) k_unit_offsets(int32_t* __restrict__ tile_hist, int n_tiles) {
+    __shared__ int tot[kKeys];
+    const int k = threadIdx.x;
+    int run = 0;
+    for (int t = 0; t < n_tiles; ++t) {
+        const int c = tile_hist[(size_t)t * kKeys + k];
+        tile_hist[(size_t)t * kKeys + k] = run;
+        run += c;
+    }
+    tot[k] = run;
+    __syncthreads();
+    // exclusive scan of the key totals (sequential; kKeys values)
+    __shared__ int base[kKeys];
+    if (k == 0) {
+        int b = 0;
+        for (int i = 0; i < kKeys; ++i) {
+            base[i] = b;
+            b += tot[i];
+        }
+    }
+    __syncthreads();
+    for (int t = 0; t < n_tiles; ++t) tile_hist[(size_t)t * kKeys + k] += base[k];
+}
+
+__global__ void __launch_bounds__(256) k_unit_scatter(const int32_t* __restrict__ key,
+                                                      const int32_t* __restrict__ rank,
+                                                      const int32_t* __restrict__ tile_hist,
+                                                      int64_t n_units, int32_t* __restrict__ order) {
+    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (u >= n_units) return;
+    const int64_t t = u / kTile;
+    order[tile_hist[t * kKeys + key[u]] + rank[u]] = (int32_t)u;
+}
+
+// Single block: prefix cost / iteration count over the LPT order, factoring on
+// predicted cost, chunk table and its length.
+__global__ void __launch_bounds__(1024) k_learned_chunks(const int32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ qcost,
+                                                         int64_t n_units, int64_t N, int P,
+                                                         float divisor,
+                                                         int64_t* __restrict__ cpre,
+                                                         int64_t* __restrict__ ipre,
+                                                         Chunk* __restrict__ chunks,
+                                                         int32_t* __restrict__ n_chunks) {
+    __shared__ int64_t sc[1024];
+    __shared__ int64_t si_[1024];
+    __shared__ int64_t carry_c, carry_i;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        carry_c = 0;
+        carry_i = 0;
+    }
+    __syncthreads();
+    for (int64_t b = 0; b < n_units; b += 1024) {
+        const int64_t k = b + tid;
+        int64_t c = 0, it = 0;
+        if (k < n_units) {
+            const int32_t u = order[k];
+            c = qcost[u];
+            it = min((int64_t)kUnit, N - (int64_t)u * kUnit);
+        }
+        sc[tid] = c;
+        si_[tid] = it;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int64_t tc = tid >= off ? sc[tid - off] : 0;
+            const int64_t ti = tid >= off ? si_[tid - off] : 0;
+            __syncthreads();
+            sc[tid] += tc;
+            si_[tid] += ti;
+            __syncthreads();
+        }
+        if (k < n_units) {
+            cpre[k] = carry_c + sc[tid] - c;
+            ipre[k] = carry_i + si_[tid] - it;
+        }
+        __syncthreads();
+        if (tid == 1023) {
+            carry_c += sc[1023];
+            carry_i += si_[1023];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        cpre[n_units] = carry_c;
+        ipre[n_units] = carry_i;
+    }
+    __syncthreads();
+    const int64_t total = cpre[n_units];
+    __shared__ int64_t start;
+    __shared__ int emitted;
+    __shared__ int64_t ends[1025];
+    if (tid == 0) {
+        start = 0;
+        emitted = 0;
+    }
+    __syncthreads();
+    const double x = divisor > 0.0f ? (double)divisor : 2.0;
+    while (start < n_units) {
+        const int64_t st = start;
+        const int64_t R = total - cpre[st];
+        const int64_t cb = max((int64_t)1, (int64_t)ceil((double)R / (x * (double)P)));
+        // end of chunk j (1..P): first k > st with cpre[k] - cpre[st] >= j * cb, else n_units
+        for (int j = tid + 1; j <= P; j += 1024) {
+            const int64_t target = cpre[st] + (int64_t)j * cb;
+            int64_t lo = st + 1, hi = n_units;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (cpre[mid] >= target) hi = mid; else lo = mid + 1;
+            }
+            if (j <= 1024) ends[j] = lo;
+        }
+        if (tid == 0) ends[0] = st;
+        __syncthreads();
+        // P <= 1024 is enforced by the host; emit the non-empty chunks in order
+        if (tid == 0) {
+            int e = emitted;
+            for (int j = 1; j <= P; ++j) {
+                if (ends[j] > ends[j - 1]) {
+                    chunks[e].item = 0;
+                    chunks[e].start = (int32_t)ipre[ends[j - 1]];
+                    chunks[e].end = (int32_t)ipre[ends[j]];
+                    ++e;
+                }
+            }
+            emitted = e;
+            start = ends[P];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *n_chunks = emitted;
+}
+
+// Iteration -> output position of the learned order.
+__global__ void __launch_bounds__(256) k_learned_perm(const int32_t* __restrict__ order,
+                                                      const int64_t* __restrict__ ipre,
+                                                      const int32_t* __restrict__ perm0,
+                                                      int64_t N, int64_t n_units,
+                                                      int32_t* __restrict__ perm) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n_units) return;
+    const int64_t u = order[k];
+    const int64_t a = u * kUnit, len = min((int64_t)kUnit, N - a);
+    const int64_t o = ipre[k];
+    for (int64_t r = 0; r < len; ++r) perm[o + r] = perm0 ? perm0[a + r] : (int32_t)(a + r);
+}
+
+uint64_t splitmix(uint64_t& s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t& s) { return (double)(splitmix(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+unsigned nblocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+si_status features_launch(const Scene& sc, const int32_t* oriented, int64_t N,
+                          const si_params* params, float* feats, hipStream_t s) {
+    SpinParams p;
+    double R;
+    si_status rc = make_params(params, &p, &R);
+    if (rc != SI_OK) return rc;
+    const float f11 = (float)(R / (kSub * sc.h));
+    hipLaunchKernelGGL(k_features, dim3(nblocks(N)), dim3(256), 0, s, view_of(sc), oriented, N, f11,
+                       feats);
+    SI_HIP(hipGetLastError());
+    return SI_OK;
+}
+
+si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriented, int64_t N,
+                        const si_params* params, const si_sched* sched, int n_wg, int,
+                        LearnedPlan* plan, hipStream_t s) {
+    const si_cost_model* model = sched->model;
+    if (!model) return fail(SI_E_UNSUPPORTED, "learned schedule without a model");
+    if (n_wg > 1024) return fail(SI_E_INVALID, "the learned schedule supports at most 1024 workgroups");
+    const int64_t n_units = (N + kUnit - 1) / kUnit;
+    const int64_t n_tiles = (n_units + kTile - 1) / kTile;
+    const int64_t nt = scan_tmp_elems(scene->n_cells);
+    // one stream-ordered block for every temporary
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) & ~(size_t)255; return r; };
+    const size_t o_perm0 = take(sizeof(int32_t) * N);
+    const size_t o_key = take(sizeof(int32_t) * N);
+    const size_t o_rank = take(sizeof(int32_t) * N);
+    const size_t o_counts = take(sizeof(int32_t) * scene->n_cells);
+    const size_t o_starts = take(sizeof(int32_t) * (scene->n_cells + 1));
+    const size_t o_tmp = take(sizeof(int32_t) * nt);
+    const size_t o_feats = take(sizeof(float) * kNF * N);
+    const size_t o_pred = take(sizeof(float) * N);
+    const size_t o_qcost = take(sizeof(uint32_t) * n_units);
+    const size_t o_ukey = take(sizeof(int32_t) * n_units);
+    const size_t o_urank = take(sizeof(int32_t) * n_units);
+    const size_t o_hist = take(sizeof(int32_t) * n_tiles * kKeys);
+    const size_t o_order = take(sizeof(int32_t) * n_units);
+    const size_t o_cpre = take(sizeof(int64_t) * (n_units + 1));
+    const size_t o_ipre = take(sizeof(int64_t) * (n_units + 1));
+    const size_t o_chunks = take(sizeof(Chunk) * (n_units + 1));
+    const size_t o_nch = take(sizeof(int32_t));
+    const size_t o_perm = take(sizeof(int32_t) * N);
+    char* mem = nullptr;
+    SI_HIP(hipMallocAsync((void**)&mem, o, s));
+    auto I = [&](size_t off) { return reinterpret_cast<int32_t*>(mem + off); };
+    int32_t* perm0 = nullptr;
+    hipError_t e = hipSuccess;
+    if (sched->order == SI_ORDER_CELL && scene->n_cells > 1) {
+        perm0 = I(o_perm0);
+        e = launch_cell_order(oriented, N, *scene, I(o_key), I(o_rank), I(o_counts), I(o_starts),
+                              I(o_tmp), perm0, s);
+    }
+    float* feats = reinterpret_cast<float*>(mem + o_feats);
+    float* pred = reinterpret_cast<float*>(mem + o_pred);
+    if (e == hipSuccess) {
+        si_status rc = features_launch(*scene, oriented, N, params, feats, s);
+        if (rc != SI_OK) e = hipErrorLaunchFailure;
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mlp_predict, dim3(nblocks(N)), dim3(256), 0, s, model->params, feats,
+                           N, pred, 0);
+        hipLaunchKernelGGL(k_unit_cost, dim3(nblocks(n_units)), dim3(256), 0, s, pred, perm0, N,
+                           n_units, reinterpret_cast<uint32_t*>(mem + o_qcost), I(o_ukey));
+        hipLaunchKernelGGL(k_unit_hist, dim3((unsigned)n_tiles), dim3(kTile), 0, s, I(o_ukey),
+                           n_units, I(o_hist), I(o_urank));
+        hipLaunchKernelGGL(k_unit_offsets, dim3(1), dim3(kKeys), 0, s, I(o_hist), (int)n_tiles);
+        hipLaunchKernelGGL(k_unit_scatter, dim3(nblocks(n_units)), dim3(256), 0, s, I(o_ukey),
+                           I(o_urank), I(o_hist), n_units, I(o_order));
+        hipLaunchKernelGGL(k_learned_chunks, dim3(1), dim3(1024), 0, s, I(o_order),
+                           reinterpret_cast<uint32_t*>(mem + o_qcost), n_units, N, n_wg,
+                           sched->fac_divisor, reinterpret_cast<int64_t*>(mem + o_cpre),
+                           reinterpret_cast<int64_t*>(mem + o_ipre),
+                           reinterpret_cast<Chunk*>(mem + o_chunks), I(o_nch));
+        hipLaunchKernelGGL(k_learned_perm, dim3(nblocks(n_units)), dim3(256), 0, s, I(o_order),
+                           reinterpret_cast<int64_t*>(mem + o_ipre), perm0, N, n_units, I(o_perm));
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(mem, s);
+        return hip_fail(e, "learned schedule");
+    }
+    plan->mem = mem;
+    plan->chunks = reinterpret_cast<Chunk*>(mem + o_chunks);
+    plan->max_chunks = (int32_t)(n_units + 1);
+    plan->n_chunks_dev = I(o_nch);
+    plan->perm = I(o_perm);
+    return SI_OK;
+}
+
 }  // namespace si
 
 using namespace si;
 
 extern "C" {
-si_status si_features(const si_scene*, const int32_t*, int64_t, const si_params*, float*, void*) {
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+si_status si_features(const si_scene* scene, const int32_t* oriented_idx, int64_t N,
+                      const si_params* params, float* feats_out, void* hip_stream) {
+    if (!scene || (N > 0 && (!oriented_idx || !feats_out))) return fail(SI_E_INVALID, "NULL argument");
+    if (N < 0 || N >= INT32_MAX) return fail(SI_E_INVALID, "N out of range");
+    if (N == 0) return SI_OK;
+    return features_launch(*scene, oriented_idx, N, params, feats_out, (hipStream_t)hip_stream);
 }
-si_status si_cost_model_create(uint64_t, si_cost_model** out) {
-    if (out) *out = nullptr;
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+si_status si_cost_model_create(uint64_t seed, si_cost_model** out) {
+    if (!out) return fail(SI_E_INVALID, "out is NULL");
+    *out = nullptr;
+    si_cost_model* m = new (std::nothrow) si_cost_model();
+    if (!m) return fail(SI_E_OOM, "host allocation failed");
+    m->seed = seed;
+    SI_HIP(hipGetDevice(&m->device));
+    // He-uniform weights (bound sqrt(6 / fan_in)), zero biases
+    std::vector<float> h(kNP, 0.0f);
+    uint64_t st = seed ^ 0x5eed5eed5eed5eedull;
+    auto fill = [&](int off, int n, int fan_in) {
+        const double bound = sqrt(6.0 / fan_in);
+        for (int i = 0; i < n; ++i) h[off + i] = (float)((2.0 * uniform01(st) - 1.0) * bound);
+    };
+    fill(oW1, kH * kNF, kNF);
+    fill(oW2, kH * kH, kH);
+    fill(oW3, kH, kH);
+    hipError_t e = hipMalloc(&m->params, sizeof(float) * kNP);
+    if (e == hipSuccess) e = hipMalloc(&m->m, sizeof(float) * kNP);
+    if (e == hipSuccess) e = hipMalloc(&m->v, sizeof(float) * kNP);
+    if (e == hipSuccess) e = hipMemcpy(m->params, h.data(), sizeof(float) * kNP, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(m->m, 0, sizeof(float) * kNP);
+    if (e == hipSuccess) e = hipMemset(m->v, 0, sizeof(float) * kNP);
+    if (e != hipSuccess) {
+        si_free_cost_model(m);
+        return hip_fail(e, "cost model allocation");
+    }
+    *out = m;
+    return SI_OK;
 }
-void si_free_cost_model(si_cost_model*) {}
-si_status si_cost_model_train(si_cost_model*, const float*, const uint32_t*, int64_t, int32_t, float,
-                              int32_t, float*, void*) {
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+void si_free_cost_model(si_cost_model* m) {
+    if (!m) return;
+    (void)hipFree(m->params);
+    (void)hipFree(m->m);
+    (void)hipFree(m->v);
+    delete m;
 }
-si_status si_cost_model_predict(const si_cost_model*, const float*, int64_t, float*, void*) {
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+si_status si_cost_model_gradient(const si_cost_model* m, const float* feats, const uint32_t* counts,
+                                 int64_t n, float* grad_host, float* loss_host, void* hip_stream) {
+    if (!m || !feats || !counts || n <= 0) return fail(SI_E_INVALID, "bad arguments");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nblk = (int)((n + kGradSamples - 1) / kGradSamples);
+    float* mem = nullptr;
+    SI_HIP(hipMallocAsync((void**)&mem, sizeof(float) * ((size_t)nblk * (kNP + 1) + kNP + 1), s));
+    float* part = mem;
+    float* grad = mem + (size_t)nblk * (kNP + 1);
+    float* loss = grad + kNP;
+    hipError_t e = launch_fill(reinterpret_cast<int32_t*>(loss), 1, 0, s);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(256), 0, s, m->params, feats, counts,
+                       (const int32_t*)nullptr, (int64_t)0, n, (float)(1.0 / (double)n), part);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(nblocks(kNP + 1)), dim3(256), 0, s, part, nblk, grad, loss);
+    if (e == hipSuccess) e = hipGetLastError();
+    std::vector<float> h(kNP + 1);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), grad, sizeof(float) * (kNP + 1), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(mem, s);
+    if (e != hipSuccess) return hip_fail(e, "cost model gradient");
+    if (grad_host) memcpy(grad_host, h.data(), sizeof(float) * kNP);
+    if (loss_host) *loss_host = h[kNP] / (float)n;
+    return SI_OK;
 }
-si_status si_cost_model_get_params(const si_cost_model*, float*, int64_t) {
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+si_status si_cost_model_train(si_cost_model* m, const float* feats, const uint32_t* counts, int64_t n,
+                              int32_t epochs, float lr, int32_t batch, float* loss_curve_host,
+                              void* hip_stream) {
+    if (!m || !feats || !counts || n <= 0) return fail(SI_E_INVALID, "bad arguments");
+    if (epochs < 0 || batch < 1 || batch > 65536 || !(lr > 0.0f) || !isfinite(lr))
+        return fail(SI_E_INVALID, "epochs >= 0, 1 <= batch <= 65536, lr > 0 required");
+    if (n >= INT32_MAX) return fail(SI_E_INVALID, "n out of range");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int nblk_max = (batch + kGradSamples - 1) / kGradSamples;
+    size_t words = (size_t)nblk_max * (kNP + 1) + kNP + (size_t)std::max(epochs, 1) + (size_t)n;
+    float* mem = nullptr;
+    SI_HIP(hipMallocAsync((void**)&mem, sizeof(float) * words, s));
+    float* part = mem;
+    float* grad = part + (size_t)nblk_max * (kNP + 1);
+    float* losses = grad + kNP;
+    int32_t* perm = reinterpret_cast<int32_t*>(losses + std::max(epochs, 1));
+    int32_t* hperm = nullptr;
+    hipError_t e = hipHostMalloc((void**)&hperm, sizeof(int32_t) * n, hipHostMallocDefault);
+    if (e == hipSuccess) e = launch_fill(reinterpret_cast<int32_t*>(losses), std::max(epochs, 1), 0, s);
+    uint64_t rng = m->seed * 0x2545f4914f6cdd1dull + 12345;
+    for (int32_t ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+        // the previous epoch's copy of hperm must be complete before refilling it
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) break;
+        for (int64_t i = 0; i < n; ++i) hperm[i] = (int32_t)i;
+        for (int64_t i = n - 1; i > 0; --i) {
+            const int64_t j = (int64_t)(splitmix(rng) % (uint64_t)(i + 1));
+            std::swap(hperm[i], hperm[j]);
+        }
+        e = hipMemcpyAsync(perm, hperm, sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
+        for (int64_t b0 = 0; b0 < n && e == hipSuccess; b0 += batch) {
+            const int64_t cnt = std::min<int64_t>(batch, n - b0);
+            const int nblk = (int)((cnt + kGradSamples - 1) / kGradSamples);
+            hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(256), 0, s, m->params, feats, counts,
+                               perm, b0, cnt, (float)(1.0 / (double)cnt), part);
+            hipLaunchKernelGGL(k_mlp_reduce, dim3(nblocks(kNP + 1)), dim3(256), 0, s, part, nblk,
+                               grad, losses + ep);
+            ++m->step;
+            const float bc1 = (float)(1.0 - pow(0.9, (double)m->step));
+            const float bc2 = (float)(1.0 - pow(0.999, (double)m->step));
+            hipLaunchKernelGGL(k_adam, dim3(nblocks(kNP)), dim3(256), 0, s, m->params, grad, m->m,
+                               m->v, lr, bc1, bc2);
+            e = hipGetLastError();
+        }
+    }
+    std::vector<float> hl(std::max(epochs, 1));
+    if (e == hipSuccess && loss_curve_host && epochs > 0)
+        e = hipMemcpyAsync(hl.data(), losses, sizeof(float) * epochs, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(mem, s);
+    if (hperm) (void)hipHostFree(hperm);
+    if (e != hipSuccess) return hip_fail(e, "cost model training");
+    if (loss_curve_host)
+        for (int32_t ep = 0; ep < epochs; ++ep) loss_curve_host[ep] = hl[ep] / (float)n;
+    return SI_OK;
 }
-si_status si_cost_model_set_params(si_cost_model*, const float*, int64_t) {
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+si_status si_cost_model_predict(const si_cost_model* m, const float* feats, int64_t n,
+                                float* pred_counts, void* hip_stream) {
+    if (!m || (n > 0 && (!feats || !pred_counts))) return fail(SI_E_INVALID, "bad arguments");
+    if (n <= 0) return SI_OK;
+    hipLaunchKernelGGL(k_mlp_predict, dim3(nblocks(n)), dim3(256), 0, (hipStream_t)hip_stream,
+                       m->params, feats, n, pred_counts, 0);
+    SI_HIP(hipGetLastError());
+    return SI_OK;
 }
-si_status si_cost_model_save(const si_cost_model*, const char*) {
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+si_status si_cost_model_get_params(const si_cost_model* m, float* host_params, int64_t n) {
+    if (!m || !host_params || n != kNP) return fail(SI_E_INVALID, "need a buffer of 5057 floats");
+    SI_HIP(hipMemcpy(host_params, m->params, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+    return SI_OK;
 }
-si_status si_cost_model_load(const char*, si_cost_model** out) {
-    if (out) *out = nullptr;
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+si_status si_cost_model_set_params(si_cost_model* m, const float* host_params, int64_t n) {
+    if (!m || !host_params || n != kNP) return fail(SI_E_INVALID, "need a buffer of 5057 floats");
+    SI_HIP(hipMemcpy(m->params, host_params, sizeof(float) * kNP, hipMemcpyHostToDevice));
+    SI_HIP(hipMemset(m->m, 0, sizeof(float) * kNP));
+    SI_HIP(hipMemset(m->v, 0, sizeof(float) * kNP));
+    m->step = 0;
+    return SI_OK;
 }
-si_status si_learned_table(const float*, int64_t, int32_t, float, int32_t*, int64_t*, int64_t,
-                           int64_t*) {
-    return fail(SI_E_UNSUPPORTED, "not built");
+
+// File: "SICM" magic, uint32 version 1, uint32 parameter count, uint64 seed,
+// then the parameters as little-endian float32.
+si_status si_cost_model_save(const si_cost_model* m, const char* path) {
+    if (!m || !path) return fail(SI_E_INVALID, "NULL argument");
+    std::vector<float> h(kNP);
+    si_status rc = si_cost_model_get_params(m, h.data(), kNP);
+    if (rc != SI_OK) return rc;
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(SI_E_INVALID, std::string("cannot open ") + path);
+    const uint32_t ver = 1, np = kNP;
+    bool ok = fwrite("SICM", 1, 4, f) == 4 && fwrite(&ver, 4, 1, f) == 1 && fwrite(&np, 4, 1, f) == 1 &&
+              fwrite(&m->seed, 8, 1, f) == 1 && fwrite(h.data(), 4, kNP, f) == (size_t)kNP;
+    ok = (fclose(f) == 0) && ok;
+    return ok ? SI_OK : fail(SI_E_INVALID, "write failed");
 }
+
+si_status si_cost_model_load(const char* path, si_cost_model** out) {
+    if (!path || !out) return fail(SI_E_INVALID, "NULL argument");
+    *out = nullptr;
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(SI_E_INVALID, std::string("cannot open ") + path);
+    char magic[4];
+    uint32_t ver = 0, np = 0;
+    uint64_t seed = 0;
+    std::vector<float> h(kNP);
+    bool ok = fread(magic, 1, 4, f) == 4 && memcmp(magic, "SICM", 4) == 0 && fread(&ver, 4, 1, f) == 1 &&
+              ver == 1 && fread(&np, 4, 1, f) == 1 && np == (uint32_t)kNP && fread(&seed, 8, 1, f) == 1 &&
+              fread(h.data(), 4, kNP, f) == (size_t)kNP;
+    fclose(f);
+    if (!ok) return fail(SI_E_INVALID, "not a cost-model file");
+    for (float x : h)
+        if (!isfinite(x)) return fail(SI_E_INVALID, "cost-model file holds non-finite parameters");
+    si_status rc = si_cost_model_create(seed, out);
+    if (rc != SI_OK) return rc;
+    rc = si_cost_model_set_params(*out, h.data(), kNP);
+    if (rc != SI_OK) {
+        si_free_cost_model(*out);
+        *out = nullptr;
+    }
+    return rc;
 }
+
+si_status si_learned_table(const float* unit_cost, int64_t n, int32_t P, float fac_divisor,
+                           int32_t* perm_out, int64_t* starts_out, int64_t cap, int64_t* n_chunks) {
+    // Host reference of the ordering and cutting the device computes (for
+    // inspection and tests): units in descending cost key (stable), then
+    // factoring on cost.  unit_cost are already-rounded positive costs.
+    if (!unit_cost || n < 0 || P < 1 || !perm_out || !starts_out || !n_chunks)
+        return fail(SI_E_INVALID, "bad arguments");
+    std::vector<uint32_t> q(n);
+    std::vector<int32_t> key(n);
+    for (int64_t u = 0; u < n; ++u) {
+        const float c = unit_cost[u];
+        q[u] = (uint32_t)std::max(rintf(c == c ? std::min(c, 4.0e9f) : 1.0f), 1.0f);
+        const int k = (int)floorf(log2f((float)q[u]) * 32.0f);
+        key[u] = kKeys - 1 - std::min(std::max(k, 0), kKeys - 1);
+    }
+    std::vector<int32_t> order(n);
+    for (int64_t u = 0; u < n; ++u) order[u] = (int32_t)u;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    std::vector<int64_t> cpre(n + 1, 0);
+    for (int64_t k = 0; k < n; ++k) cpre[k + 1] = cpre[k] + q[order[k]];
+    const double x = fac_divisor > 0.0f ? (double)fac_divisor : 2.0;
+    std::vector<int64_t> starts;
+    starts.push_back(0);
+    int64_t st = 0;
+    while (st < n) {
+        const int64_t R = cpre[n] - cpre[st];
+        const int64_t cb = std::max<int64_t>(1, (int64_t)ceil((double)R / (x * (double)P)));
+        int64_t prev = st;
+        for (int j = 1; j <= P; ++j) {
+            const int64_t target = cpre[st] + (int64_t)j * cb;
+            const int64_t e = std::lower_bound(cpre.begin() + st + 1, cpre.end() - 1 + 1, target) -
+                              cpre.begin();
+            const int64_t end = std::min<int64_t>(e, n);
+            if (end > prev) {
+                starts.push_back(end);
+                prev = end;
+            }
+        }
+        st = prev;
+    }
+    *n_chunks = (int64_t)starts.size() - 1;
+    for (int64_t u = 0; u < n; ++u) perm_out[u] = order[u];
+    if (cap < (int64_t)starts.size()) return fail(SI_E_INVALID, "starts_out capacity too small");
+    for (size_t i = 0; i < starts.size(); ++i) starts_out[i] = starts[i];
+    return SI_OK;
+}
+
+}  // extern "C"

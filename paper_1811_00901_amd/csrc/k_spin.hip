@@ -370,6 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
 
     const int tid = threadIdx.x;
     const uint64_t t_begin = wall_clock64();
+    const int n_chunks = d.n_chunks_dev ? rfl(*d.n_chunks_dev) : d.n_chunks;
     unsigned long long my_tested = 0, my_support = 0;
     uint32_t my_invalid = 0, my_overflow = 0;
     int local = 0;  // static: chunks this workgroup has taken
@@ -381,16 +382,16 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
                 step = (int)atomicAdd(d.counter, 1u);
             } else if (d.wg_first) {
                 step = d.wg_first[blockIdx.x] + local;
-                if (step >= d.wg_first[blockIdx.x + 1]) step = d.n_chunks;
+                if (step >= d.wg_first[blockIdx.x + 1]) step = n_chunks;
             } else {
-                step = local == 0 ? (int)blockIdx.x : d.n_chunks;
+                step = local == 0 ? (int)blockIdx.x : n_chunks;
             }
             s_step = step;
         }
         ++local;
         __syncthreads();
         const int step = rfl(s_step);
-        if (step >= d.n_chunks) break;
+        if (step >= n_chunks) break;
         const Chunk ch = d.chunks[step];
         const int item_id = rfl(ch.item);
         const int c_start = rfl(ch.start);

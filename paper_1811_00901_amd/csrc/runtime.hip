@@ -446,6 +446,11 @@ si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_st
     stats->sched_used = sched_used;
     stats->n_wg = n_wg;
     stats->n_chunks = d.n_chunks;
+    if (d.n_chunks_dev) {
+        int32_t nc = 0;
+        SI_HIP(hipMemcpy(&nc, d.n_chunks_dev, sizeof(nc), hipMemcpyDeviceToHost));
+        stats->n_chunks = nc;
+    }
     if (stats->wg_busy_ns) {
         const int n = std::min(stats->wg_busy_cap, n_wg);
         for (int i = 0; i < n; ++i)
@@ -558,18 +563,24 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     int kind = sched->kind;
     Chunk* chunks = nullptr;
     int n_chunks = 0;
+    char* learned_mem = nullptr;
     if (kind == SI_SCHED_LEARNED) {
-        int32_t* perm = nullptr;
-        rc = learned_table(st, scene, oriented_idx, N, params, sched, n_wg, group, &chunks,
-                           &n_chunks, &perm, s);
-        if (rc == SI_E_UNSUPPORTED || (rc == SI_OK && !chunks)) {
+        LearnedPlan plan;
+        rc = sched->model ? learned_table(st, scene, oriented_idx, N, params, sched, n_wg, group,
+                                          &plan, s)
+                          : SI_E_UNSUPPORTED;
+        if (rc == SI_E_UNSUPPORTED) {
             if (!sched->fallback_to_fac)
                 return fail(SI_E_INVALID, "SI_SCHED_LEARNED needs a model (fallback disabled)");
-            kind = SI_SCHED_FAC;
+            kind = SI_SCHED_FAC;  // FAC is the fallback of the learned schedule
         } else if (rc != SI_OK) {
             return rc;
         } else {
-            d.single.perm = perm;
+            learned_mem = plan.mem;
+            d.single.perm = plan.perm;
+            chunks = plan.chunks;
+            n_chunks = plan.max_chunks;
+            d.n_chunks_dev = plan.n_chunks_dev;
         }
     }
     int32_t* order_mem = nullptr;
@@ -586,6 +597,7 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     d.dynamic = kind == SI_SCHED_STATIC ? 0 : 1;
     rc = run_launch(st, d, n_wg, w2, stats, s, kind);
     if (order_mem) (void)hipFreeAsync(order_mem, s);
+    if (learned_mem) (void)hipFreeAsync(learned_mem, s);
     return rc;
 }
 

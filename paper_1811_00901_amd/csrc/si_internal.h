@@ -95,6 +95,7 @@ struct LaunchDesc {
     int32_t dynamic;          // 0: static (see wg_first); 1: atomic claims
     const int32_t* wg_first;  // static only: workgroup k runs chunks
                               // [wg_first[k], wg_first[k+1]); nullptr = chunk k
+    const int32_t* n_chunks_dev;  // if set, the chunk count is read from here
     uint32_t* counter;        // 2 words: claim counter, finished workgroups
     int32_t group;            // images per shared candidate pass (1..kMaxGroup)
     int32_t max_w2;           // largest W*W over items (LDS sizing)
@@ -169,11 +170,22 @@ si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk, 
                     Chunk** out, int* n_out);
 si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_stats* stats,
                      hipStream_t s, int sched_used);
-// Learned schedule: device chunk table and iteration->output permutation for
-// one scene; returns SI_E_UNSUPPORTED when no model is given.
+// Learned schedule of one scene, computed on the device in stream order:
+// chunk table (its length on the device), iteration -> output permutation,
+// all inside `mem` (stream-ordered allocation the caller frees after use).
+struct LearnedPlan {
+    char* mem = nullptr;
+    Chunk* chunks = nullptr;
+    int32_t max_chunks = 0;
+    const int32_t* n_chunks_dev = nullptr;
+    const int32_t* perm = nullptr;
+};
+// Returns SI_E_UNSUPPORTED when sched->model is NULL.
 si_status learned_table(DeviceState* st, const Scene* scene, const int32_t* oriented, int64_t N,
                         const si_params* params, const si_sched* sched, int n_wg, int group,
-                        Chunk** chunks, int* n_chunks, int32_t** perm, hipStream_t s);
+                        LearnedPlan* plan, hipStream_t s);
+si_status features_launch(const Scene& sc, const int32_t* oriented, int64_t N,
+                          const si_params* params, float* feats, hipStream_t s);
 
 // Host chunk tables.
 int64_t chunk_sizes(int kind, int64_t N, int P, int min_chunk, float divisor,

@@ -1,0 +1,150 @@
+"""GPU: per-image cost model (features, MLP forward/backward/Adam) and the
+learned schedule, against the FP64 oracle of ``oracle.mlp``.
+
+Training data are in-support counts the library itself logs (counts_out of
+si_generate) on the uneven-density primitives scene.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import chunks as och
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+S60 = float(np.float32(math.pi / 3))
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import oracle
+    import paper_1811_00901_amd as si
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, si, oracle
+
+
+@pytest.fixture(scope="module")
+def prims(env):
+    """The 100k-point primitives scene, all 65,536 images, their counts and features."""
+    torch, si, oracle = env
+    xyz, nrm = sg.config_scene("prims100k")
+    params = si.Params(32, 0.02, S60)
+    radius = si.si_support_radius(params)
+    scene = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(), radius)
+    idx = torch.arange(65536, dtype=torch.int32, device="cuda")
+    img, cnt, _ = si.si_generate(scene, idx, params, si.Sched("fac"))
+    feats = si.si_features(scene, idx, params)
+    torch.cuda.synchronize()
+    return dict(xyz=xyz, nrm=nrm, params=params, radius=radius, scene=scene, idx=idx,
+                img=img, cnt=cnt, feats=feats)
+
+
+def test_features_vs_oracle(env, prims):
+    torch, si, oracle = env
+    print("\n[case] features", flush=True)
+    sample = np.sort(np.random.default_rng(1).choice(65536, 400, replace=False))
+    got = prims["feats"].cpu().numpy()[sample]
+    exp, _ = mlp.features(prims["xyz"], prims["nrm"], sample, prims["radius"],
+                          oracle.support_radius(32, 0.02))
+    np.testing.assert_allclose(got, exp, rtol=2e-5, atol=2e-6)
+
+
+def test_gradient_and_forward_vs_oracle(env, prims):
+    torch, si, _ = env
+    print("\n[case] gradient", flush=True)
+    model = si.si_cost_model_create(7)
+    theta = model.get_params().astype(np.float64)
+    sel = np.sort(np.random.default_rng(2).choice(65536, 4096, replace=False))
+    feats = prims["feats"][torch.from_numpy(sel).cuda()].contiguous()
+    counts = prims["cnt"][torch.from_numpy(sel).cuda()].contiguous()
+    g, loss = si.si_cost_model_gradient(model, feats, counts)
+    X = feats.cpu().numpy().astype(np.float64)
+    c = counts.cpu().numpy().view(np.uint32)
+    loss_o, g_o = mlp.loss_and_grad(theta, X, c)
+    assert abs(loss - loss_o) <= 1e-5 * loss_o
+    assert np.linalg.norm(g - g_o) <= 1e-4 * np.linalg.norm(g_o)
+    np.testing.assert_allclose(g, g_o, rtol=1e-3, atol=1e-4 * np.abs(g_o).max())
+    pred = si.si_cost_model_predict(model, feats).cpu().numpy()
+    out, _ = mlp.forward(theta, X)
+    np.testing.assert_allclose(pred, np.maximum(np.expm1(out), 0), rtol=1e-4, atol=1e-3)
+
+
+def test_training_save_load_and_reproducibility(env, prims, tmp_path):
+    torch, si, _ = env
+    print("\n[case] training", flush=True)
+    rng = np.random.default_rng(5)
+    order = rng.permutation(65536)
+    tr, te = order[:52428], order[52428:]
+    f = prims["feats"]
+    c = prims["cnt"]
+    f_tr = f[torch.from_numpy(tr).cuda()].contiguous()
+    c_tr = c[torch.from_numpy(tr).cuda()].contiguous()
+    f_te = f[torch.from_numpy(te).cuda()].contiguous()
+    c_te = c[torch.from_numpy(te).cuda()].cpu().numpy().view(np.uint32).astype(np.float64)
+    m = si.si_cost_model_create(11)
+    mae0 = np.abs(si.si_cost_model_predict(m, f_te).cpu().numpy() - c_te).mean()
+    curve = si.si_cost_model_train(m, f_tr, c_tr, epochs=6, lr=2e-3, batch=1024)
+    assert curve[-1] < 0.5 * curve[0], curve
+    mae1 = np.abs(si.si_cost_model_predict(m, f_te).cpu().numpy() - c_te).mean()
+    print(f"held-out MAE untrained {mae0:.1f} trained {mae1:.1f} (mean count {c_te.mean():.1f})")
+    assert mae1 < 0.5 * mae0
+    path = str(tmp_path / "model.sicm")
+    m.save(path)
+    m2 = si.CostModel.load(path)
+    assert np.array_equal(m.get_params(), m2.get_params())
+    # the same seed and data give the same trained parameters (fixed-order reductions)
+    m3 = si.si_cost_model_create(11)
+    si.si_cost_model_train(m3, f_tr, c_tr, epochs=6, lr=2e-3, batch=1024)
+    assert np.array_equal(m.get_params(), m3.get_params())
+
+
+def test_learned_schedule_images_identical(env, prims):
+    torch, si, _ = env
+    print("\n[case] learned schedule", flush=True)
+    m = si.si_cost_model_create(3)
+    si.si_cost_model_train(m, prims["feats"], prims["cnt"], epochs=2, lr=2e-3, batch=2048)
+    for order in ("cell", "given"):
+        img, cnt, st = si.si_generate(prims["scene"], prims["idx"], prims["params"],
+                                      si.Sched("learned", model=m, order=order), stats=True)
+        torch.cuda.synchronize()
+        assert st["sched_used"] == si.SCHED["learned"]
+        assert 0 < st["n_chunks"] <= 65536 // 16 + 1
+        assert torch.equal(img, prims["img"]) and torch.equal(cnt, prims["cnt"])
+    # a model file that is not one is rejected; no model falls back to FAC
+    with pytest.raises(si.SiError):
+        si.CostModel.load(__file__)
+    _, _, st = si.si_generate(prims["scene"], prims["idx"], prims["params"],
+                              si.Sched("learned"), stats=True)
+    assert st["sched_used"] == si.SCHED["fac"]
+
+
+def test_learned_order_gain_simulated(env, prims):
+    """Judge: per-image costs taken as the logged in-support counts (+1), P =
+    768 workers; the learned cut of the trained model's predictions gives a
+    shorter simulated makespan than FAC2 on the same loop and than the learned
+    cut of an untrained network's predictions."""
+    torch, si, _ = env
+    print("\n[case] learned gain (simulated)", flush=True)
+    P = 768
+    true = prims["cnt"].cpu().numpy().view(np.uint32).astype(np.float64) + 1.0
+    m = si.si_cost_model_create(9)
+    pred_u = si.si_cost_model_predict(m, prims["feats"]).cpu().numpy().astype(np.float64) + 1.0
+    si.si_cost_model_train(m, prims["feats"], prims["cnt"], epochs=6, lr=2e-3, batch=1024)
+    pred_t = si.si_cost_model_predict(m, prims["feats"]).cpu().numpy().astype(np.float64) + 1.0
+    U = 16
+    n_units = 65536 // U
+    unit_true = true.reshape(n_units, U).sum(1)
+
+    def learned_makespan(pred):
+        perm, st = si.si_learned_table(pred.reshape(n_units, U).sum(1), P, 2.0)
+        return och.simulate(unit_true[perm], np.diff(st), P).max()
+
+    fac = och.simulate(true, och.fac_sizes(65536, P), P).max()
+    lt, lu = learned_makespan(pred_t), learned_makespan(pred_u)
+    print(f"makespan FAC2 {fac:.0f} learned {lt:.0f} untrained {lu:.0f} mean {true.sum() / P:.0f}")
+    assert lt < fac and lt <= lu
