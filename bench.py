@@ -1,20 +1,31 @@
 """Spin-image generation benchmark on one MI355X.
 
-Workload (seeded, synthetic): the clustered primitives scene -- 2,000,000
-float32 oriented points on 400 random tori and ellipsoids whose centres are
-Gaussian-clustered (sigma 1) in a [0, 40]^3 box, per-object density varying
-tenfold -- with every point oriented, W = 32, bin 0.02, support angle 60
-degrees, bilinear binning, FAC chunking on the persistent kernel.
+Main workload (seeded, synthetic): the clustered primitives scene --
+2,000,000 float32 oriented points on 400 random tori and ellipsoids whose
+centres are Gaussian-clustered (sigma 1) in a [0, 40]^3 box, per-object
+density varying tenfold -- with every point oriented, W = 32, bin 0.02,
+support angle 60 degrees, bilinear binning, FAC chunking on the persistent
+kernel.
 
-One step = the whole hot path: si_build_scene (bounding box, cell binning,
-scan, scatter) followed by si_generate (FAC chunk claims, candidate culling,
-pair tests, LDS accumulation, image write-back), inputs already resident in
-HBM.  Reported value: in-support point pairs binned per second; also images
-per second, the generation-only time of every schedule with its speedup over
-STATIC (images bit-identical), the roofline of the spin kernel and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+One timed step = the whole hot path: si_build_scene (bounding box, cell
+binning, scan, scatter) followed by si_generate (cell ordering, FAC chunk
+claims, candidate culling, pair tests, LDS accumulation, image write-back),
+inputs already resident in HBM.  The reported value is in-support point pairs
+binned per second over the step; images per second beside it.
+
+Also reported (outside the timed steps):
+  * generation time of every schedule (STATIC, SS, GSS, FAC, LEARNED) with
+    its speedup over STATIC and a bit-identity check of the images;
+  * the learned cost model: trained on the in-support counts logged on the
+    100k-point primitives scene and on this scene (80/20 split), held-out MAE;
+  * batching: 256 primitive scenes of log-uniform size in [1k, 200k] points
+    and mixed W in {16, 32, 64}, one autotuned HIP-graph launch against a loop
+    of 256 si_generate calls;
+  * the roofline of the spin kernel and the FP64 CPU oracle timed on a
+    bounded sample of the main workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--no-schedules] [--no-batch] [--no-extent]
 """
 from __future__ import annotations
 
@@ -32,8 +43,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "in-support point-pairs binned/sec + spin-images/sec; learned vs FAC vs static"
 
-# Algorithmic work per unit (VALU lane operations and LDS atomics), counted on
-# the definition rather than on executed instructions:
+# Algorithmic work per unit (VALU lane operations), counted on the definition
+# rather than on executed instructions:
 #   every in-extent pair (inside the beta/alpha window, whatever its angle):
 #     3 subtractions, two 3-term dot products and a 3-term squared norm
 #     (9 mul/fma), 1 fma for alpha^2, 4 comparisons          -> 17 ops
@@ -57,14 +68,104 @@ def parse():
     ap.add_argument("--workload", default="clustered2m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-schedules", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-extent", action="store_true",
-                    help="skip the extra launches that count in-extent pairs (profiling runs)")
+                    help="stop after the timed steps (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def timed(torch, fn, reps, warm=1):
+    """Median wall time (ms) of fn() between device synchronisations."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+    return float(np.median(ts))
+
+
+def train_cost_model(torch, si, sg, main):
+    """Train the cost model on counts logged by the library on the 100k-point
+    primitives scene and on the main scene; 80/20 split, seed 5."""
+    cfg = sg.CONFIGS["prims100k"]
+    xyz, nrm = sg.config_scene("prims100k")
+    p2 = si.Params(cfg.W, cfg.bin, cfg.support_angle)
+    sc2 = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(),
+                            si.si_support_radius(p2))
+    idx2 = torch.arange(cfg.N, dtype=torch.int32, device="cuda")
+    _, cnt2, _ = si.si_generate(sc2, idx2, p2, si.Sched("fac"))
+    feats = torch.cat([si.si_features(sc2, idx2, p2),
+                       si.si_features(main["scene"], main["idx"], main["params"])])
+    counts = torch.cat([cnt2, main["counts"]])
+    n = int(feats.shape[0])
+    perm = torch.from_numpy(np.random.default_rng(5).permutation(n)).cuda()
+    n_tr = int(0.8 * n)
+    f_tr, c_tr = feats[perm[:n_tr]].contiguous(), counts[perm[:n_tr]].contiguous()
+    f_te, c_te = feats[perm[n_tr:]].contiguous(), counts[perm[n_tr:]].contiguous()
+    y_te = c_te.to(torch.float64)
+    model = si.si_cost_model_create(5)
+    mae0 = float((si.si_cost_model_predict(model, f_te).double() - y_te).abs().mean())
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    curve = si.si_cost_model_train(model, f_tr, c_tr, epochs=4, lr=2e-3, batch=4096)
+    train_s = time.perf_counter() - t
+    mae = float((si.si_cost_model_predict(model, f_te).double() - y_te).abs().mean())
+    info = {"samples_train": n_tr, "samples_test": n - n_tr, "epochs": 4, "batch": 4096,
+            "lr": 2e-3, "train_s": train_s, "loss_curve": [float(x) for x in curve],
+            "mae_test": mae, "mae_test_untrained": mae0, "mean_count_test": float(y_te.mean()),
+            "data": "counts logged on prims100k (65,536 images) + clustered2m (2,000,000 images)"}
+    sc2.free()
+    return model, info
+
+
+def batched(torch, si, sg):
+    """256 uneven scenes: per-scene loop of si_generate vs one autotuned graph launch."""
+    specs = sg.batch_specs(256)
+    items = []
+    for seed, M, W in specs:
+        xyz, nrm = sg.batch_scene(seed, M)
+        params = si.Params(W, 0.02, float(np.float32(math.pi / 3)))
+        scene = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(),
+                                  si.si_support_radius(params))
+        idx = torch.arange(M, dtype=torch.int32, device="cuda")
+        img = torch.empty((M, W, W), dtype=torch.float32, device="cuda")
+        cnt = torch.empty((M,), dtype=torch.int32, device="cuda")
+        items.append((scene, idx, params, img, cnt))
+    total_img = sum(int(it[1].shape[0]) for it in items)
+    fac = si.Sched("fac")
+
+    def loop():
+        for scene, idx, params, img, cnt in items:
+            si.si_generate(scene, idx, params, fac, img, cnt)
+
+    loop_ms = timed(torch, loop, 3)
+    ref = [(float(img.double().sum()), int(cnt.to(torch.int64).sum())) for _, _, _, img, cnt in items]
+    pairs = sum(r[1] for r in ref)
+    tuned, tune_ms = si.si_autotune(items, "fac", use_graph=True, max_trials=12)
+    graph_ms = timed(torch, lambda: si.si_generate_batched(items, tuned, use_graph=True), 5)
+    default_ms = timed(torch, lambda: si.si_generate_batched(items, fac, use_graph=True), 3)
+    same = all((float(img.double().sum()), int(cnt.to(torch.int64).sum())) == r
+               for (_, _, _, img, cnt), r in zip(items, ref))
+    out = {"workload": "256 primitive scenes, M log-uniform in [1k, 200k], W in {16,32,64}, "
+                       "bin 0.02, 60 deg, all points oriented",
+           "points": int(sum(s[1] for s in specs)), "images": total_img, "in_support_pairs": pairs,
+           "loop_ms": loop_ms, "graph_default_ms": default_ms, "graph_tuned_ms": graph_ms,
+           "speedup_vs_loop": loop_ms / graph_ms, "pairs_per_s": pairs / (graph_ms * 1e-3),
+           "images_per_s": total_img / (graph_ms * 1e-3), "identical": same,
+           "tuned": {"group": tuned.group, "num_workgroups": tuned.num_workgroups,
+                     "fac_divisor": tuned.fac_divisor, "min_chunk": tuned.min_chunk}}
+    for scene, *_ in items:
+        scene.free()
+    return out
 
 
 def main():
@@ -98,7 +199,7 @@ def main():
 
     def step():
         # e0/e1: the whole generation call (cell ordering + spin kernel);
-        # k0/k1: recorded by the library around the spin kernel alone
+        # e2/e3: recorded by the library around the spin kernel alone
         scene = si.si_build_scene(d_xyz, d_nrm, radius)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
@@ -110,11 +211,10 @@ def main():
 
     log("[bench] warmup")
     for _ in range(args.warmup):
-        sc, _ = step()
+        step()
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
-    events = []
-    scenes = []
+    events, scenes = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -133,13 +233,13 @@ def main():
     images_per_s = N / (ms_step * 1e-3)
     log(f"[bench] step {ms_step:.2f} ms (generation {gen_ms:.2f} ms, spin kernel {kernel_ms:.2f} ms), "
         f"{pairs} in-support pairs")
-
     if args.no_extent:
         print(json.dumps({"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
                           "generation_ms": gen_ms, "kernel_ms": kernel_ms, "profiling_run": True}),
               flush=True)
         return
+
     # ---- workload units for the roofline (outside the timed region) ----
     _, _, st = si.si_generate(scene, idx, params, fac, images, counts, stats=True)
     ref_img = images.clone()
@@ -167,32 +267,53 @@ def main():
         "lds_atomics_per_s": ATOMICS_PER_SUPPORT_PAIR * pairs / (kernel_ms * 1e-3),
     }
 
+    # ---- learned cost model ----
+    model, cm_info = None, None
+    if not args.no_schedules:
+        log("[bench] training the cost model")
+        model, cm_info = train_cost_model(
+            torch, si, sg, {"scene": scene, "idx": idx, "params": params, "counts": ref_cnt})
+        log(f"[bench] cost model: {cm_info['mae_test']:.1f} held-out MAE "
+            f"(untrained {cm_info['mae_test_untrained']:.1f})")
+
     # ---- every schedule, generation only, bit-identical images ----
     sched_res = {}
     if not args.no_schedules:
         for kind in ["static", "ss", "gss", "fac", "learned"]:
-            sch = si.Sched(kind)
-            times = []
-            ok = True
-            used = None
+            sch = si.Sched(kind, model=model if kind == "learned" else None)
+            times, used = [], None
             for r in range(4):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                ev[0].record(stream)
                 _, _, s2 = si.si_generate(scene, idx, params, sch, images, counts, stats=True)
+                ev[1].record(stream)
+                torch.cuda.synchronize()
                 used = s2["sched_used"]
                 if r:
-                    times.append(s2["kernel_ms"])
+                    times.append((s2["kernel_ms"], ev[0].elapsed_time(ev[1])))
             busy = s2["wg_busy_ns"].astype(np.float64)
             ok = bool(torch.equal(images, ref_img) and torch.equal(counts, ref_cnt))
-            sched_res[kind] = {"ms": float(np.median(times)), "identical": ok,
-                               "sched_used": list(si.SCHED)[used], "n_chunks": s2["n_chunks"],
+            sched_res[kind] = {"kernel_ms": float(np.median([t[0] for t in times])),
+                               "call_ms": float(np.median([t[1] for t in times])),
+                               "identical": ok, "sched_used": list(si.SCHED)[used],
+                               "n_chunks": s2["n_chunks"],
                                "imbalance": float(busy.max() / max(busy.mean(), 1.0))}
             log(f"[bench] {kind}: {sched_res[kind]}")
-        base = sched_res["static"]["ms"]
+        base = sched_res["static"]["call_ms"]
         for k in sched_res:
-            sched_res[k]["speedup_vs_static"] = base / sched_res[k]["ms"]
+            sched_res[k]["speedup_vs_static"] = base / sched_res[k]["call_ms"]
         si.si_generate(scene, idx, params, fac, images, counts)
     torch.cuda.synchronize()
+    del ref_img, ref_cnt
 
-    # ---- FP64 CPU oracle on a bounded sample of the same workload ----
+    # ---- batching ----
+    batch = None
+    if not args.no_batch:
+        log("[bench] batched: 256 scenes")
+        batch = batched(torch, si, sg)
+        log(f"[bench] batched: {batch}")
+
+    # ---- FP64 CPU oracle on a bounded sample of the main workload ----
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -201,7 +322,7 @@ def main():
         rng = np.random.default_rng(12345)
         probe = rng.choice(N, size=threads * 2, replace=False)
         t = time.perf_counter()
-        r = oracle.generate(xyz, nrm, probe, cfg.W, cfg.bin, cfg.support_angle, want_touch=False)
+        oracle.generate(xyz, nrm, probe, cfg.W, cfg.bin, cfg.support_angle, want_touch=False)
         per_img = (time.perf_counter() - t) / len(probe)
         n_s = int(max(threads, min(N, args.cpu_seconds / max(per_img, 1e-6))))
         sample = rng.choice(N, size=n_s, replace=False)
@@ -234,6 +355,8 @@ def main():
         "images_per_s": images_per_s,
         "generation_ms": gen_ms,
         "schedules": sched_res,
+        "cost_model": cm_info,
+        "batched": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
