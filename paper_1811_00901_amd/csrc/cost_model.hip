@@ -67,22 +67,40 @@ __global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* _
     const int c[3] = {cell % sc.dims[0], (cell / sc.dims[0]) % sc.dims[1],
                       cell / (sc.dims[0] * sc.dims[1])};
     const int half = kSub / 2;
+    // point counts of the 3 x 3 x 3 coarse cells around p: coarse offset d
+    // covers fine cells c + kSub d - half .. c + kSub d + half on each axis;
+    // each fine row (y, z) contributes to three coarse cells through four
+    // cell_start boundaries along x
+    int occ[3][3][3] = {};
+    const int xb[4] = {c[0] - kSub - half, c[0] - half, c[0] + half + 1, c[0] + kSub + half + 1};
+    int xc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) xc[b] = min(max(xb[b], 0), sc.dims[0]);
+    for (int zz = -kSub - half; zz <= kSub + half; ++zz) {
+        const int z = c[2] + zz;
+        if (z < 0 || z >= sc.dims[2]) continue;
+        const int dz = (zz + half + kSub) / kSub;  // 0, 1, 2 for offsets -1, 0, +1
+        for (int yy = -kSub - half; yy <= kSub + half; ++yy) {
+            const int y = c[1] + yy;
+            if (y < 0 || y >= sc.dims[1]) continue;
+            const int dy = (yy + half + kSub) / kSub;
+            const int row = (z * sc.dims[1] + y) * sc.dims[0];
+            int e[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) e[b] = sc.cell_start[row + xc[b]];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) occ[dz][dy][dx] += e[dx + 1] - e[dx];
+        }
+    }
     float shell[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float tot = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f, s8 = 0.0f, s9 = 0.0f;
+#pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
-        const int z0 = max(c[2] + kSub * dz - half, 0), z1 = min(c[2] + kSub * dz + half, sc.dims[2] - 1);
+#pragma unroll
         for (int dy = -1; dy <= 1; ++dy) {
-            const int y0 = max(c[1] + kSub * dy - half, 0), y1 = min(c[1] + kSub * dy + half, sc.dims[1] - 1);
+#pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
-                const int x0 = max(c[0] + kSub * dx - half, 0), x1 = min(c[0] + kSub * dx + half, sc.dims[0] - 1);
-                int cnt = 0;
-                if (x1 >= x0)
-                    for (int z = z0; z <= z1; ++z)
-                        for (int y = y0; y <= y1; ++y) {
-                            const int row = (z * sc.dims[1] + y) * sc.dims[0];
-                            cnt += sc.cell_start[row + x1 + 1] - sc.cell_start[row + x0];
-                        }
-                const float o_ = (float)cnt;
+                const float o_ = (float)occ[dz + 1][dy + 1][dx + 1];
                 shell[abs(dx) + abs(dy) + abs(dz)] += o_;
                 tot += o_;
                 mx += o_ * dx;
@@ -300,134 +318,133 @@ __global__ void __launch_bounds__(kTile) k_unit_hist(const int32_t* __restrict__
         tile_hist[(size_t)blockIdx.x * kKeys + k] = hist[k];
 }
 
-// Exclusive offsets: tile_hist[t][k] <- units of key k in tiles < t, plus the
-// units of all smaller keys.  One block of kKeys threads.
-__global__ void __launch_bounds__(kKeys) k_unit_offsets(int32_t* __restrict__ tile_hist, int n_tiles) {
-    __shared__ int tot[kKeys];
-    const int k = threadIdx.x;
-    int run = 0;
-    for (int t = 0; t < n_tiles; ++t) {
-        const int c = tile_hist[(size_t)t * kKeys + k];
-        tile_hist[(size_t)t * kKeys + k] = run;
-        run += c;
-    }
-    tot[k] = run;
+// Exclusive offsets of key k over the tiles (block k): tile_hist[t][k] <- units
+// of key k in tiles < t; key_total[k] <- units of key k.
+__global__ void __launch_bounds__(256) k_unit_tile_scan(int32_t* __restrict__ tile_hist, int n_tiles,
+                                                        int32_t* __restrict__ key_total) {
+    __shared__ int sc[256];
+    __shared__ int carry;
+    const int k = blockIdx.x, tid = threadIdx.x;
+    if (tid == 0) carry = 0;
     __syncthreads();
-    // exclusive scan of the key totals (sequential; kKeys values)
-    __shared__ int base[kKeys];
-    if (k == 0) {
-        int b = 0;
-        for (int i = 0; i < kKeys; ++i) {
-            base[i] = b;
-            b += tot[i];
+    for (int t0 = 0; t0 < n_tiles; t0 += 256) {
+        const int t = t0 + tid;
+        const int v = t < n_tiles ? tile_hist[(size_t)t * kKeys + k] : 0;
+        sc[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int a = tid >= off ? sc[tid - off] : 0;
+            __syncthreads();
+            sc[tid] += a;
+            __syncthreads();
         }
+        if (t < n_tiles) tile_hist[(size_t)t * kKeys + k] = carry + sc[tid] - v;
+        __syncthreads();
+        if (tid == 255) carry += sc[255];
+        __syncthreads();
     }
+    if (tid == 0) key_total[k] = carry;
+}
+
+// key_base[k] = units of all keys < k (one block of kKeys threads).
+__global__ void __launch_bounds__(kKeys) k_unit_key_base(const int32_t* __restrict__ key_total,
+                                                         int32_t* __restrict__ key_base) {
+    __shared__ int sc[kKeys];
+    const int k = threadIdx.x;
+    const int v = key_total[k];
+    sc[k] = v;
     __syncthreads();
-    for (int t = 0; t < n_tiles; ++t) tile_hist[(size_t)t * kKeys + k] += base[k];
+    for (int off = 1; off < kKeys; off <<= 1) {
+        const int a = k >= off ? sc[k - off] : 0;
+        __syncthreads();
+        sc[k] += a;
+        __syncthreads();
+    }
+    key_base[k] = sc[k] - v;
 }
 
 __global__ void __launch_bounds__(256) k_unit_scatter(const int32_t* __restrict__ key,
                                                       const int32_t* __restrict__ rank,
                                                       const int32_t* __restrict__ tile_hist,
+                                                      const int32_t* __restrict__ key_base,
                                                       int64_t n_units, int32_t* __restrict__ order) {
     const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (u >= n_units) return;
     const int64_t t = u / kTile;
-    order[tile_hist[t * kKeys + key[u]] + rank[u]] = (int32_t)u;
+    const int k = key[u];
+    order[key_base[k] + tile_hist[t * kKeys + k] + rank[u]] = (int32_t)u;
 }
 
-// Single block: prefix cost / iteration count over the LPT order, factoring on
-// predicted cost, chunk table and its length.
-__global__ void __launch_bounds__(1024) k_learned_chunks(const int32_t* __restrict__ order,
-                                                         const uint32_t* __restrict__ qcost,
-                                                         int64_t n_units, int64_t N, int P,
-                                                         float divisor,
-                                                         int64_t* __restrict__ cpre,
-                                                         int64_t* __restrict__ ipre,
+// Per LPT position k: the cost and the iteration count of unit order[k].
+__global__ void __launch_bounds__(256) k_unit_gather(const int32_t* __restrict__ order,
+                                                     const uint32_t* __restrict__ qcost,
+                                                     int64_t n_units, int64_t N,
+                                                     int64_t* __restrict__ cval,
+                                                     int64_t* __restrict__ ival) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n_units) return;
+    const int64_t u = order[k];
+    cval[k] = qcost[u];
+    ival[k] = min((int64_t)kUnit, N - u * kUnit);
+}
+
+// Single block: factoring on predicted cost over the LPT order (cpre, ipre:
+// exclusive prefix sums of cost and iterations, n_units + 1 entries), the
+// chunk table and its length.
+__global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restrict__ cpre,
+                                                         const int64_t* __restrict__ ipre,
+                                                         int64_t n_units, int P, float divisor,
                                                          Chunk* __restrict__ chunks,
                                                          int32_t* __restrict__ n_chunks) {
-    __shared__ int64_t sc[1024];
-    __shared__ int64_t si_[1024];
-    __shared__ int64_t carry_c, carry_i;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        carry_c = 0;
-        carry_i = 0;
-    }
-    __syncthreads();
-    for (int64_t b = 0; b < n_units; b += 1024) {
-        const int64_t k = b + tid;
-        int64_t c = 0, it = 0;
-        if (k < n_units) {
-            const int32_t u = order[k];
-            c = qcost[u];
-            it = min((int64_t)kUnit, N - (int64_t)u * kUnit);
-        }
-        sc[tid] = c;
-        si_[tid] = it;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int64_t tc = tid >= off ? sc[tid - off] : 0;
-            const int64_t ti = tid >= off ? si_[tid - off] : 0;
-            __syncthreads();
-            sc[tid] += tc;
-            si_[tid] += ti;
-            __syncthreads();
-        }
-        if (k < n_units) {
-            cpre[k] = carry_c + sc[tid] - c;
-            ipre[k] = carry_i + si_[tid] - it;
-        }
-        __syncthreads();
-        if (tid == 1023) {
-            carry_c += sc[1023];
-            carry_i += si_[1023];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        cpre[n_units] = carry_c;
-        ipre[n_units] = carry_i;
-    }
-    __syncthreads();
     const int64_t total = cpre[n_units];
     __shared__ int64_t start;
     __shared__ int emitted;
     __shared__ int64_t ends[1025];
+    __shared__ int pos[1024];
     if (tid == 0) {
         start = 0;
         emitted = 0;
     }
     __syncthreads();
     const double x = divisor > 0.0f ? (double)divisor : 2.0;
+    const int j = tid + 1;  // this thread's chunk of the batch (P <= 1024)
     while (start < n_units) {
         const int64_t st = start;
         const int64_t R = total - cpre[st];
         const int64_t cb = max((int64_t)1, (int64_t)ceil((double)R / (x * (double)P)));
         // end of chunk j (1..P): first k > st with cpre[k] - cpre[st] >= j * cb, else n_units
-        for (int j = tid + 1; j <= P; j += 1024) {
+        if (j <= P) {
             const int64_t target = cpre[st] + (int64_t)j * cb;
             int64_t lo = st + 1, hi = n_units;
             while (lo < hi) {
                 const int64_t mid = (lo + hi) >> 1;
                 if (cpre[mid] >= target) hi = mid; else lo = mid + 1;
             }
-            if (j <= 1024) ends[j] = lo;
+            ends[j] = lo;
         }
         if (tid == 0) ends[0] = st;
         __syncthreads();
-        // P <= 1024 is enforced by the host; emit the non-empty chunks in order
+        // non-empty chunks of the batch, written in order (block prefix sum)
+        const int f = (j <= P && ends[j] > ends[j - 1]) ? 1 : 0;
+        pos[tid] = f;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int t = tid >= off ? pos[tid - off] : 0;
+            __syncthreads();
+            pos[tid] += t;
+            __syncthreads();
+        }
+        if (f) {
+            Chunk c;
+            c.item = 0;
+            c.start = (int32_t)ipre[ends[j - 1]];
+            c.end = (int32_t)ipre[ends[j]];
+            chunks[emitted + pos[tid] - 1] = c;
+        }
+        __syncthreads();
         if (tid == 0) {
-            int e = emitted;
-            for (int j = 1; j <= P; ++j) {
-                if (ends[j] > ends[j - 1]) {
-                    chunks[e].item = 0;
-                    chunks[e].start = (int32_t)ipre[ends[j - 1]];
-                    chunks[e].end = (int32_t)ipre[ends[j]];
-                    ++e;
-                }
-            }
-            emitted = e;
+            emitted += pos[1023];
             start = ends[P];
         }
         __syncthreads();
@@ -500,8 +517,13 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
     const size_t o_urank = take(sizeof(int32_t) * n_units);
     const size_t o_hist = take(sizeof(int32_t) * n_tiles * kKeys);
     const size_t o_order = take(sizeof(int32_t) * n_units);
+    const size_t o_ktot = take(sizeof(int32_t) * kKeys);
+    const size_t o_kbase = take(sizeof(int32_t) * kKeys);
     const size_t o_cpre = take(sizeof(int64_t) * (n_units + 1));
     const size_t o_ipre = take(sizeof(int64_t) * (n_units + 1));
+    const size_t o_cval = take(sizeof(int64_t) * n_units);
+    const size_t o_ival = take(sizeof(int64_t) * n_units);
+    const size_t o_stmp = take(sizeof(int64_t) * scan_tmp_elems(n_units));
     const size_t o_chunks = take(sizeof(Chunk) * (n_units + 1));
     const size_t o_nch = take(sizeof(int32_t));
     const size_t o_perm = take(sizeof(int32_t) * N);
@@ -528,17 +550,23 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
                            n_units, reinterpret_cast<uint32_t*>(mem + o_qcost), I(o_ukey));
         hipLaunchKernelGGL(k_unit_hist, dim3((unsigned)n_tiles), dim3(kTile), 0, s, I(o_ukey),
                            n_units, I(o_hist), I(o_urank));
-        hipLaunchKernelGGL(k_unit_offsets, dim3(1), dim3(kKeys), 0, s, I(o_hist), (int)n_tiles);
+        hipLaunchKernelGGL(k_unit_tile_scan, dim3(kKeys), dim3(256), 0, s, I(o_hist), (int)n_tiles,
+                           I(o_ktot));
+        hipLaunchKernelGGL(k_unit_key_base, dim3(1), dim3(kKeys), 0, s, I(o_ktot), I(o_kbase));
         hipLaunchKernelGGL(k_unit_scatter, dim3(nblocks(n_units)), dim3(256), 0, s, I(o_ukey),
-                           I(o_urank), I(o_hist), n_units, I(o_order));
-        hipLaunchKernelGGL(k_learned_chunks, dim3(1), dim3(1024), 0, s, I(o_order),
-                           reinterpret_cast<uint32_t*>(mem + o_qcost), n_units, N, n_wg,
-                           sched->fac_divisor, reinterpret_cast<int64_t*>(mem + o_cpre),
-                           reinterpret_cast<int64_t*>(mem + o_ipre),
+                           I(o_urank), I(o_hist), I(o_kbase), n_units, I(o_order));
+        auto L = [&](size_t off) { return reinterpret_cast<int64_t*>(mem + off); };
+        hipLaunchKernelGGL(k_unit_gather, dim3(nblocks(n_units)), dim3(256), 0, s, I(o_order),
+                           reinterpret_cast<uint32_t*>(mem + o_qcost), n_units, N, L(o_cval),
+                           L(o_ival));
+        e = launch_scan64(L(o_cval), L(o_cpre), n_units, L(o_stmp), s);
+        if (e == hipSuccess) e = launch_scan64(L(o_ival), L(o_ipre), n_units, L(o_stmp), s);
+        hipLaunchKernelGGL(k_learned_chunks, dim3(1), dim3(1024), 0, s, L(o_cpre), L(o_ipre),
+                           n_units, n_wg, sched->fac_divisor,
                            reinterpret_cast<Chunk*>(mem + o_chunks), I(o_nch));
         hipLaunchKernelGGL(k_learned_perm, dim3(nblocks(n_units)), dim3(256), 0, s, I(o_order),
                            reinterpret_cast<int64_t*>(mem + o_ipre), perm0, N, n_units, I(o_perm));
-        e = hipGetLastError();
+        if (e == hipSuccess) e = hipGetLastError();
     }
     if (e != hipSuccess) {
         (void)hipFreeAsync(mem, s);

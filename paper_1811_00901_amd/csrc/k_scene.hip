@@ -105,16 +105,17 @@ __global__ void __launch_bounds__(256) k_bin_points(const float* __restrict__ xy
 }
 
 // Tile sums of the input.
-__global__ void __launch_bounds__(256) k_scan_tiles(const int32_t* __restrict__ in, int64_t n,
-                                                    int32_t* __restrict__ tile_sum) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_scan_tiles(const T* __restrict__ in, int64_t n,
+                                                    T* __restrict__ tile_sum) {
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    int s = 0;
+    T s = 0;
 #pragma unroll
     for (int k = 0; k < kScanTile / 256; ++k) {
         const int64_t i = base + k * 256 + threadIdx.x;
         if (i < n) s += in[i];
     }
-    __shared__ int red[256];
+    __shared__ T red[256];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -125,34 +126,36 @@ __global__ void __launch_bounds__(256) k_scan_tiles(const int32_t* __restrict__ 
 }
 
 // Exclusive block scan of 256 values; returns the exclusive prefix, *total.
-__device__ int block_excl_scan(int v, int* s, int* total) {
+template <typename T>
+__device__ T block_excl_scan(T v, T* s, T* total) {
     s[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-        const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+        const T t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
         __syncthreads();
         s[threadIdx.x] += t;
         __syncthreads();
     }
-    const int incl = s[threadIdx.x];
+    const T incl = s[threadIdx.x];
     *total = s[255];
     __syncthreads();
     return incl - v;
 }
 
 // Exclusive scan of the tile sums in place (one workgroup).
-__global__ void __launch_bounds__(256) k_scan_tile_sums(int32_t* __restrict__ t, int64_t n_tiles) {
-    __shared__ int s[256];
+template <typename T>
+__global__ void __launch_bounds__(256) k_scan_tile_sums(T* __restrict__ t, int64_t n_tiles) {
+    __shared__ T s[256];
     const int64_t per = (n_tiles + 255) / 256;
     const int64_t b = threadIdx.x * per;
-    int sum = 0;
+    T sum = 0;
     for (int64_t k = 0; k < per; ++k)
         if (b + k < n_tiles) sum += t[b + k];
-    int total;
-    int run = block_excl_scan(sum, s, &total);
+    T total;
+    T run = block_excl_scan(sum, s, &total);
     for (int64_t k = 0; k < per; ++k) {
         if (b + k < n_tiles) {
-            const int v = t[b + k];
+            const T v = t[b + k];
             t[b + k] = run;
             run += v;
         }
@@ -160,20 +163,21 @@ __global__ void __launch_bounds__(256) k_scan_tile_sums(int32_t* __restrict__ t,
 }
 
 // Exclusive scan of each tile plus its offset; out[n] = total.
-__global__ void __launch_bounds__(256) k_scan_apply(const int32_t* __restrict__ in, int64_t n,
-                                                    const int32_t* __restrict__ tile_off,
-                                                    int32_t* __restrict__ out) {
-    __shared__ int s[256];
+template <typename T>
+__global__ void __launch_bounds__(256) k_scan_apply(const T* __restrict__ in, int64_t n,
+                                                    const T* __restrict__ tile_off,
+                                                    T* __restrict__ out) {
+    __shared__ T s[256];
     const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * (kScanTile / 256);
-    int v[kScanTile / 256];
-    int sum = 0;
+    T v[kScanTile / 256];
+    T sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanTile / 256; ++k) {
         v[k] = (base + k < n) ? in[base + k] : 0;
         sum += v[k];
     }
-    int total;
-    int run = block_excl_scan(sum, s, &total) + tile_off[blockIdx.x];
+    T total;
+    T run = block_excl_scan(sum, s, &total) + tile_off[blockIdx.x];
 #pragma unroll
     for (int k = 0; k < kScanTile / 256; ++k) {
         if (base + k < n) out[base + k] = run;
@@ -331,13 +335,27 @@ hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32
 
 int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
+template <typename T>
+static hipError_t scan_impl(const T* in, T* out, int64_t n, T* tmp, hipStream_t s) {
+    const int64_t nt = (n + kScanTile - 1) / kScanTile;
+    if (nt == 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, reinterpret_cast<int32_t*>(out),
+                           (int64_t)(sizeof(T) / 4), 0);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_tiles<T>, dim3((unsigned)nt), dim3(256), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_tile_sums<T>, dim3(1), dim3(256), 0, s, tmp, nt);
+    hipLaunchKernelGGL(k_scan_apply<T>, dim3((unsigned)nt), dim3(256), 0, s, in, n, tmp, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t,
                        hipStream_t s) {
-    const int64_t nt = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(256), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(256), 0, s, tmp, nt);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(256), 0, s, in, n, tmp, out);
-    return hipGetLastError();
+    return scan_impl<int32_t>(in, out, n, tmp, s);
+}
+
+hipError_t launch_scan64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+    return scan_impl<int64_t>(in, out, n, tmp, s);
 }
 
 hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* cell_of,

@@ -122,6 +122,8 @@ hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t tmp_n,
                        hipStream_t s);
 int64_t scan_tmp_elems(int64_t n);
+// 64-bit exclusive scan, out[n] = total; tmp holds scan_tmp_elems(n) values.
+hipError_t launch_scan64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // perm: iterations sorted by the cell of their oriented point (counting sort;
 // order within a cell is arbitrary).  Temporaries: key, rank (N), counts
