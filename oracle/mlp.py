@@ -16,8 +16,8 @@ instead.  This module is the plain definition used to check the library:
     f10     log1p(sum o);
     f11     support radius / (s h).
   The grid is rebuilt here from the raw points exactly as the library
-  defines it (origin = per-axis minimum, h = R_max (1 + 2e-5) / 3, cell =
-  floor((x - origin) / h) in float64).
+  defines it (origin = per-axis minimum, cell =
+  floor((x - origin) / h) in float64, h = R_max (1 + 2e-5) / s).
 * ``forward`` / ``backward``: MLP 12 -> 64 -> 64 -> 1 with ReLU, loss =
   mean((out - log1p(count))^2); analytic gradients.
 * ``adam_step``: Adam (beta1 0.9, beta2 0.999, eps 1e-8) with bias correction.

@@ -50,6 +50,49 @@ __device__ __forceinline__ float rfl(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 __device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double rfl(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = (uint32_t)rfl((int)(uint32_t)b), hi = (uint32_t)rfl((int)(uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <typename T>
+__device__ __forceinline__ T* rfl(T* v) {
+    const uint64_t b = (uint64_t)v;
+    const uint64_t lo = (uint32_t)rfl((int)(uint32_t)b), hi = (uint32_t)rfl((int)(uint32_t)(b >> 32));
+    return (T*)((hi << 32) | lo);
+}
+
+// Per-item values the whole workgroup shares, pinned to scalar registers so
+// that comparisons against them and branches on them stay wave-uniform.
+__device__ __forceinline__ SpinParams uniform(const SpinParams& a) {
+    SpinParams b;
+    b.W = rfl(a.W);
+    b.mode = rfl(a.mode);
+    b.half = rfl(a.half);
+    b.inv_bin = rfl(a.inv_bin);
+    b.beta_lo = rfl(a.beta_lo);
+    b.beta_hi = rfl(a.beta_hi);
+    b.alpha2_max = rfl(a.alpha2_max);
+    b.cos_s = rfl(a.cos_s);
+    b.angle_on = rfl(a.angle_on);
+    b.radius = rfl(a.radius);
+    b.reach = rfl(a.reach);
+    return b;
+}
+__device__ __forceinline__ SceneView uniform(const SceneView& a) {
+    SceneView b;
+    b.pos = rfl(a.pos);
+    b.nrm = rfl(a.nrm);
+    b.cell_start = rfl(a.cell_start);
+    b.inv = rfl(a.inv);
+    for (int k = 0; k < 3; ++k) {
+        b.dims[k] = rfl(a.dims[k]);
+        b.origin[k] = rfl(a.origin[k]);
+    }
+    b.h = rfl(a.h);
+    b.M = rfl(a.M);
+    return b;
+}
 
 __device__ __forceinline__ void cell_xyz(int cell, const int* dims, int& cx, int& cy, int& cz) {
     cx = cell % dims[0];
@@ -68,23 +111,26 @@ __device__ __forceinline__ void cell_xyz(int cell, const int* dims, int& cx, int
 template <int MODE, typename Acc>
 __device__ __forceinline__ void bin_pair(Acc* img, const SpinParams& p, float beta, float a2) {
     const int W = p.W;
-    const float v = fmaf(-beta, p.inv_bin, p.half);
     a2 = fmaxf(a2, 0.0f);
     if (MODE == SI_BIN_BILINEAR) {
-        const float u = __builtin_amdgcn_sqrtf(a2) * p.inv_bin;
-        const float fi = fminf(fmaxf(floorf(v), 0.0f), (float)(W - 2));
-        const float fj = fminf(fmaxf(floorf(u), 0.0f), (float)(W - 2));
-        const float a = __saturatef(v - fi);
-        const float b = __saturatef(u - fj);
-        const uint32_t qa = (uint32_t)rintf(a * 65536.0f);
-        const uint32_t qb = (uint32_t)rintf(b * 65536.0f);
-        const uint32_t q11 = (uint32_t)(((uint64_t)qa * qb + 32768u) >> 16);
-        Acc* r0 = img + __umul24((uint32_t)fi, (uint32_t)W) + (uint32_t)fj;
-        atomicAdd(r0, (Acc)(65536u - qa - qb + q11));
-        atomicAdd(r0 + 1, (Acc)(qb - q11));
-        atomicAdd(r0 + W, (Acc)(qa - q11));
+        // 16.16 fixed-point positions V = round(v 2^16), U = round(u 2^16),
+        // kept below (W - 1) 2^16 so that the 2 x 2 footprint stays inside
+        const float s = 65536.0f;
+        const float top = (float)(((W - 1) << 16) - 1);
+        const float vf = fmaf(-beta, p.inv_bin * s, fmaf(p.half, s, 0.5f));
+        const float uf = fmaf(__builtin_amdgcn_sqrtf(a2), p.inv_bin * s, 0.5f);
+        const uint32_t V = (uint32_t)__builtin_amdgcn_fmed3f(vf, 0.0f, top);
+        const uint32_t U = (uint32_t)__builtin_amdgcn_fmed3f(uf, 0.0f, top);
+        const uint32_t qa = V & 0xffffu, qb = U & 0xffffu;
+        const uint32_t q11 = (__umul24(qa, qb) + 32768u) >> 16;
+        const uint32_t w10 = qa - q11, w01 = qb - q11;
+        Acc* r0 = img + __umul24(V >> 16, (uint32_t)W) + (U >> 16);
+        atomicAdd(r0, (Acc)(65536u - qb - w10));
+        atomicAdd(r0 + 1, (Acc)w01);
+        atomicAdd(r0 + W, (Acc)w10);
         atomicAdd(r0 + W + 1, (Acc)q11);
     } else {
+        const float v = fmaf(-beta, p.inv_bin, p.half);
         const float u = sqrtf(a2) * p.inv_bin;
         int k = (int)ceilf(v);
         int l = (int)ceilf(u);
@@ -156,11 +202,17 @@ template <int MODE>
 __device__ __forceinline__ void flush_queue(const SpinParams& p, uint32_t* acc, const float2* q_ba,
                                             const uint32_t* q_g, int qn) {
     const int lane = threadIdx.x & 63;
-    const uint32_t w2 = (uint32_t)(p.W * p.W);
+    const uint32_t w2 = (uint32_t)(p.W * p.W) + 4u;  // padded image stride
     wave_sync_lds();
-    for (int e = lane; e < qn; e += 64) {
-        const float2 ba = q_ba[e];
-        bin_pair<MODE>(acc + __umul24(q_g[e], w2), p, ba.x, ba.y);
+    // lane l takes entries l*T .. l*T+T-1 (T = rounds): entries appended
+    // together (neighbouring points, often the same bins) go to different rounds
+    const int T = (qn + 63) >> 6;
+    for (int t = 0; t < T; ++t) {
+        const int e = lane * T + t;
+        if (e < qn) {
+            const float2 ba = q_ba[e];
+            bin_pair<MODE>(acc + __umul24(q_g[e], w2), p, ba.x, ba.y);
+        }
     }
     wave_sync_lds();
 }
@@ -195,6 +247,7 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
         m = gnrm[j];
     };
     int qn = 0;
+    const bool angle_on = rfl(p.angle_on) != 0;
     f32x4 xn = {0.0f, 0.0f, 0.0f, 0.0f}, mn = xn;
     int kb = wave * 64;
     bool vn = kb + lane < total;
@@ -202,6 +255,7 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
     for (; kb < total; kb += kBlock) {
         const f32x4 x = xn, m = mn;
         const bool valid = vn;
+        const uint64_t vmask = __builtin_amdgcn_ballot_w64(valid);
         vn = kb + kBlock + lane < total;
         if (vn) fetch(kb + kBlock + lane, xn, mn);
 #pragma unroll
@@ -213,17 +267,22 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
                 const float beta = fmaf(gi[g].nz, dz, fmaf(gi[g].ny, dy, gi[g].nx * dx));
                 const float dd = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                 const float a2 = fmaf(-beta, beta, dd);
-                bool in;
-                if (MODE == SI_BIN_BILINEAR)
-                    in = (beta <= p.beta_hi) & (beta > p.beta_lo) & (a2 < p.alpha2_max);
-                else
-                    in = (beta < p.beta_hi) & (beta >= p.beta_lo) & (a2 <= p.alpha2_max);
-                if (p.angle_on) {
-                    const float c = fmaf(gi[g].nz, m[2], fmaf(gi[g].ny, m[1], gi[g].nx * m[0]));
-                    in = in & (c >= p.cos_s);
+                // one ballot per comparison: each is that compare's lane mask
+                bool b0, b1, b2;
+                if (MODE == SI_BIN_BILINEAR) {
+                    b0 = beta <= p.beta_hi; b1 = beta > p.beta_lo; b2 = a2 < p.alpha2_max;
+                } else {
+                    b0 = beta < p.beta_hi; b1 = beta >= p.beta_lo; b2 = a2 <= p.alpha2_max;
                 }
-                in = in & valid;
-                const uint64_t mask = __builtin_amdgcn_ballot_w64(in);
+                uint64_t mask = __builtin_amdgcn_ballot_w64(b0) & __builtin_amdgcn_ballot_w64(b1) &
+                                __builtin_amdgcn_ballot_w64(b2) & vmask;
+                bool in = b0 & b1 & b2 & valid;
+                if (angle_on) {
+                    const float c = fmaf(gi[g].nz, m[2], fmaf(gi[g].ny, m[1], gi[g].nx * m[0]));
+                    const bool b3 = c >= p.cos_s;
+                    mask &= __builtin_amdgcn_ballot_w64(b3);
+                    in = in & b3;
+                }
                 if (mask) {
                     if (in) {
                         const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi(
@@ -252,72 +311,101 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
-// Rows (z, y) of grid cells that may hold candidates of the group, with the
-// contiguous x-run of cells of each row, culled against the support sphere of
-// every image (double precision, radius inflated by 1e-6 relative).
-// Executed by wave 0; lane l handles row l.  Writes row_start/row_pref.
-__device__ __forceinline__ void build_rows(const SceneView& sc, const SpinParams& p, const GroupImg* gi,
-                           const int* gcell, int ng, int lo[3], int hi[3], int* row_start,
-                           int* row_pref, int* n_rows_out) {
-    const int lane = threadIdx.x;  // caller guarantees threadIdx.x < 64
+// Rows (z, y) of grid cells that may hold candidates of the group, each with
+// the contiguous x-run of cells that meets the support sphere and the beta
+// slab of some image of the group (double precision; radius inflated by 1e-5
+// relative and slab by 1e-4 R, far above the rounding of the reciprocals
+// used here).  Two phases, both called by every thread of the block:
+// rows_cull: thread t bounds row t % 64 against images t / 64 and t / 64 + 4
+// into part_x0/part_x1[t]; rows_emit (after a barrier): lane r of wave 0
+// merges the four partial runs of row r, looks the run up in cell_start and
+// writes row_start / row_pref (exclusive prefix of run lengths) / n_rows.
+__device__ __forceinline__ void rows_cull(const SceneView& sc, const SpinParams& p,
+                                          const GroupImg* gi, const int* gcell, int ng,
+                                          const int lo[3], const int hi[3], int* part_x0,
+                                          int* part_x1) {
+    const int t = threadIdx.x;
+    const int r = t & 63, q = rfl(t >> 6);
     const int ny_rows = hi[1] - lo[1] + 1;
     const int nz_rows = hi[2] - lo[2] + 1;
     const int n_rows = ny_rows * nz_rows;  // <= kMaxRows by construction
-    int len = 0, start = 0;
-    if (lane < n_rows) {
-        const int cy = lo[1] + lane % ny_rows;
-        const int cz = lo[2] + lane / ny_rows;
+    int x0 = 0x7fffffff, x1 = -1;
+    if (r < n_rows) {
+        const int cy = lo[1] + r % ny_rows;
+        const int cz = lo[2] + r / ny_rows;
         const double h = sc.h;
+        const double inv_h = 1.0 / h;
         const double R = (double)p.radius;
         const double R2 = R * R;
         // float32 beta is accurate to ~1e-6; the slab keeps a much wider margin
         const double slab_eps = 1e-4 * fmax(1.0, R);
         const double ylo = (double)sc.origin[1] + cy * h, yhi = ylo + h;
         const double zlo = (double)sc.origin[2] + cz * h, zhi = zlo + h;
-        int x0 = 0x7fffffff, x1 = -1;
 #pragma unroll
         for (int g = 0; g < kMaxGroup; ++g) {
             if (g >= ng) break;
+            if ((g & 3) != q) continue;  // wave q takes images q and q + 4
             const double py = gi[g].py, pz = gi[g].pz, px = gi[g].px;
             if (!(py == py) || !(pz == pz) || !(px == px)) continue;  // invalid image
             const double dy = fmax(0.0, fmax(ylo - py, py - yhi));
             const double dz = fmax(0.0, fmax(zlo - pz, pz - zhi));
             const double d2 = dy * dy + dz * dz;
             if (d2 > R2) continue;
-            double xa = px - sqrt(R2 - d2), xb = px + sqrt(R2 - d2);
+            const double half_chord = sqrt(R2 - d2);
+            double xa = px - half_chord, xb = px + half_chord;
             // slab beta_lo < n.(x - p) <= beta_hi over the row's y-z box
-            {
-                const double nx = gi[g].nx, ny = gi[g].ny, nz = gi[g].nz;
-                const double ty0 = ny * (ylo - py), ty1 = ny * (yhi - py);
-                const double tz0 = nz * (zlo - pz), tz1 = nz * (zhi - pz);
-                const double tmin = fmin(ty0, ty1) + fmin(tz0, tz1);
-                const double tmax = fmax(ty0, ty1) + fmax(tz0, tz1);
-                const double A = (double)p.beta_lo - slab_eps - tmax;  // bound of nx (x - px)
-                const double Bv = (double)p.beta_hi + slab_eps - tmin;
-                if (fabs(nx) > 1e-12) {
-                    double s0 = A / nx, s1 = Bv / nx;
-                    if (s0 > s1) { const double t = s0; s0 = s1; s1 = t; }
-                    xa = fmax(xa, px + s0);
-                    xb = fmin(xb, px + s1);
-                } else if (A > 0.0 || Bv < 0.0) {
-                    continue;
-                }
-                if (!(xa <= xb)) continue;
+            const double nx = gi[g].nx, ny = gi[g].ny, nz = gi[g].nz;
+            const double ty0 = ny * (ylo - py), ty1 = ny * (yhi - py);
+            const double tz0 = nz * (zlo - pz), tz1 = nz * (zhi - pz);
+            const double tmin = fmin(ty0, ty1) + fmin(tz0, tz1);
+            const double tmax = fmax(ty0, ty1) + fmax(tz0, tz1);
+            const double A = (double)p.beta_lo - slab_eps - tmax;  // bound of nx (x - px)
+            const double Bv = (double)p.beta_hi + slab_eps - tmin;
+            if (fabs(nx) > 1e-12) {
+                const double inv_nx = 1.0 / nx;
+                double s0 = A * inv_nx, s1 = Bv * inv_nx;
+                if (s0 > s1) { const double tt = s0; s0 = s1; s1 = tt; }
+                xa = fmax(xa, px + s0);
+                xb = fmin(xb, px + s1);
+            } else if (A > 0.0 || Bv < 0.0) {
+                continue;
             }
-            const double fa = floor((xa - (double)sc.origin[0]) / h);
-            const double fb = floor((xb - (double)sc.origin[0]) / h);
+            if (!(xa <= xb)) continue;
+            const double fa = floor((xa - (double)sc.origin[0]) * inv_h);
+            const double fb = floor((xb - (double)sc.origin[0]) * inv_h);
             int a = (int)fmax(-1.0, fmin(fa, 1.0e9));
             int b = (int)fmax(-1.0, fmin(fb, 1.0e9));
             int gx, gy, gz;
             cell_xyz(gcell[g], sc.dims, gx, gy, gz);
-            a = max(a, gx - p.reach);
-            b = min(b, gx + p.reach);
-            x0 = min(x0, a);
-            x1 = max(x1, b);
+            x0 = min(x0, max(a, gx - p.reach));
+            x1 = max(x1, min(b, gx + p.reach));
+        }
+    }
+    part_x0[t] = x0;
+    part_x1[t] = x1;
+}
+
+__device__ __forceinline__ void rows_emit(const SceneView& sc, const int lo[3], const int hi[3],
+                                          bool any_valid, const int* part_x0,
+                                          const int* part_x1, int* row_start, int* row_pref,
+                                          int* n_rows_out) {
+    const int lane = threadIdx.x;  // caller guarantees threadIdx.x < 64
+    const int ny_rows = any_valid ? hi[1] - lo[1] + 1 : 0;
+    const int nz_rows = any_valid ? hi[2] - lo[2] + 1 : 0;
+    const int n_rows = ny_rows * nz_rows;
+    int len = 0, start = 0;
+    if (lane < n_rows) {
+        int x0 = part_x0[lane], x1 = part_x1[lane];
+#pragma unroll
+        for (int q = 1; q < kBlock / 64; ++q) {
+            x0 = min(x0, part_x0[lane + 64 * q]);
+            x1 = max(x1, part_x1[lane + 64 * q]);
         }
         x0 = max(x0, 0);
         x1 = min(x1, sc.dims[0] - 1);
         if (x1 >= x0) {
+            const int cy = lo[1] + lane % ny_rows;
+            const int cz = lo[2] + lane / ny_rows;
             const int base = (cz * sc.dims[1] + cy) * sc.dims[0];
             start = sc.cell_start[base + x0];
             len = sc.cell_start[base + x1 + 1] - start;
@@ -327,8 +415,8 @@ __device__ __forceinline__ void build_rows(const SceneView& sc, const SpinParams
     int incl = len;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += t;
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
     }
     if (lane < n_rows) {
         row_start[lane] = start;
@@ -356,13 +444,14 @@ __device__ __forceinline__ void run_group_pass(int mode, const SceneView& sc, co
 
 }  // namespace
 
-__global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_spin(LaunchDesc d) {
     extern __shared__ uint4 acc_lds[];
     uint32_t* acc = reinterpret_cast<uint32_t*>(acc_lds);
     __shared__ ImgInfo s_info[kInfo];
     __shared__ int s_row_start[kMaxRows];
     __shared__ int s_row_pref[kMaxRows + 1];
     __shared__ int s_n_rows;
+    __shared__ int s_part_x0[kBlock], s_part_x1[kBlock];
     __shared__ uint32_t s_cnt[kMaxGroup];
     __shared__ int s_step;
     __shared__ float2 s_q_ba[kBlock / 64][kQueue];
@@ -397,12 +486,12 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
         const int c_start = rfl(ch.start);
         const int c_end = rfl(ch.end);
         const Item& it = d.items ? d.items[item_id] : d.single;
-        const SceneView sc = it.scene;
-        const SpinParams p = it.p;
+        const SceneView sc = uniform(it.scene);
+        const SpinParams p = uniform(it.p);
         const int W = p.W;
         const int w2 = W * W;
         // images per group: keep the LDS footprint of the launch (group x max_w2)
-        const int G_item = min(kMaxGroup, max(1, (d.group * d.max_w2) / w2));
+        const int G_item = min(kMaxGroup, max(1, (d.group * (d.max_w2 + 4)) / (w2 + 4)));
         // cells a group may span per axis beyond the first, and rows available
         const int span_lim = max(0, min(1, 7 - 2 * p.reach));
 
@@ -475,22 +564,18 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
                     rhi[a] = any_valid ? min(hi[a] + p.reach, sc.dims[a] - 1) : -1;
                 }
 
-                // ---- zero accumulators + counts; wave 0 builds the rows ----
+                // ---- zero accumulators + counts; cull the rows (all waves) ----
                 {
                     uint4* a4 = reinterpret_cast<uint4*>(acc);
-                    const int n4 = (ng * w2 + 3) / 4;
+                    const int n4 = (ng * (w2 + 4) + 3) / 4;
                     for (int i = tid; i < n4; i += kBlock) a4[i] = make_uint4(0, 0, 0, 0);
                     if (tid < kMaxGroup) s_cnt[tid] = 0;
                 }
-                if (tid < 64) {
-                    if (any_valid) {
-                        build_rows(sc, p, gi, gcell, ng, rlo, rhi, s_row_start, s_row_pref,
-                                   &s_n_rows);
-                    } else if (tid == 0) {
-                        s_row_pref[0] = 0;
-                        s_n_rows = 0;
-                    }
-                }
+                rows_cull(sc, p, gi, gcell, ng, rlo, rhi, s_part_x0, s_part_x1);
+                __syncthreads();
+                if (tid < 64)
+                    rows_emit(sc, rlo, rhi, any_valid, s_part_x0, s_part_x1, s_row_start,
+                              s_row_pref, &s_n_rows);
                 __syncthreads();
                 const int n_rows = rfl(s_n_rows);
 
@@ -527,7 +612,7 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
                     const bool valid = out_code >= 0;
                     const int out = valid ? out_code : -1 - out_code;
                     float* img = it.images + (size_t)out * w2;
-                    const uint32_t* a = acc + g * w2;
+                    const uint32_t* a = acc + g * (w2 + 4);
                     if ((w2 & 3) == 0 && ((reinterpret_cast<uintptr_t>(img) & 15) == 0)) {
                         for (int i = tid; i < w2 / 4; i += kBlock) {
                             const uint4 q = reinterpret_cast<const uint4*>(a)[i];
@@ -601,7 +686,7 @@ __global__ void __launch_bounds__(kBlock) k_spin(LaunchDesc d) {
 
 size_t spin_lds_bytes(int max_w2, int group) {
     const int slots = group < 2 ? 2 : group;  // room for one 64-bit image
-    return (size_t)slots * (size_t)max_w2 * sizeof(uint32_t) + 16;
+    return (size_t)slots * (size_t)(max_w2 + 4) * sizeof(uint32_t) + 16;
 }
 
 int spin_max_wg_per_cu(int max_w2, int group) {

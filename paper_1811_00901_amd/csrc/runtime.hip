@@ -386,11 +386,13 @@ si_status si_chunk_table(int32_t kind, int64_t N, int32_t P, int32_t min_chunk,
 // --------------------------------------------------------------- generate --
 namespace si {
 
-int default_group(int W) { return W >= 64 ? 2 : 8; }
+// Images per candidate pass: 4 keeps the per-image values of a group in
+// scalar registers; W = 64 images are 16 KB each, so two per pass.
+int default_group(int W) { return W >= 64 ? 2 : 4; }
 
 // Largest group <= the requested one whose accumulators fit the LDS limit.
 int fit_group(DeviceState* st, int group, int max_w2) {
-    const size_t static_lds = 4096;  // kernel's own shared arrays, rounded up
+    const size_t static_lds = 20480;  // kernel's own shared arrays (~17 KB), rounded up
     while (group > 1 && spin_lds_bytes(max_w2, group) + static_lds > (size_t)st->max_lds) --group;
     return group;
 }

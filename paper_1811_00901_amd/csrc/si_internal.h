@@ -25,7 +25,8 @@ si_status hip_fail(hipError_t e, const char* what);
     } while (0)
 
 // ----------------------------------------------------------------- scene --
-// Grid cells per support radius: cell edge h = R_max (1 + 2e-5) / kSub.
+// Grid cells per support radius: cell edge h = R_max (1 + 2e-5) / kSub (odd,
+// so that the 3 x 3 x 3 coarse cells of the cost features are centred).
 constexpr int kSub = 3;
 // Cap on the number of grid cells of one scene; a larger box gets bigger cells.
 constexpr int64_t kMaxCells = int64_t(1) << 25;

@@ -77,13 +77,14 @@ def test_features_hand_pattern():
     Shells 1 / 5 / 4 / 5, total 15, m = (1, -1, -8)/15,
     sum o (d.n)^2 = 3 + 5 = 8, sum o |d - (d.n)n|^2 = 2 + 8 + 10 = 20."""
     R = 0.3
-    h = R * (1 + 2e-5) / 3
+    S = mlp.SUB
+    h = R * (1 + 2e-5) / S
     c = np.array([20, 20, 20])            # p's cell; an anchor at the origin fixes the grid
     pts, nrm = [[0.0, 0.0, 0.0]], [[0, 0, 1]]
 
     def put(d, k):
         for _ in range(k):
-            pts.append(list((c + 3 * np.array(d) + 0.5) * h))
+            pts.append(list((c + S * np.array(d) + 0.5) * h))
             nrm.append([0, 0, 1])
 
     put((0, 0, 0), 1)
@@ -96,5 +97,5 @@ def test_features_hand_pattern():
     Rs = 0.25
     f, _ = mlp.features(xyz, nn, [1], R, Rs)
     exp = [math.log1p(1), math.log1p(5), math.log1p(4), math.log1p(5),
-           1 / 15, -1 / 15, -8 / 15, -8 / 15, 8 / 15, 20 / 15, math.log1p(15), Rs / (3 * h)]
+           1 / 15, -1 / 15, -8 / 15, -8 / 15, 8 / 15, 20 / 15, math.log1p(15), Rs / (S * h)]
     np.testing.assert_allclose(f[0], exp, rtol=1e-12, atol=1e-12)
