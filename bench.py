@@ -26,6 +26,7 @@ Also reported (outside the timed steps):
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
                     [--no-schedules] [--no-batch] [--no-extent]
+                    [--copy-calibration BYTES]
 """
 from __future__ import annotations
 
@@ -60,6 +61,34 @@ ATOMICS_PER_SUPPORT_PAIR = 4
 PEAK_VALU_OPS = 256 * 64 * 2.4e9
 
 
+# HBM bytes per spin-kernel launch on the main workload, from two counter runs
+# (FETCH_SIZE, WRITE_SIZE) calibrated on a plain copy; recorded with a hash of
+# the kernel sources it was measured on and reported only while they match.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_spin_clustered2m_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1811_00901_amd", "csrc", f)
+                  for f in ("k_spin.hip", "si_internal.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +101,9 @@ def parse():
     ap.add_argument("--no-extent", action="store_true",
                     help="stop after the timed steps (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="after the timed steps, copy BYTES device-to-device once, so that a "
+                         "counter run sees a plain copy of known size beside the spin kernel")
     return ap.parse_args()
 
 
@@ -233,6 +265,15 @@ def main():
     images_per_s = N / (ms_step * 1e-3)
     log(f"[bench] step {ms_step:.2f} ms (generation {gen_ms:.2f} ms, spin kernel {kernel_ms:.2f} ms), "
         f"{pairs} in-support pairs")
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {4 * n} bytes for counter calibration")
+        del src, dst
     if args.no_extent:
         print(json.dumps({"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
                           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -258,7 +299,7 @@ def main():
         "peak": PEAK_VALU_OPS / 1e12,
         "unit": "TOP/s",
         "frac": achieved / PEAK_VALU_OPS,
-        "traffic": None,
+        "traffic": measured_traffic(),
         "kernel": "k_spin",
         "kernel_ms": kernel_ms,
         "in_extent_pairs": extent_pairs,
