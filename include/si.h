@@ -166,8 +166,9 @@ typedef struct si_scene_info {
 /*
  * Build a scene: the list of oriented points OP (Section 2.1) in the layout
  * the kernels read -- a uniform grid of cells of edge h >= R / 3 (three cells
- * per support radius), points sorted by cell into 32-byte float4 position and
- * normal records.  The grid is conservative for every pair with
+ * per support radius), points sorted by cell, and within a cell by the quarter
+ * of the cell their x falls in, into 32-byte float4 position and normal
+ * records.  The grid is conservative for every pair with
  * |x - p| <= max_support_radius; max_support_radius <= 0 builds a single
  * cell (brute force over all M points, the paper's O(N M) loop).
  *   points_xyz, normals_xyz  device, M x 3 float32, row-major; read only

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* _
     // point counts of the 3 x 3 x 3 coarse cells around p: coarse offset d
     // covers fine cells c + kSub d - half .. c + kSub d + half on each axis;
     // each fine row (y, z) contributes to three coarse cells through four
-    // cell_start boundaries along x
+    // cell boundaries along x (every kSubX-th entry of sub_start)
     int occ[3][3][3] = {};
     const int xb[4] = {c[0] - kSub - half, c[0] - half, c[0] + half + 1, c[0] + kSub + half + 1};
     int xc[4];
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* _
             const int row = (z * sc.dims[1] + y) * sc.dims[0];
             int e[4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) e[b] = sc.cell_start[row + xc[b]];
+            for (int b = 0; b < 4; ++b) e[b] = sc.sub_start[(row + xc[b]) * kSubX];
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) occ[dz][dy][dx] += e[dx + 1] - e[dx];
         }

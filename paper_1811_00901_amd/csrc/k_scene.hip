@@ -81,27 +81,33 @@ struct GridDesc {
     int32_t dims[3];
 };
 
-__device__ __forceinline__ int cell_of_point(const GridDesc& g, float x, float y, float z) {
+// Sort key of a point: cell * kSubX + the quarter of the cell along x,
+// floor(kSubX t) - kSubX floor(t) for t = (x - origin) / h.
+__device__ __forceinline__ int key_of_point(const GridDesc& g, float x, float y, float z) {
     const float v[3] = {x, y, z};
     int c[3];
+    int sub = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double t = floor(((double)v[a] - g.origin[a]) / g.h);
+        const double u = ((double)v[a] - g.origin[a]) / g.h;
+        const double t = floor(u);
         // non-finite coordinates (never in support of anything) go to cell 0
-        c[a] = (t >= 0.0 && t < (double)g.dims[a]) ? (int)t : 0;
+        const bool ok = t >= 0.0 && t < (double)g.dims[a];
+        c[a] = ok ? (int)t : 0;
+        if (a == 0 && ok) sub = min(max((int)(floor(u * kSubX) - t * kSubX), 0), kSubX - 1);
     }
-    return (c[2] * g.dims[1] + c[1]) * g.dims[0] + c[0];
+    return ((c[2] * g.dims[1] + c[1]) * g.dims[0] + c[0]) * kSubX + sub;
 }
 
 __global__ void __launch_bounds__(256) k_bin_points(const float* __restrict__ xyz, int64_t M,
-                                                    GridDesc g, int32_t* __restrict__ cell_of,
+                                                    GridDesc g, int32_t* __restrict__ key_of,
                                                     int32_t* __restrict__ rank,
                                                     int32_t* __restrict__ counts) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= M) return;
-    const int c = cell_of_point(g, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
-    cell_of[i] = c;
-    rank[i] = atomicAdd(counts + c, 1);
+    const int k = key_of_point(g, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+    key_of[i] = k;
+    rank[i] = atomicAdd(counts + k, 1);
 }
 
 // Tile sums of the input.
@@ -188,16 +194,16 @@ __global__ void __launch_bounds__(256) k_scan_apply(const T* __restrict__ in, in
 
 __global__ void __launch_bounds__(256) k_scatter(const float* __restrict__ xyz,
                                                  const float* __restrict__ nrm, int64_t M,
-                                                 const int32_t* __restrict__ cell_of,
+                                                 const int32_t* __restrict__ key_of,
                                                  const int32_t* __restrict__ rank,
-                                                 const int32_t* __restrict__ cell_start,
+                                                 const int32_t* __restrict__ sub_start,
                                                  float4* __restrict__ pos, float4* __restrict__ nr,
                                                  int32_t* __restrict__ inv) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= M) return;
-    const int c = cell_of[i];
-    const int s = cell_start[c] + rank[i];
-    pos[s] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], __int_as_float(c));
+    const int k = key_of[i];
+    const int s = sub_start[k] + rank[i];
+    pos[s] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], __int_as_float(k / kSubX));
     nr[s] = make_float4(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2], __int_as_float((int)i));
     inv[i] = s;
 }
@@ -320,7 +326,7 @@ hipError_t launch_bbox(const float* xyz, int64_t M, float* out6, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32_t* cell_of,
+hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32_t* key_of,
                              int32_t* rank, int32_t* counts, hipStream_t s) {
     GridDesc g;
     for (int a = 0; a < 3; ++a) {
@@ -329,7 +335,7 @@ hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32
     }
     g.h = sc.h;
     hipLaunchKernelGGL(k_bin_points, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, xyz, M,
-                       g, cell_of, rank, counts);
+                       g, key_of, rank, counts);
     return hipGetLastError();
 }
 
@@ -358,11 +364,11 @@ hipError_t launch_scan64(const int64_t* in, int64_t* out, int64_t n, int64_t* tm
     return scan_impl<int64_t>(in, out, n, tmp, s);
 }
 
-hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* cell_of,
-                          const int32_t* rank, const int32_t* cell_start, Scene& sc,
+hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* key_of,
+                          const int32_t* rank, const int32_t* sub_start, Scene& sc,
                           hipStream_t s) {
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, xyz, nrm,
-                       M, cell_of, rank, cell_start, sc.pos, sc.nrm, sc.inv);
+                       M, key_of, rank, sub_start, sc.pos, sc.nrm, sc.inv);
     return hipGetLastError();
 }
 

@@ -83,7 +83,7 @@ __device__ __forceinline__ SceneView uniform(const SceneView& a) {
     SceneView b;
     b.pos = rfl(a.pos);
     b.nrm = rfl(a.nrm);
-    b.cell_start = rfl(a.cell_start);
+    b.sub_start = rfl(a.sub_start);
     b.inv = rfl(a.inv);
     for (int k = 0; k < 3; ++k) {
         b.dims[k] = rfl(a.dims[k]);
@@ -312,14 +312,15 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 // Rows (z, y) of grid cells that may hold candidates of the group, each with
-// the contiguous x-run of cells that meets the support sphere and the beta
-// slab of some image of the group (double precision; radius inflated by 1e-5
-// relative and slab by 1e-4 R, far above the rounding of the reciprocals
-// used here).  Two phases, both called by every thread of the block:
-// rows_cull: thread t bounds row t % 64 against images t / 64 and t / 64 + 4
-// into part_x0/part_x1[t]; rows_emit (after a barrier): lane r of wave 0
-// merges the four partial runs of row r, looks the run up in cell_start and
-// writes row_start / row_pref (exclusive prefix of run lengths) / n_rows.
+// the contiguous run of points, in quarter-cell steps along x (the sort key
+// of the scene), that meets the support sphere and the beta slab of some
+// image of the group (double precision; radius inflated by 1e-5 relative and
+// slab by 1e-4 R, far above the rounding of the reciprocals used here).  Two
+// phases, both called by every thread of the block: rows_cull: thread t
+// bounds row t % 64 against images t / 64 and t / 64 + 4 into the key range
+// part_x0/part_x1[t]; rows_emit (after a barrier): lane r of wave 0 merges
+// the four partial ranges of row r, looks them up in sub_start and writes
+// row_start / row_pref (exclusive prefix of run lengths) / n_rows.
 __device__ __forceinline__ void rows_cull(const SceneView& sc, const SpinParams& p,
                                           const GroupImg* gi, const int* gcell, int ng,
                                           const int lo[3], const int hi[3], int* part_x0,
@@ -371,14 +372,21 @@ __device__ __forceinline__ void rows_cull(const SceneView& sc, const SpinParams&
                 continue;
             }
             if (!(xa <= xb)) continue;
-            const double fa = floor((xa - (double)sc.origin[0]) * inv_h);
-            const double fb = floor((xb - (double)sc.origin[0]) * inv_h);
-            int a = (int)fmax(-1.0, fmin(fa, 1.0e9));
-            int b = (int)fmax(-1.0, fmin(fb, 1.0e9));
+            // keys along the row: kSubX per cell
+            const double fa = floor((xa - (double)sc.origin[0]) * (inv_h * kSubX));
+            const double fb = floor((xb - (double)sc.origin[0]) * (inv_h * kSubX));
+            const int a = (int)fmax(-1.0, fmin(fa, 1.0e9));
+            const int b = (int)fmax(-1.0, fmin(fb, 1.0e9));
             int gx, gy, gz;
             cell_xyz(gcell[g], sc.dims, gx, gy, gz);
-            x0 = min(x0, max(a, gx - p.reach));
-            x1 = max(x1, min(b, gx + p.reach));
+            if (p.reach == 0) {
+                // single-cell scene: the paper's loop over all M points
+                x0 = 0;
+                x1 = kSubX - 1;
+                continue;
+            }
+            x0 = min(x0, max(a, (gx - p.reach) * kSubX));
+            x1 = max(x1, min(b, (gx + p.reach) * kSubX + kSubX - 1));
         }
     }
     part_x0[t] = x0;
@@ -402,13 +410,13 @@ __device__ __forceinline__ void rows_emit(const SceneView& sc, const int lo[3], 
             x1 = max(x1, part_x1[lane + 64 * q]);
         }
         x0 = max(x0, 0);
-        x1 = min(x1, sc.dims[0] - 1);
+        x1 = min(x1, sc.dims[0] * kSubX - 1);
         if (x1 >= x0) {
             const int cy = lo[1] + lane % ny_rows;
             const int cz = lo[2] + lane / ny_rows;
-            const int base = (cz * sc.dims[1] + cy) * sc.dims[0];
-            start = sc.cell_start[base + x0];
-            len = sc.cell_start[base + x1 + 1] - start;
+            const int base = (cz * sc.dims[1] + cy) * sc.dims[0] * kSubX;
+            start = sc.sub_start[base + x0];
+            len = sc.sub_start[base + x1 + 1] - start;
         }
     }
     // inclusive scan of len over the wave

@@ -212,7 +212,7 @@ SceneView view_of(const Scene& s) {
     SceneView v;
     v.pos = s.pos;
     v.nrm = s.nrm;
-    v.cell_start = s.cell_start;
+    v.sub_start = s.sub_start;
     v.inv = s.inv;
     for (int a = 0; a < 3; ++a) {
         v.dims[a] = s.dims[a];
@@ -227,10 +227,10 @@ static void free_scene_mem(Scene* s) {
     if (!s) return;
     (void)hipFree(s->pos);
     (void)hipFree(s->nrm);
-    (void)hipFree(s->cell_start);
+    (void)hipFree(s->sub_start);
     (void)hipFree(s->inv);
     s->pos = s->nrm = nullptr;
-    s->cell_start = s->inv = nullptr;
+    s->sub_start = s->inv = nullptr;
 }
 
 }  // namespace si
@@ -302,10 +302,11 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     }
 
     // ---- bin, scan, scatter ----
-    int32_t *cell_of = nullptr, *rank = nullptr, *counts = nullptr, *tmp = nullptr;
-    const int64_t ntmp = scan_tmp_elems(sc->n_cells);
+    int32_t *key_of = nullptr, *rank = nullptr, *counts = nullptr, *tmp = nullptr;
+    const int64_t n_keys = sc->n_cells * kSubX;
+    const int64_t ntmp = scan_tmp_elems(n_keys);
     auto cleanup = [&]() {
-        (void)hipFree(cell_of);
+        (void)hipFree(key_of);
         (void)hipFree(rank);
         (void)hipFree(counts);
         (void)hipFree(tmp);
@@ -313,16 +314,16 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     e = hipMalloc(&sc->pos, sizeof(float4) * M);
     if (e == hipSuccess) e = hipMalloc(&sc->nrm, sizeof(float4) * M);
     if (e == hipSuccess) e = hipMalloc(&sc->inv, sizeof(int32_t) * M);
-    if (e == hipSuccess) e = hipMalloc(&sc->cell_start, sizeof(int32_t) * (sc->n_cells + 1));
-    if (e == hipSuccess) e = hipMalloc(&cell_of, sizeof(int32_t) * M);
+    if (e == hipSuccess) e = hipMalloc(&sc->sub_start, sizeof(int32_t) * (n_keys + 1));
+    if (e == hipSuccess) e = hipMalloc(&key_of, sizeof(int32_t) * M);
     if (e == hipSuccess) e = hipMalloc(&rank, sizeof(int32_t) * M);
-    if (e == hipSuccess) e = hipMalloc(&counts, sizeof(int32_t) * sc->n_cells);
+    if (e == hipSuccess) e = hipMalloc(&counts, sizeof(int32_t) * n_keys);
     if (e == hipSuccess) e = hipMalloc(&tmp, sizeof(int32_t) * ntmp);
-    if (e == hipSuccess) e = launch_fill(counts, sc->n_cells, 0, s);
-    if (e == hipSuccess) e = launch_bin_points(points_xyz, M, *sc, cell_of, rank, counts, s);
-    if (e == hipSuccess) e = launch_scan(counts, sc->cell_start, sc->n_cells, tmp, ntmp, s);
+    if (e == hipSuccess) e = launch_fill(counts, n_keys, 0, s);
+    if (e == hipSuccess) e = launch_bin_points(points_xyz, M, *sc, key_of, rank, counts, s);
+    if (e == hipSuccess) e = launch_scan(counts, sc->sub_start, n_keys, tmp, ntmp, s);
     if (e == hipSuccess)
-        e = launch_scatter(points_xyz, normals_xyz, M, cell_of, rank, sc->cell_start, *sc, s);
+        e = launch_scatter(points_xyz, normals_xyz, M, key_of, rank, sc->sub_start, *sc, s);
     // temporaries are released once the stream has used them
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     cleanup();

@@ -28,6 +28,10 @@ si_status hip_fail(hipError_t e, const char* what);
 // Grid cells per support radius: cell edge h = R_max (1 + 2e-5) / kSub (odd,
 // so that the 3 x 3 x 3 coarse cells of the cost features are centred).
 constexpr int kSub = 3;
+// Points of a cell are sorted by the quarter of the cell their x falls in:
+// key = cell * kSubX + floor(kSubX * frac(x / h)), so that a row's candidate
+// run can be cut at quarter-cell resolution.
+constexpr int kSubX = 4;
 // Cap on the number of grid cells of one scene; a larger box gets bigger cells.
 constexpr int64_t kMaxCells = int64_t(1) << 25;
 
@@ -35,7 +39,7 @@ struct Scene {
     int64_t M = 0;
     float4* pos = nullptr;       // sorted by cell: (x, y, z, bits(cell id))
     float4* nrm = nullptr;       // sorted by cell: (nx, ny, nz, bits(original index))
-    int32_t* cell_start = nullptr;  // n_cells + 1
+    int32_t* sub_start = nullptr;   // n_cells * kSubX + 1: first point of each key
     int32_t* inv = nullptr;      // original index -> sorted position
     int32_t dims[3] = {1, 1, 1};
     float origin[3] = {0, 0, 0};
@@ -63,7 +67,7 @@ struct SpinParams {
 struct SceneView {
     const float4* pos;
     const float4* nrm;
-    const int32_t* cell_start;
+    const int32_t* sub_start;
     const int32_t* inv;
     int32_t dims[3];
     float origin[3];
@@ -118,7 +122,9 @@ int spin_max_wg_per_cu(int max_w2, int group);
 
 // Scene-building kernels.
 hipError_t launch_bbox(const float* xyz, int64_t M, float* out6, hipStream_t s);
-hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32_t* cell_of,
+// key_of[i] = cell * kSubX + x-quarter of point i; counts (n_cells * kSubX)
+// are incremented, rank[i] = the point's rank within its key.
+hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32_t* key_of,
                              int32_t* rank, int32_t* counts, hipStream_t s);
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, int64_t tmp_n,
                        hipStream_t s);
@@ -141,8 +147,8 @@ hipError_t launch_cell_order_multi(const Item* items, const int64_t* item_off,
                                    int64_t total_cells, int32_t* key, int32_t* rank,
                                    int32_t* counts, int32_t* starts, int32_t* tmp, int32_t* perm,
                                    hipStream_t s);
-hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* cell_of,
-                          const int32_t* rank, const int32_t* cell_start, Scene& sc,
+hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* key_of,
+                          const int32_t* rank, const int32_t* sub_start, Scene& sc,
                           hipStream_t s);
 
 // ------------------------------------------------------------ host state --
