@@ -107,12 +107,33 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def timed(torch, fn, reps, warm=1):
-    """Median wall time (ms) of fn() between device synchronisations."""
+WARM, REPS = 3, 15   # warm-ups and timed repetitions of every comparison
+
+
+def spread(ts):
+    """Median, quartiles and extremes of a list of times (ms)."""
+    q = np.percentile(np.asarray(ts, dtype=np.float64), [0, 25, 50, 75, 100])
+    return {"median": float(q[2]), "q1": float(q[1]), "q3": float(q[3]),
+            "min": float(q[0]), "max": float(q[4])}
+
+
+def timed(torch, fn, reps=REPS, warm=WARM):
+    """Wall times (ms) of fn() between device synchronisations: spread()."""
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
@@ -122,7 +143,7 @@ def timed(torch, fn, reps, warm=1):
         fn()
         torch.cuda.synchronize()
         ts.append((time.perf_counter() - t) * 1e3)
-    return float(np.median(ts))
+    return spread(ts)
 
 
 def train_cost_model(torch, si, sg, main):
@@ -159,19 +180,30 @@ def train_cost_model(torch, si, sg, main):
     return model, info
 
 
-def batched(torch, si, sg):
-    """256 uneven scenes: per-scene loop of si_generate vs one autotuned graph launch."""
+def batched(torch, si, sg, model):
+    """256 uneven scenes: a loop of si_generate calls against one batched
+    graph launch (FAC with default and autotuned parameters, and LEARNED with
+    the trained model on the tuned parameters); scene builds timed apart."""
     specs = sg.batch_specs(256)
-    items = []
+    raw, items = [], []
     for seed, M, W in specs:
         xyz, nrm = sg.batch_scene(seed, M)
         params = si.Params(W, 0.02, float(np.float32(math.pi / 3)))
-        scene = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(),
-                                  si.si_support_radius(params))
+        raw.append((torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(),
+                    si.si_support_radius(params)))
         idx = torch.arange(M, dtype=torch.int32, device="cuda")
         img = torch.empty((M, W, W), dtype=torch.float32, device="cuda")
         cnt = torch.empty((M,), dtype=torch.int32, device="cuda")
-        items.append((scene, idx, params, img, cnt))
+        items.append([None, idx, params, img, cnt])
+
+    def build():
+        scenes = [si.si_build_scene(x, n, r) for x, n, r in raw]
+        for it, sc in zip(items, scenes):
+            if it[0] is not None:
+                it[0].free()
+            it[0] = sc
+
+    build_ms = timed(torch, build, reps=5, warm=1)
     total_img = sum(int(it[1].shape[0]) for it in items)
     fac = si.Sched("fac")
 
@@ -179,24 +211,39 @@ def batched(torch, si, sg):
         for scene, idx, params, img, cnt in items:
             si.si_generate(scene, idx, params, fac, img, cnt)
 
-    loop_ms = timed(torch, loop, 3)
-    ref = [(float(img.double().sum()), int(cnt.to(torch.int64).sum())) for _, _, _, img, cnt in items]
-    pairs = sum(r[1] for r in ref)
-    tuned, tune_ms = si.si_autotune(items, "fac", use_graph=True, max_trials=12)
-    graph_ms = timed(torch, lambda: si.si_generate_batched(items, tuned, use_graph=True), 5)
-    default_ms = timed(torch, lambda: si.si_generate_batched(items, fac, use_graph=True), 3)
-    same = all((float(img.double().sum()), int(cnt.to(torch.int64).sum())) == r
+    loop_ms = timed(torch, loop)
+    ref = [(img.clone(), cnt.clone()) for _, _, _, img, cnt in items]
+    pairs = sum(int(c.to(torch.int64).sum()) for _, c in ref)
+    tuned, _ = si.si_autotune(items, "fac", use_graph=True, max_trials=12)
+    graph_ms = timed(torch, lambda: si.si_generate_batched(items, tuned, use_graph=True))
+    default_ms = timed(torch, lambda: si.si_generate_batched(items, fac, use_graph=True))
+    same = all(torch.equal(img, r[0]) and torch.equal(cnt, r[1])
                for (_, _, _, img, cnt), r in zip(items, ref))
+    learned = None
+    if model is not None:
+        ls = si.Sched("learned", tuned.num_workgroups, tuned.min_chunk, tuned.fac_divisor, model,
+                      True, tuned.group)
+        learned_ms = timed(torch, lambda: si.si_generate_batched(items, ls, use_graph=True))
+        st = si.si_generate_batched(items, ls, use_graph=True, stats=True)
+        learned = {"ms": learned_ms, "sched_used": list(si.SCHED)[st["sched_used"]],
+                   "n_chunks": st["n_chunks"],
+                   "identical": all(torch.equal(img, r[0]) and torch.equal(cnt, r[1])
+                                    for (_, _, _, img, cnt), r in zip(items, ref)),
+                   "speedup_vs_fac_tuned": graph_ms["median"] / learned_ms["median"]}
+    best = min(graph_ms["median"], learned["ms"]["median"] if learned else float("inf"))
     out = {"workload": "256 primitive scenes, M log-uniform in [1k, 200k], W in {16,32,64}, "
                        "bin 0.02, 60 deg, all points oriented",
            "points": int(sum(s[1] for s in specs)), "images": total_img, "in_support_pairs": pairs,
-           "loop_ms": loop_ms, "graph_default_ms": default_ms, "graph_tuned_ms": graph_ms,
-           "speedup_vs_loop": loop_ms / graph_ms, "pairs_per_s": pairs / (graph_ms * 1e-3),
-           "images_per_s": total_img / (graph_ms * 1e-3), "identical": same,
+           "build_ms": build_ms, "loop_ms": loop_ms, "graph_default_ms": default_ms,
+           "graph_tuned_ms": graph_ms, "graph_learned": learned,
+           "speedup_vs_loop": loop_ms["median"] / graph_ms["median"],
+           "build_plus_generation_ms": build_ms["median"] + best,
+           "pairs_per_s": pairs / (best * 1e-3), "images_per_s": total_img / (best * 1e-3),
+           "identical": same,
            "tuned": {"group": tuned.group, "num_workgroups": tuned.num_workgroups,
                      "fac_divisor": tuned.fac_divisor, "min_chunk": tuned.min_chunk}}
-    for scene, *_ in items:
-        scene.free()
+    for it in items:
+        it[0].free()
     return out
 
 
@@ -322,27 +369,32 @@ def main():
     if not args.no_schedules:
         for kind in ["static", "ss", "gss", "fac", "learned"]:
             sch = si.Sched(kind, model=model if kind == "learned" else None)
-            times, used = [], None
-            for r in range(4):
+            times, used, ok = [], None, True
+            for r in range(WARM + REPS):
+                images.fill_(-1.0)
                 ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
                 ev[0].record(stream)
                 _, _, s2 = si.si_generate(scene, idx, params, sch, images, counts, stats=True)
                 ev[1].record(stream)
                 torch.cuda.synchronize()
                 used = s2["sched_used"]
-                if r:
+                ok = ok and bool(torch.equal(images, ref_img) and torch.equal(counts, ref_cnt))
+                if r >= WARM:
                     times.append((s2["kernel_ms"], ev[0].elapsed_time(ev[1])))
             busy = s2["wg_busy_ns"].astype(np.float64)
-            ok = bool(torch.equal(images, ref_img) and torch.equal(counts, ref_cnt))
-            sched_res[kind] = {"kernel_ms": float(np.median([t[0] for t in times])),
-                               "call_ms": float(np.median([t[1] for t in times])),
+            call = spread([t[1] for t in times])
+            sched_res[kind] = {"kernel_ms": spread([t[0] for t in times]), "call_ms": call,
+                               "pairs_per_s": pairs / (call["median"] * 1e-3),
+                               "images_per_s": N / (call["median"] * 1e-3),
                                "identical": ok, "sched_used": list(si.SCHED)[used],
                                "n_chunks": s2["n_chunks"],
                                "imbalance": float(busy.max() / max(busy.mean(), 1.0))}
-            log(f"[bench] {kind}: {sched_res[kind]}")
-        base = sched_res["static"]["call_ms"]
+            log(f"[bench] {kind}: kernel {sched_res[kind]['kernel_ms']['median']:.2f} ms, "
+                f"call {call['median']:.2f} ms, identical {ok}, "
+                f"imbalance {sched_res[kind]['imbalance']:.3f}")
+        base = sched_res["static"]["call_ms"]["median"]
         for k in sched_res:
-            sched_res[k]["speedup_vs_static"] = base / sched_res[k]["call_ms"]
+            sched_res[k]["speedup_vs_static"] = base / sched_res[k]["call_ms"]["median"]
         si.si_generate(scene, idx, params, fac, images, counts)
     torch.cuda.synchronize()
     del ref_img, ref_cnt
@@ -351,7 +403,7 @@ def main():
     batch = None
     if not args.no_batch:
         log("[bench] batched: 256 scenes")
-        batch = batched(torch, si, sg)
+        batch = batched(torch, si, sg, model)
         log(f"[bench] batched: {batch}")
 
     # ---- FP64 CPU oracle on a bounded sample of the main workload ----
@@ -376,7 +428,7 @@ def main():
             batch_n = int(min(max(threads, len(sample) * max(left, 0.5) / max(el, 1e-3)), 200000))
         log(f"[bench] cpu oracle: {done} images, {threads} threads, {dt:.1f} s")
         cpu = {"value": float(pairs_cpu / dt), "unit": "pairs/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
                "sample": f"{done} seeded-random images of {cfg.name} (brute force over all {M} "
                          f"points each, FP64), {dt:.1f} s",
                "images_per_s": done / dt}

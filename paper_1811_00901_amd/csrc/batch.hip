@@ -36,6 +36,13 @@ struct Flat {
     bool ordered = false;
     int64_t total_N = 0;
     int64_t total_cells = 0;
+    // SI_SCHED_LEARNED: the plan is computed on the device before each launch
+    bool learned = false;
+    const si_cost_model* model = nullptr;
+    float divisor = 0.0f;
+    std::vector<int64_t> unit_off;  // n + 1
+    std::vector<float> f11;         // n
+    int64_t n_units = 0;
 };
 
 // Device memory of one flattened launch (one allocation).
@@ -54,6 +61,7 @@ struct FlatMem {
     int32_t* starts = nullptr;
     int32_t* tmp = nullptr;
     unsigned long long* stats = nullptr;  // 4 + n_wg words
+    LearnedMulti lm;                      // learned schedule only
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -80,6 +88,12 @@ size_t layout(const Flat& f, FlatMem& m, char* base) {
         m.counts = (int32_t*)take(sizeof(int32_t) * f.total_cells);
         m.starts = (int32_t*)take(sizeof(int32_t) * (f.total_cells + 1));
         m.tmp = (int32_t*)take(sizeof(int32_t) * scan_tmp_elems(f.total_cells));
+    }
+    if (f.learned) {
+        LearnedMulti size_only;
+        const int ni = (int)f.items.size();
+        char* lb = take(learned_multi_layout(ni, f.total_N, f.n_units, f.n_wg, size_only, nullptr));
+        if (base) learned_multi_layout(ni, f.total_N, f.n_units, f.n_wg, m.lm, lb);
     }
     m.base = base;
     m.bytes = o;
@@ -136,6 +150,7 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
                                           ": support radius exceeds the scene's max_support_radius");
         p.reach = sc.max_radius > 0.0f ? (int)floor((double)p.radius / sc.h) + 1 : 0;
         if (p.reach > kSub + 1) return fail(SI_E_INVALID, "support radius too large for the grid");
+        f.f11.push_back((float)(R / (kSub * sc.h)));
         Item it;
         memset(&it, 0, sizeof(it));
         it.scene = view_of(sc);
@@ -155,13 +170,36 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
     if (f.total_N >= INT32_MAX || f.total_cells >= INT32_MAX)
         return fail(SI_E_INVALID, "batch too large (2^31 images or cells)");
     if (f.items.empty()) return SI_OK;
-    f.kind = sched->kind == SI_SCHED_LEARNED ? SI_SCHED_FAC : sched->kind;
-    int g = sched->group > 0 ? sched->group : 8;
+    f.kind = sched->kind;
+    if (f.kind == SI_SCHED_LEARNED) {
+        if (!sched->model) {
+            if (!sched->fallback_to_fac)
+                return fail(SI_E_INVALID, "SI_SCHED_LEARNED needs a model (fallback disabled)");
+            f.kind = SI_SCHED_FAC;  // FAC is the fallback of the learned schedule
+        } else {
+            f.learned = true;
+            f.model = sched->model;
+        }
+    }
+    int max_W = 2;
+    while (max_W * max_W < f.max_w2) ++max_W;
+    const int g = sched->group > 0 ? sched->group : default_group(max_W);
     f.group = fit_group(st, g, f.max_w2);
     f.n_wg = sched->num_workgroups > 0 ? sched->num_workgroups
                                        : auto_workgroups(st, f.max_w2, f.group);
     f.ordered = sched->order == SI_ORDER_CELL && f.total_cells > (int64_t)f.items.size();
-    flat_chunks(f, sched->min_chunk, sched->fac_divisor);
+    if (f.learned) {
+        if (f.n_wg > kMaxLearnedP)
+            return fail(SI_E_INVALID, "the learned schedule supports at most " +
+                                          std::to_string(kMaxLearnedP) + " workgroups");
+        std::vector<int64_t> Ns;
+        for (const Item& it : f.items) Ns.push_back(it.N);
+        f.unit_off.resize(f.items.size() + 1);
+        f.n_units = learned_units(Ns.data(), (int)Ns.size(), f.unit_off.data());
+        f.divisor = sched->fac_divisor;
+    } else {
+        flat_chunks(f, sched->min_chunk, sched->fac_divisor);
+    }
     return SI_OK;
 }
 
@@ -169,15 +207,24 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
 si_status upload(const Flat& f, FlatMem& m, hipStream_t s) {
     std::vector<Item> items = f.items;
     for (size_t i = 0; i < items.size(); ++i)
-        items[i].perm = f.ordered ? m.perm + f.item_off[i] : nullptr;
+        items[i].perm = f.learned   ? m.lm.perm + f.item_off[i]
+                        : f.ordered ? m.perm + f.item_off[i]
+                                    : nullptr;
     SI_HIP(hipMemcpyAsync(m.items, items.data(), sizeof(Item) * items.size(),
                           hipMemcpyHostToDevice, s));
     SI_HIP(hipMemcpyAsync(m.item_off, f.item_off.data(), sizeof(int64_t) * f.item_off.size(),
                           hipMemcpyHostToDevice, s));
     SI_HIP(hipMemcpyAsync(m.cell_base, f.cell_base.data(), sizeof(int64_t) * f.cell_base.size(),
                           hipMemcpyHostToDevice, s));
-    SI_HIP(hipMemcpyAsync(m.chunks, f.chunks.data(), sizeof(Chunk) * f.chunks.size(),
-                          hipMemcpyHostToDevice, s));
+    if (!f.chunks.empty())
+        SI_HIP(hipMemcpyAsync(m.chunks, f.chunks.data(), sizeof(Chunk) * f.chunks.size(),
+                              hipMemcpyHostToDevice, s));
+    if (f.learned) {
+        SI_HIP(hipMemcpyAsync(m.lm.unit_off, f.unit_off.data(), sizeof(int64_t) * f.unit_off.size(),
+                              hipMemcpyHostToDevice, s));
+        SI_HIP(hipMemcpyAsync(m.lm.f11, f.f11.data(), sizeof(float) * f.f11.size(),
+                              hipMemcpyHostToDevice, s));
+    }
     if (!f.wg_first.empty())
         SI_HIP(hipMemcpyAsync(m.wg_first, f.wg_first.data(), sizeof(int32_t) * f.wg_first.size(),
                               hipMemcpyHostToDevice, s));
@@ -190,6 +237,11 @@ LaunchDesc desc_of(const Flat& f, const FlatMem& m, uint32_t* counter, bool stat
     d.items = m.items;
     d.chunks = m.chunks;
     d.n_chunks = (int32_t)f.chunks.size();
+    if (f.learned) {
+        d.chunks = m.lm.chunks;
+        d.n_chunks = (int32_t)f.n_units;  // capacity; the count is on the device
+        d.n_chunks_dev = m.lm.n_chunks;
+    }
     d.dynamic = f.kind == SI_SCHED_STATIC ? 0 : 1;
     d.wg_first = f.kind == SI_SCHED_STATIC ? m.wg_first : nullptr;
     d.counter = counter;
@@ -207,17 +259,24 @@ LaunchDesc desc_of(const Flat& f, const FlatMem& m, uint32_t* counter, bool stat
     return d;
 }
 
-// Enqueue ordering + spin kernel (the body of a graph, or a direct launch).
+// Enqueue ordering (+ learned plan) + spin kernel (the body of a graph, or a
+// direct launch).  ev0/ev1 and ub/ue bracket the spin kernel.
 hipError_t enqueue(const Flat& f, const FlatMem& m, const LaunchDesc& d, bool stats,
-                   hipEvent_t ev0, hipEvent_t ev1, hipStream_t s) {
+                   hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ub, hipEvent_t ue, hipStream_t s) {
     hipError_t e = hipSuccess;
     if (stats) e = launch_fill(reinterpret_cast<int32_t*>(m.stats), 2 * (4 + (int64_t)f.n_wg), 0, s);
     if (e == hipSuccess && f.ordered)
         e = launch_cell_order_multi(m.items, m.item_off, m.cell_base, (int)f.items.size(),
                                     f.total_N, f.total_cells, m.key, m.rank, m.counts, m.starts,
                                     m.tmp, m.perm, s);
+    if (e == hipSuccess && f.learned)
+        e = learned_multi_enqueue(f.model, m.lm, m.items, m.item_off, (int)f.items.size(),
+                                  f.ordered ? m.perm : nullptr, f.total_N, f.n_units, f.n_wg,
+                                  f.divisor, s);
     if (e == hipSuccess && ev0) e = hipEventRecord(ev0, s);
+    if (e == hipSuccess && ub) e = hipEventRecord(ub, s);
     if (e == hipSuccess) e = launch_spin(d, f.n_wg, s);
+    if (e == hipSuccess && ue) e = hipEventRecord(ue, s);
     if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     return e;
 }
@@ -236,6 +295,11 @@ si_status read_stats(DeviceState* st, const Flat& f, const FlatMem& m, float ms,
     stats->sched_used = f.kind;
     stats->n_wg = f.n_wg;
     stats->n_chunks = (int32_t)f.chunks.size();
+    if (f.learned) {
+        int32_t nc = 0;
+        SI_HIP(hipMemcpy(&nc, m.lm.n_chunks, sizeof(nc), hipMemcpyDeviceToHost));
+        stats->n_chunks = nc;
+    }
     if (stats->wg_busy_ns) {
         const int n = std::min(stats->wg_busy_cap, f.n_wg);
         for (int i = 0; i < n; ++i)
@@ -284,6 +348,8 @@ std::string graph_key(const si_batch_item* items, int32_t n_items, const si_sche
     put(&sc.fac_divisor, sizeof(sc.fac_divisor));
     put(&sc.group, sizeof(sc.group));
     put(&sc.order, sizeof(sc.order));
+    put(&sc.model, sizeof(sc.model));
+    put(&sc.fallback_to_fac, sizeof(sc.fallback_to_fac));
     const char* lim = getenv("SI_TEST_OVERFLOW_LIMIT");
     k.append(lim ? lim : "-");
     for (int32_t i = 0; i < n_items; ++i) {
@@ -335,7 +401,7 @@ si_status make_graph(DeviceState* st, const si_batch_item* items, int32_t n_item
         LaunchDesc d = desc_of(e->flat, e->mem, e->counter, stats);
         if (err == hipSuccess) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (err == hipSuccess) {
-            hipError_t qe = enqueue(e->flat, e->mem, d, stats, nullptr, nullptr, cs);
+            hipError_t qe = enqueue(e->flat, e->mem, d, stats, nullptr, nullptr, nullptr, nullptr, cs);
             err = hipStreamEndCapture(cs, &graph);
             if (qe != hipSuccess) err = qe;
         }
@@ -395,17 +461,7 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
         }
         if (rc == SI_OK) {
             LaunchDesc d = desc_of(f, m, take_counter(st), stats != nullptr);
-            hipError_t e = hipSuccess;
-            if (stats) e = launch_fill(reinterpret_cast<int32_t*>(m.stats), 2 * (4 + (int64_t)f.n_wg), 0, s);
-            if (e == hipSuccess && f.ordered)
-                e = launch_cell_order_multi(m.items, m.item_off, m.cell_base, (int)f.items.size(),
-                                            f.total_N, f.total_cells, m.key, m.rank, m.counts,
-                                            m.starts, m.tmp, m.perm, s);
-            if (e == hipSuccess && e0) e = hipEventRecord(e0, s);
-            if (e == hipSuccess && ub) e = hipEventRecord(ub, s);
-            if (e == hipSuccess) e = launch_spin(d, f.n_wg, s);
-            if (e == hipSuccess && ue) e = hipEventRecord(ue, s);
-            if (e == hipSuccess && e1) e = hipEventRecord(e1, s);
+            hipError_t e = enqueue(f, m, d, stats != nullptr, e0, e1, ub, ue, s);
             if (e != hipSuccess) rc = hip_fail(e, "batched launch");
         }
         if (rc == SI_OK && stats) {

@@ -50,12 +50,8 @@ constexpr int kKeys = 1024;              // LPT key buckets (32 per octave of co
 constexpr int kTile = 256;               // units per sort tile
 
 // ---------------------------------------------------------------- features --
-__global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* __restrict__ oriented,
-                                                  int64_t N, float f11, float* __restrict__ feats) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    float* f = feats + kNF * i;
-    const int o = oriented[i];
+// The 12 features of oriented point o of the scene into f.
+__device__ void features_of(const SceneView& sc, int o, float f11, float* f) {
     if (o < 0 || o >= sc.M) {
         for (int k = 0; k < kNF; ++k) f[k] = 0.0f;
         return;
@@ -123,6 +119,13 @@ __global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* _
     f[9] = s9 * inv;
     f[10] = log1pf(tot);
     f[11] = f11;
+}
+
+__global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* __restrict__ oriented,
+                                                  int64_t N, float f11, float* __restrict__ feats) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    features_of(sc, oriented[i], f11, feats + kNF * i);
 }
 
 // ------------------------------------------------------------- MLP forward --
@@ -466,6 +469,212 @@ __global__ void __launch_bounds__(256) k_learned_perm(const int32_t* __restrict_
     for (int64_t r = 0; r < len; ++r) perm[o + r] = perm0 ? perm0[a + r] : (int32_t)(a + r);
 }
 
+// ------------------------------------------ learned schedule, many items --
+// The loop of a batched launch is the concatenation of the items' loops
+// (cell-ordered within each item).  Units never cross an item: item i has
+// units unit_off[i] .. unit_off[i+1]-1 of kUnit iterations (the last one
+// shorter).  All units are put in one LPT order (stable by cost key, so
+// within a key by item, then by unit) and cut by factoring on predicted cost
+// into global chunks; a global chunk is split into its runs of one item.
+// Item i's units, taken in LPT order, are its new loop order, so every run is
+// a contiguous range of that order: the segment of (key k, item i) starts at
+// base_len[i][k] = iterations of item i's units with keys < k.
+
+__device__ __forceinline__ int find_off(const int64_t* off, int n, int64_t t) {
+    int lo = 0, hi = n - 1;  // largest i with off[i] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Features of flattened iteration t (the image of item i's iteration
+// perm_cell[t], or t - item_off[i] without a cell order).
+__global__ void __launch_bounds__(256) k_features_multi(const Item* __restrict__ items,
+                                                        const int64_t* __restrict__ item_off,
+                                                        int n_items,
+                                                        const int32_t* __restrict__ perm_cell,
+                                                        const float* __restrict__ f11,
+                                                        int64_t total_N, float* __restrict__ feats) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= total_N) return;
+    const int i = find_off(item_off, n_items, t);
+    const Item& it = items[i];
+    const int w = perm_cell ? perm_cell[t] : (int)(t - item_off[i]);
+    features_of(it.scene, it.oriented[w], f11[i], feats + kNF * t);
+}
+
+// Cost and key of unit u (as k_unit_cost), its length and item, and the
+// per-(item, key) unit and iteration counts.
+__global__ void __launch_bounds__(256) k_unit_cost_multi(
+    const float* __restrict__ pred, const int64_t* __restrict__ unit_off,
+    const int64_t* __restrict__ item_off, int n_items, int64_t n_units,
+    uint32_t* __restrict__ qcost, int32_t* __restrict__ key, int32_t* __restrict__ ulen,
+    int32_t* __restrict__ uitem, int32_t* __restrict__ hcount, int32_t* __restrict__ hlen) {
+    const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (u >= n_units) return;
+    const int i = find_off(unit_off, n_items, u);
+    const int64_t a = item_off[i] + (u - unit_off[i]) * kUnit;
+    const int64_t b = min(item_off[i + 1], a + kUnit);
+    float c = 0.0f;
+    for (int64_t t = a; t < b; ++t) {
+        const float pv = pred[t];
+        c += (pv == pv) ? fminf(pv, 1e7f) + 1.0f : 1.0f;  // a non-finite prediction costs 1
+    }
+    const uint32_t q = (uint32_t)fmaxf(rintf(c), 1.0f);
+    qcost[u] = q;
+    const int k = kKeys - 1 - min(max((int)floorf(log2f((float)q) * 32.0f), 0), kKeys - 1);
+    key[u] = k;
+    ulen[u] = (int32_t)(b - a);
+    uitem[u] = i;
+    atomicAdd(hcount + (size_t)i * kKeys + k, 1);
+    atomicAdd(hlen + (size_t)i * kKeys + k, (int32_t)(b - a));
+}
+
+__global__ void __launch_bounds__(256) k_unit_gather_multi(const int32_t* __restrict__ order,
+                                                           const uint32_t* __restrict__ qcost,
+                                                           const int32_t* __restrict__ ulen,
+                                                           int64_t n_units,
+                                                           int64_t* __restrict__ cval,
+                                                           int64_t* __restrict__ ival) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n_units) return;
+    const int64_t u = order[k];
+    cval[k] = qcost[u];
+    ival[k] = ulen[u];
+}
+
+// Single block: factoring on predicted cost over the LPT order (cpre:
+// exclusive prefix of cost, n_units + 1 entries); marks the first LPT
+// position of every non-empty global chunk in cut (zeroed by the caller).
+// ends: P + 1 int64 of scratch.
+__global__ void __launch_bounds__(1024) k_learned_cuts(const int64_t* __restrict__ cpre,
+                                                       int64_t n_units, int P, float divisor,
+                                                       int64_t* __restrict__ ends,
+                                                       int32_t* __restrict__ cut) {
+    const int tid = threadIdx.x;
+    const int64_t total = cpre[n_units];
+    __shared__ int64_t start;
+    if (tid == 0) start = 0;
+    __syncthreads();
+    const double x = divisor > 0.0f ? (double)divisor : 2.0;
+    while (start < n_units) {
+        const int64_t st = start;
+        const int64_t R = total - cpre[st];
+        const int64_t cb = max((int64_t)1, (int64_t)ceil((double)R / (x * (double)P)));
+        for (int j = tid + 1; j <= P; j += 1024) {
+            const int64_t target = cpre[st] + (int64_t)j * cb;
+            int64_t lo = st + 1, hi = n_units;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (cpre[mid] >= target) hi = mid; else lo = mid + 1;
+            }
+            ends[j] = lo;
+        }
+        if (tid == 0) ends[0] = st;
+        __syncthreads();
+        for (int j = tid + 1; j <= P; j += 1024)
+            if (ends[j] > ends[j - 1]) cut[ends[j - 1]] = 1;
+        __syncthreads();
+        if (tid == 0) start = ends[P];
+        __syncthreads();
+    }
+}
+
+// base_len[i][k] = iterations of item i's units with keys < k (block i).
+__global__ void __launch_bounds__(kKeys) k_item_key_base(const int32_t* __restrict__ hlen,
+                                                         int32_t* __restrict__ base_len) {
+    __shared__ int sc[kKeys];
+    const int k = threadIdx.x;
+    const size_t row = (size_t)blockIdx.x * kKeys;
+    const int v = hlen[row + k];
+    sc[k] = v;
+    __syncthreads();
+    for (int off = 1; off < kKeys; off <<= 1) {
+        const int a = k >= off ? sc[k - off] : 0;
+        __syncthreads();
+        sc[k] += a;
+        __syncthreads();
+    }
+    base_len[row + k] = sc[k] - v;
+}
+
+// seg_first[k][i] = LPT position of the first unit of (key k, item i):
+// key_base[k] + units of key k in items < i (block k).
+__global__ void __launch_bounds__(256) k_seg_first(const int32_t* __restrict__ hcount,
+                                                   const int32_t* __restrict__ key_base,
+                                                   int n_items, int32_t* __restrict__ seg_first) {
+    __shared__ int sc[256];
+    __shared__ int carry;
+    const int k = blockIdx.x, tid = threadIdx.x;
+    if (tid == 0) carry = key_base[k];
+    __syncthreads();
+    for (int i0 = 0; i0 < n_items; i0 += 256) {
+        const int i = i0 + tid;
+        const int v = i < n_items ? hcount[(size_t)i * kKeys + k] : 0;
+        sc[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int a = tid >= off ? sc[tid - off] : 0;
+            __syncthreads();
+            sc[tid] += a;
+            __syncthreads();
+        }
+        if (i < n_items) seg_first[(size_t)k * n_items + i] = carry + sc[tid] - v;
+        __syncthreads();
+        if (tid == 255) carry += sc[255];
+        __syncthreads();
+    }
+}
+
+// Per LPT position k: the unit's offset in its item's new order, its
+// iterations written there, and whether a run (sub-chunk) starts at k.
+__global__ void __launch_bounds__(256) k_learned_perm_multi(
+    const int32_t* __restrict__ order, const int32_t* __restrict__ key,
+    const int32_t* __restrict__ ulen, const int32_t* __restrict__ uitem,
+    const int64_t* __restrict__ unit_off, const int64_t* __restrict__ item_off, int n_items,
+    const int64_t* __restrict__ ipre, const int32_t* __restrict__ base_len,
+    const int32_t* __restrict__ seg_first, const int32_t* __restrict__ cut,
+    const int32_t* __restrict__ perm_cell, int64_t n_units, int32_t* __restrict__ offs,
+    int32_t* __restrict__ flag, int32_t* __restrict__ perm) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n_units) return;
+    const int64_t u = order[k];
+    const int i = uitem[u];
+    const int kk = key[u];
+    const int64_t first = seg_first[(size_t)kk * n_items + i];
+    const int32_t off = base_len[(size_t)i * kKeys + kk] + (int32_t)(ipre[k] - ipre[first]);
+    offs[k] = off;
+    flag[k] = (k == 0 || cut[k] || uitem[order[k - 1]] != i) ? 1 : 0;
+    const int64_t a = item_off[i] + (u - unit_off[i]) * kUnit;
+    const int len = ulen[u];
+    int32_t* dst = perm + item_off[i] + off;
+    for (int r = 0; r < len; ++r)
+        dst[r] = perm_cell ? perm_cell[a + r] : (int32_t)(a + r - item_off[i]);
+}
+
+// Sub-chunks from the run starts: fpre = exclusive prefix of flag
+// (n_units + 1 entries).
+__global__ void __launch_bounds__(256) k_emit_runs(const int32_t* __restrict__ order,
+                                                   const int32_t* __restrict__ uitem,
+                                                   const int32_t* __restrict__ ulen,
+                                                   const int32_t* __restrict__ offs,
+                                                   const int32_t* __restrict__ flag,
+                                                   const int32_t* __restrict__ fpre,
+                                                   int64_t n_units, Chunk* __restrict__ chunks,
+                                                   int32_t* __restrict__ n_chunks) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n_units) return;
+    const int c = fpre[k + 1] - 1;  // run holding position k
+    if (flag[k]) {
+        chunks[c].item = uitem[order[k]];
+        chunks[c].start = offs[k];
+    }
+    if (k == n_units - 1 || flag[k + 1]) chunks[c].end = offs[k] + ulen[order[k]];
+    if (k == n_units - 1) *n_chunks = fpre[n_units];
+}
+
 uint64_t splitmix(uint64_t& s) {
     uint64_t z = (s += 0x9e3779b97f4a7c15ull);
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -578,6 +787,107 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
     plan->n_chunks_dev = I(o_nch);
     plan->perm = I(o_perm);
     return SI_OK;
+}
+
+int64_t learned_units(const int64_t* item_N, int n_items, int64_t* unit_off) {
+    int64_t u = 0;
+    for (int i = 0; i < n_items; ++i) {
+        if (unit_off) unit_off[i] = u;
+        u += (item_N[i] + kUnit - 1) / kUnit;
+    }
+    if (unit_off) unit_off[n_items] = u;
+    return u;
+}
+
+size_t learned_multi_layout(int n_items, int64_t total_N, int64_t n_units, int P,
+                            LearnedMulti& b, char* base) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + o : nullptr;
+        o += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+        return p;
+    };
+    const int64_t n_tiles = (n_units + kTile - 1) / kTile;
+    const size_t ik = (size_t)n_items * kKeys;
+    b.unit_off = (int64_t*)take(sizeof(int64_t) * (n_items + 1));
+    b.f11 = (float*)take(sizeof(float) * n_items);
+    b.feats = (float*)take(sizeof(float) * kNF * total_N);
+    b.pred = (float*)take(sizeof(float) * total_N);
+    b.qcost = (uint32_t*)take(sizeof(uint32_t) * n_units);
+    b.ukey = (int32_t*)take(sizeof(int32_t) * n_units);
+    b.ulen = (int32_t*)take(sizeof(int32_t) * n_units);
+    b.uitem = (int32_t*)take(sizeof(int32_t) * n_units);
+    b.urank = (int32_t*)take(sizeof(int32_t) * n_units);
+    b.hist = (int32_t*)take(sizeof(int32_t) * n_tiles * kKeys);
+    b.ktot = (int32_t*)take(sizeof(int32_t) * kKeys);
+    b.kbase = (int32_t*)take(sizeof(int32_t) * kKeys);
+    b.order = (int32_t*)take(sizeof(int32_t) * n_units);
+    b.cval = (int64_t*)take(sizeof(int64_t) * n_units);
+    b.ival = (int64_t*)take(sizeof(int64_t) * n_units);
+    b.cpre = (int64_t*)take(sizeof(int64_t) * (n_units + 1));
+    b.ipre = (int64_t*)take(sizeof(int64_t) * (n_units + 1));
+    b.ltmp = (int64_t*)take(sizeof(int64_t) * scan_tmp_elems(n_units + 1));
+    b.ends = (int64_t*)take(sizeof(int64_t) * (P + 1));
+    b.cut = (int32_t*)take(sizeof(int32_t) * n_units);
+    b.hcount = (int32_t*)take(sizeof(int32_t) * ik);
+    b.hlen = (int32_t*)take(sizeof(int32_t) * ik);
+    b.base_len = (int32_t*)take(sizeof(int32_t) * ik);
+    b.seg_first = (int32_t*)take(sizeof(int32_t) * ik);
+    b.offs = (int32_t*)take(sizeof(int32_t) * n_units);
+    b.flag = (int32_t*)take(sizeof(int32_t) * n_units);
+    b.fpre = (int32_t*)take(sizeof(int32_t) * (n_units + 1));
+    b.itmp = (int32_t*)take(sizeof(int32_t) * scan_tmp_elems(n_units + 1));
+    b.perm = (int32_t*)take(sizeof(int32_t) * total_N);
+    b.chunks = (Chunk*)take(sizeof(Chunk) * n_units);
+    b.n_chunks = (int32_t*)take(sizeof(int32_t));
+    return o;
+}
+
+hipError_t learned_multi_enqueue(const si_cost_model* model, const LearnedMulti& b,
+                                 const Item* items, const int64_t* item_off, int n_items,
+                                 const int32_t* perm_cell, int64_t total_N, int64_t n_units, int P,
+                                 float divisor, hipStream_t s) {
+    const int64_t n_tiles = (n_units + kTile - 1) / kTile;
+    const int64_t ik = (int64_t)n_items * kKeys;
+    hipError_t e = launch_fill(b.hcount, ik, 0, s);
+    if (e == hipSuccess) e = launch_fill(b.hlen, ik, 0, s);
+    if (e == hipSuccess) e = launch_fill(b.cut, n_units, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_features_multi, dim3(nblocks(total_N)), dim3(256), 0, s, items, item_off,
+                       n_items, perm_cell, b.f11, total_N, b.feats);
+    hipLaunchKernelGGL(k_mlp_predict, dim3(nblocks(total_N)), dim3(256), 0, s, model->params,
+                       b.feats, total_N, b.pred, 0);
+    hipLaunchKernelGGL(k_unit_cost_multi, dim3(nblocks(n_units)), dim3(256), 0, s, b.pred,
+                       b.unit_off, item_off, n_items, n_units, b.qcost, b.ukey, b.ulen, b.uitem,
+                       b.hcount, b.hlen);
+    // one LPT order of all units (stable by key)
+    hipLaunchKernelGGL(k_unit_hist, dim3((unsigned)n_tiles), dim3(kTile), 0, s, b.ukey, n_units,
+                       b.hist, b.urank);
+    hipLaunchKernelGGL(k_unit_tile_scan, dim3(kKeys), dim3(256), 0, s, b.hist, (int)n_tiles,
+                       b.ktot);
+    hipLaunchKernelGGL(k_unit_key_base, dim3(1), dim3(kKeys), 0, s, b.ktot, b.kbase);
+    hipLaunchKernelGGL(k_unit_scatter, dim3(nblocks(n_units)), dim3(256), 0, s, b.ukey, b.urank,
+                       b.hist, b.kbase, n_units, b.order);
+    hipLaunchKernelGGL(k_unit_gather_multi, dim3(nblocks(n_units)), dim3(256), 0, s, b.order,
+                       b.qcost, b.ulen, n_units, b.cval, b.ival);
+    e = launch_scan64(b.cval, b.cpre, n_units, b.ltmp, s);
+    if (e == hipSuccess) e = launch_scan64(b.ival, b.ipre, n_units, b.ltmp, s);
+    if (e != hipSuccess) return e;
+    // global chunks by factoring on cost, then each item's new order
+    hipLaunchKernelGGL(k_learned_cuts, dim3(1), dim3(1024), 0, s, b.cpre, n_units, P, divisor,
+                       b.ends, b.cut);
+    hipLaunchKernelGGL(k_item_key_base, dim3((unsigned)n_items), dim3(kKeys), 0, s, b.hlen,
+                       b.base_len);
+    hipLaunchKernelGGL(k_seg_first, dim3(kKeys), dim3(256), 0, s, b.hcount, b.kbase, n_items,
+                       b.seg_first);
+    hipLaunchKernelGGL(k_learned_perm_multi, dim3(nblocks(n_units)), dim3(256), 0, s, b.order,
+                       b.ukey, b.ulen, b.uitem, b.unit_off, item_off, n_items, b.ipre, b.base_len,
+                       b.seg_first, b.cut, perm_cell, n_units, b.offs, b.flag, b.perm);
+    e = launch_scan(b.flag, b.fpre, n_units, b.itmp, scan_tmp_elems(n_units), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_emit_runs, dim3(nblocks(n_units)), dim3(256), 0, s, b.order, b.uitem,
+                       b.ulen, b.offs, b.flag, b.fpre, n_units, b.chunks, b.n_chunks);
+    return hipGetLastError();
 }
 
 }  // namespace si

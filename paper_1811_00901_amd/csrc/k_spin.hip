@@ -498,8 +498,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
         const SpinParams p = uniform(it.p);
         const int W = p.W;
         const int w2 = W * W;
-        // images per group: keep the LDS footprint of the launch (group x max_w2)
-        const int G_item = min(kMaxGroup, max(1, (d.group * (d.max_w2 + 4)) / (w2 + 4)));
+        // images per group: keep the LDS footprint of the launch (group x
+        // max_w2); items of a smaller W take more images, at most
+        // max(group, 4) (more would not fit the scalar registers)
+        const int G_item = min(max(d.group, 4),
+                               min(kMaxGroup, max(1, (d.group * (d.max_w2 + 4)) / (w2 + 4))));
         // cells a group may span per axis beyond the first, and rows available
         const int span_lim = max(0, min(1, 7 - 2 * p.reach));
 

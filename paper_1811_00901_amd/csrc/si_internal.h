@@ -195,6 +195,38 @@ si_status learned_table(DeviceState* st, const Scene* scene, const int32_t* orie
                         LearnedPlan* plan, hipStream_t s);
 si_status features_launch(const Scene& sc, const int32_t* oriented, int64_t N,
                           const si_params* params, float* feats, hipStream_t s);
+// Learned schedule of a batched launch (many items), all on the device.
+// Buffers in one block laid out by learned_multi_layout (base == nullptr:
+// size only).  unit_off (n_items + 1: first unit of each item, kUnit
+// iterations per unit) and f11 (n_items: the support-radius feature) are
+// filled by the caller; the plan writes perm (total_N: each item's new loop
+// order, item-local iterations, at item_off[i]), chunks and *n_chunks.
+struct LearnedMulti {
+    int64_t* unit_off = nullptr;
+    float* f11 = nullptr;
+    float* feats = nullptr;
+    float* pred = nullptr;
+    uint32_t* qcost = nullptr;
+    int32_t *ukey = nullptr, *ulen = nullptr, *uitem = nullptr, *urank = nullptr;
+    int32_t *hist = nullptr, *ktot = nullptr, *kbase = nullptr, *order = nullptr;
+    int64_t *cval = nullptr, *ival = nullptr, *cpre = nullptr, *ipre = nullptr, *ltmp = nullptr;
+    int64_t* ends = nullptr;
+    int32_t *cut = nullptr, *hcount = nullptr, *hlen = nullptr, *base_len = nullptr;
+    int32_t *seg_first = nullptr, *offs = nullptr, *flag = nullptr, *fpre = nullptr;
+    int32_t* itmp = nullptr;
+    int32_t* perm = nullptr;
+    Chunk* chunks = nullptr;
+    int32_t* n_chunks = nullptr;
+};
+int64_t learned_units(const int64_t* item_N, int n_items, int64_t* unit_off_host);
+size_t learned_multi_layout(int n_items, int64_t total_N, int64_t n_units, int P,
+                            LearnedMulti& b, char* base);
+hipError_t learned_multi_enqueue(const si_cost_model* model, const LearnedMulti& b,
+                                 const Item* items, const int64_t* item_off, int n_items,
+                                 const int32_t* perm_cell, int64_t total_N, int64_t n_units, int P,
+                                 float divisor, hipStream_t s);
+// Largest P the learned schedules accept.
+constexpr int kMaxLearnedP = 4096;
 
 // Host chunk tables.
 int64_t chunk_sizes(int kind, int64_t N, int P, int min_chunk, float divisor,

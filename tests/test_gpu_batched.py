@@ -171,3 +171,48 @@ def test_autotune(env, tmp_path):
         assert s1.kind == "static"
     finally:
         del os.environ["SI_AUTOTUNE_CACHE"]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_learned(env, use_graph):
+    """SI_SCHED_LEARNED in a batched launch: one LPT order of the units of all
+    items, cut by factoring on predicted cost and split into runs of one item.
+    Every image is written once (outputs start at -1; the in-support total
+    would double-count a repeated image), for several workgroup counts,
+    both loop orders, items shorter than one unit, and a model trained on the
+    logged counts as well as an untrained one."""
+    torch, si, _ = env
+    print(f"\n[case] batched learned graph={use_graph}", flush=True)
+    batch = make_batch(torch, si, n_scenes=10, seed=4500, brute=(2,))
+    batch[3]["idx"] = batch[3]["idx"][:5]             # shorter than one unit
+    batch[3]["img"] = batch[3]["img"][:5]
+    batch[3]["cnt"] = batch[3]["cnt"][:5]
+    batch[3]["N"] = 5
+    ref = singles(si, torch, batch, si.Sched("fac"))
+    total = sum(int(c.to(torch.int64).sum()) for _, c in ref)
+    trained = si.si_cost_model_create(21)
+    feats = si.si_features(batch[0]["scene"], batch[0]["idx"], batch[0]["params"])
+    si.si_cost_model_train(trained, feats, ref[0][1], epochs=3, lr=2e-3, batch=256)
+    for model in (si.si_cost_model_create(20), trained):
+        for order in ("cell", "given"):
+            for P in (200, 1500):
+                for b in batch:
+                    b["img"].fill_(-1.0)
+                    b["cnt"].fill_(-1)
+                st = si.si_generate_batched(
+                    items_of(batch), si.Sched("learned", model=model, order=order, num_workgroups=P),
+                    use_graph=use_graph, stats=True)
+                torch.cuda.synchronize()
+                assert st["sched_used"] == si.SCHED["learned"]
+                assert 0 < st["n_chunks"] <= sum((b["N"] + 15) // 16 for b in batch)
+                assert st["pairs_in_support"] == total, (order, P)
+                for b, (img, cnt) in zip(batch, ref):
+                    assert torch.equal(b["img"], img), (order, P)
+                    assert torch.equal(b["cnt"], cnt), (order, P)
+    # no model: FAC, or an error when the fallback is off
+    st = si.si_generate_batched(items_of(batch), si.Sched("learned"), use_graph=use_graph,
+                                stats=True)
+    assert st["sched_used"] == si.SCHED["fac"]
+    with pytest.raises(si.SiError):
+        si.si_generate_batched(items_of(batch), si.Sched("learned", fallback_to_fac=False),
+                               use_graph=use_graph)
