@@ -214,7 +214,7 @@ def batched(torch, si, sg, model):
     loop_ms = timed(torch, loop)
     ref = [(img.clone(), cnt.clone()) for _, _, _, img, cnt in items]
     pairs = sum(int(c.to(torch.int64).sum()) for _, c in ref)
-    tuned, _ = si.si_autotune(items, "fac", use_graph=True, max_trials=12)
+    tuned, _ = si.si_autotune(items, "fac", use_graph=True, max_trials=24)
     graph_ms = timed(torch, lambda: si.si_generate_batched(items, tuned, use_graph=True))
     default_ms = timed(torch, lambda: si.si_generate_batched(items, fac, use_graph=True))
     same = all(torch.equal(img, r[0]) and torch.equal(cnt, r[1])
@@ -225,7 +225,13 @@ def batched(torch, si, sg, model):
                       True, tuned.group)
         learned_ms = timed(torch, lambda: si.si_generate_batched(items, ls, use_graph=True))
         st = si.si_generate_batched(items, ls, use_graph=True, stats=True)
-        learned = {"ms": learned_ms, "sched_used": list(si.SCHED)[st["sched_used"]],
+        # the same with the library's defaults (no tuning)
+        ld = si.Sched("learned", model=model)
+        learned_default_ms = timed(torch, lambda: si.si_generate_batched(items, ld, use_graph=True))
+        learned = {"ms": learned_ms, "default_ms": learned_default_ms,
+                   "speedup_default_vs_fac_default":
+                       default_ms["median"] / learned_default_ms["median"],
+                   "sched_used": list(si.SCHED)[st["sched_used"]],
                    "n_chunks": st["n_chunks"],
                    "identical": all(torch.equal(img, r[0]) and torch.equal(cnt, r[1])
                                     for (_, _, _, img, cnt), r in zip(items, ref)),

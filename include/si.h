@@ -242,10 +242,12 @@ si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
 /*
  * Autotuner: picks the launch parameters of a workload (the items as for
  * si_generate_batched; one item for a single scene) for scheduling technique
- * `kind`.  Tuned: group (images per shared candidate pass), num_workgroups,
- * fac_divisor (FAC and LEARNED) and min_chunk (dynamic techniques), by
- * coordinate descent from the defaults, at most max_trials timed candidates
- * (each the median of two launches after a warm-up).  Every candidate's
+ * `kind`.  Tuned: group (images per shared candidate pass, from 1, 2, 4, 6,
+ * 8), num_workgroups (2, 3, 4, 6 or 8 per compute unit), fac_divisor (FAC and
+ * LEARNED: 1.5, 2, 3, 4) and min_chunk (dynamic techniques: 0, 4, 16), by two
+ * sweeps of coordinate descent from the library's defaults for the workload,
+ * at most max_trials timed candidates (each the median of two launches after
+ * a warm-up).  Every candidate's
  * images and counts must give the same 64-bit checksum as the first one,
  * else SI_E_DEVICE.  The winner is written to *best (kind and order filled,
  * model NULL) and its time to *best_ms (host, may be NULL).  Winners are

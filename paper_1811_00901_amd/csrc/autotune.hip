@@ -4,10 +4,11 @@
 // here are the knobs of this implementation that do not change any image:
 // images per shared candidate pass (group), persistent workgroups (P), the
 // factoring divisor x and the minimum chunk.  The search is coordinate descent
-// from the defaults, each candidate timed with HIP events on the caller's
-// workload; every candidate's images and counts must hash to the same 64-bit
-// checksum as the first one.  Winners are cached per (device, technique,
-// image widths, size class), in memory and optionally in a JSON file.
+// (two sweeps) from the library defaults, each candidate timed with HIP events
+// on the caller's workload; every candidate's images and counts must hash to
+// the same 64-bit checksum as the first one.  Winners are cached per (device,
+// technique, image widths, size class), in memory and optionally in a JSON
+// file.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -188,6 +189,16 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
         }
     }
 
+    // the defaults the library would pick for this workload, spelled out
+    int max_w2 = 4;
+    for (int32_t i = 0; i < n_items; ++i)
+        if (items[i].N > 0) max_w2 = std::max(max_w2, items[i].params.W * items[i].params.W);
+    int max_W = 2;
+    while (max_W * max_W < max_w2) ++max_W;
+    base.group = fit_group(st, default_group(max_W), max_w2);
+    base.num_workgroups = auto_workgroups(st, max_w2, base.group);
+    base.fac_divisor = (kind == SI_SCHED_FAC || kind == SI_SCHED_LEARNED) ? 2.0f : 0.0f;
+
     unsigned long long* dsum = nullptr;
     SI_HIP(hipMalloc(&dsum, 16));
     uint64_t ref_sum = 0;
@@ -217,8 +228,7 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
         return SI_OK;
     };
 
-    si_sched cur = base;
-    cur.group = 8;
+    si_sched cur = base;  // the library defaults first
     double cur_ms = 0.0;
     rc = measure(cur, &cur_ms);
     auto try_set = [&](si_sched cand) -> si_status {
@@ -232,34 +242,37 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
         }
         return SI_OK;
     };
-    // images per shared pass
-    for (int g : {4, 6, 2}) {
-        if (rc != SI_OK) break;
-        si_sched c = cur;
-        c.group = g;
-        rc = try_set(c);
-    }
-    // persistent workgroups per CU
-    for (int per_cu : {2, 4, 3, 6}) {
-        if (rc != SI_OK) break;
-        si_sched c = cur;
-        c.num_workgroups = st->n_cu * per_cu;
-        rc = try_set(c);
-    }
-    if (kind == SI_SCHED_FAC || kind == SI_SCHED_LEARNED) {
-        for (float x : {1.5f, 3.0f, 4.0f}) {
-            if (rc != SI_OK) break;
+    // two sweeps of coordinate descent while the trial budget lasts
+    for (int sweep = 0; sweep < 2 && rc == SI_OK && trials < max_trials; ++sweep) {
+        // images per shared pass
+        for (int g : {4, 8, 2, 6, 1}) {
+            if (rc != SI_OK || g == cur.group) continue;
             si_sched c = cur;
-            c.fac_divisor = x;
+            c.group = g;
             rc = try_set(c);
         }
-    }
-    if (kind != SI_SCHED_STATIC) {
-        for (int mc : {4, 16}) {
-            if (rc != SI_OK) break;
+        // persistent workgroups per CU
+        for (int per_cu : {4, 6, 3, 8, 2}) {
+            if (rc != SI_OK || st->n_cu * per_cu == cur.num_workgroups) continue;
             si_sched c = cur;
-            c.min_chunk = mc;
+            c.num_workgroups = st->n_cu * per_cu;
             rc = try_set(c);
+        }
+        if (kind == SI_SCHED_FAC || kind == SI_SCHED_LEARNED) {
+            for (float x : {4.0f, 3.0f, 1.5f, 2.0f}) {
+                if (rc != SI_OK || x == cur.fac_divisor) continue;
+                si_sched c = cur;
+                c.fac_divisor = x;
+                rc = try_set(c);
+            }
+        }
+        if (kind != SI_SCHED_STATIC) {
+            for (int mc : {4, 16, 0}) {
+                if (rc != SI_OK || mc == cur.min_chunk) continue;
+                si_sched c = cur;
+                c.min_chunk = mc;
+                rc = try_set(c);
+            }
         }
     }
     (void)hipFree(dsum);
