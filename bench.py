@@ -373,8 +373,13 @@ def main():
     # ---- every schedule, generation only, bit-identical images ----
     sched_res = {}
     if not args.no_schedules:
-        for kind in ["static", "ss", "gss", "fac", "learned"]:
-            sch = si.Sched(kind, model=model if kind == "learned" else None)
+        # the four techniques of the paper on the spread cell order (default)
+        # and on the contiguous cell order; LEARNED builds its own order
+        runs = [(k, k, "spread") for k in ("static", "ss", "gss", "fac")]
+        runs += [(k + "_cell", k, "cell") for k in ("static", "ss", "gss", "fac")]
+        runs += [("learned", "learned", "spread")]
+        for name, kind, order in runs:
+            sch = si.Sched(kind, model=model if kind == "learned" else None, order=order)
             times, used, ok = [], None, True
             for r in range(WARM + REPS):
                 images.fill_(-1.0)
@@ -389,18 +394,22 @@ def main():
                     times.append((s2["kernel_ms"], ev[0].elapsed_time(ev[1])))
             busy = s2["wg_busy_ns"].astype(np.float64)
             call = spread([t[1] for t in times])
-            sched_res[kind] = {"kernel_ms": spread([t[0] for t in times]), "call_ms": call,
+            sched_res[name] = {"order": order if kind != "learned" else "learned",
+                               "kernel_ms": spread([t[0] for t in times]), "call_ms": call,
                                "pairs_per_s": pairs / (call["median"] * 1e-3),
                                "images_per_s": N / (call["median"] * 1e-3),
                                "identical": ok, "sched_used": list(si.SCHED)[used],
                                "n_chunks": s2["n_chunks"],
                                "imbalance": float(busy.max() / max(busy.mean(), 1.0))}
-            log(f"[bench] {kind}: kernel {sched_res[kind]['kernel_ms']['median']:.2f} ms, "
+            log(f"[bench] {name}: kernel {sched_res[name]['kernel_ms']['median']:.2f} ms, "
                 f"call {call['median']:.2f} ms, identical {ok}, "
-                f"imbalance {sched_res[kind]['imbalance']:.3f}")
+                f"imbalance {sched_res[name]['imbalance']:.3f}")
         base = sched_res["static"]["call_ms"]["median"]
+        base_cell = sched_res["static_cell"]["call_ms"]["median"]
         for k in sched_res:
             sched_res[k]["speedup_vs_static"] = base / sched_res[k]["call_ms"]["median"]
+            if k.endswith("_cell"):
+                sched_res[k]["speedup_vs_static_cell"] = base_cell / sched_res[k]["call_ms"]["median"]
         si.si_generate(scene, idx, params, fac, images, counts)
     torch.cuda.synchronize()
     del ref_img, ref_cnt
@@ -453,7 +462,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {M} points, {N} oriented, W={cfg.W}, bin={cfg.bin}, "
-                               f"support angle 60 deg, bilinear, FAC, cell list",
+                               f"support angle 60 deg, bilinear, FAC2, cell list, "
+                               f"spread cell order",
                    "global_batch": N, "parallelism": "single GPU, persistent workgroups"},
         "images_per_s": images_per_s,
         "generation_ms": gen_ms,

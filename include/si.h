@@ -102,7 +102,14 @@ typedef struct si_params {
  *   fallback_to_fac SI_SCHED_LEARNED without a model: 1 = run FAC, 0 = error
  *   group           images that share one pass over their common candidate
  *                   points (1..8); 0 = library default
- *   order           SI_ORDER_CELL (0): the loop runs over the oriented points
+ *   order           SI_ORDER_SPREAD (0): the oriented points sorted by grid
+ *                   cell, in units of 64 consecutive iterations, and the
+ *                   units taken with a stride coprime to their number, so
+ *                   that every part of the loop holds units from the whole
+ *                   scene (chunks of neighbouring images keep sharing
+ *                   candidates, while costs stop clustering along the loop;
+ *                   SI_SCHED_LEARNED builds its own order from the cell
+ *                   order); SI_ORDER_CELL (2): the loop runs over the oriented points
  *                   sorted by grid cell, so that neighbouring images share
  *                   candidates (iterations of a DOALL loop may run in any
  *                   order); SI_ORDER_GIVEN (1): in the order of oriented_idx,
@@ -121,8 +128,9 @@ typedef struct si_sched {
 } si_sched;
 
 enum {
-    SI_ORDER_CELL = 0,
-    SI_ORDER_GIVEN = 1
+    SI_ORDER_SPREAD = 0,
+    SI_ORDER_GIVEN = 1,
+    SI_ORDER_CELL = 2
 };
 
 /*

@@ -33,7 +33,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libspinimg.
 
 SCHED = {"static": 0, "ss": 1, "gss": 2, "fac": 3, "learned": 4}
 MODE = {"bilinear": 0, "ceil": 1}
-ORDER = {"cell": 0, "given": 1}
+ORDER = {"spread": 0, "given": 1, "cell": 2}
 STATUS = {0: "SI_OK", -1: "SI_E_INVALID", -2: "SI_E_OOM", -3: "SI_E_DEVICE", -4: "SI_E_UNSUPPORTED"}
 
 
@@ -182,7 +182,9 @@ class Sched:
     model: "CostModel | None" = None
     fallback_to_fac: bool = True
     group: int = 0
-    order: str = "cell"   # "cell": loop over points sorted by grid cell; "given": oriented_idx order
+    # "spread": units of 64 cell-ordered iterations spread over the loop;
+    # "cell": loop over points sorted by grid cell; "given": oriented_idx order
+    order: str = "spread"
 
     def c(self) -> c_sched:
         return c_sched(SCHED[self.kind], int(self.num_workgroups), int(self.min_chunk),
@@ -323,7 +325,7 @@ def si_autotune(items, kind: str = "fac", use_graph: bool = True, max_trials: in
                              1 if force else 0, ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
     inv = {v: k for k, v in SCHED.items()}
     sched = Sched(inv[best.kind], best.num_workgroups, best.min_chunk, best.fac_divisor,
-                  None, True, best.group, "cell" if best.order == 0 else "given")
+                  None, True, best.group, {v: k for k, v in ORDER.items()}[best.order])
     return sched, float(ms.value)
 
 

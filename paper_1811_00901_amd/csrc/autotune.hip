@@ -172,7 +172,7 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
     memset(&base, 0, sizeof(base));
     base.kind = kind;
     base.fallback_to_fac = 1;
-    base.order = SI_ORDER_CELL;
+    base.order = SI_ORDER_SPREAD;
     const std::string key = tune_key(items, n_items, kind, use_graph);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

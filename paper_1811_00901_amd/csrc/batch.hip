@@ -187,7 +187,13 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
     f.group = fit_group(st, g, f.max_w2);
     f.n_wg = sched->num_workgroups > 0 ? sched->num_workgroups
                                        : auto_workgroups(st, f.max_w2, f.group);
-    f.ordered = sched->order == SI_ORDER_CELL && f.total_cells > (int64_t)f.items.size();
+    f.ordered = sched->order != SI_ORDER_GIVEN && f.total_cells > (int64_t)f.items.size();
+    if (f.ordered && sched->order == SI_ORDER_SPREAD && !f.learned) {
+        for (Item& it : f.items) {
+            it.spread_mult = spread_mult(it.N / 64);
+            it.spread_full = it.spread_mult ? (int32_t)(it.N / 64) : 0;
+        }
+    }
     if (f.learned) {
         if (f.n_wg > kMaxLearnedP)
             return fail(SI_E_INVALID, "the learned schedule supports at most " +

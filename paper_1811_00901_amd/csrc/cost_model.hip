@@ -741,7 +741,7 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
     auto I = [&](size_t off) { return reinterpret_cast<int32_t*>(mem + off); };
     int32_t* perm0 = nullptr;
     hipError_t e = hipSuccess;
-    if (sched->order == SI_ORDER_CELL && scene->n_cells > 1) {
+    if (sched->order != SI_ORDER_GIVEN && scene->n_cells > 1) {
         perm0 = I(o_perm0);
         e = launch_cell_order(oriented, N, *scene, I(o_key), I(o_rank), I(o_counts), I(o_starts),
                               I(o_tmp), perm0, s);

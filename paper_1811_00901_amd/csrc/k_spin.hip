@@ -43,7 +43,8 @@ struct __attribute__((aligned(16))) ImgInfo {
     float px, py, pz;
     int32_t out;      // output position, -1 = invalid index
     float nx, ny, nz;
-    int32_t cell;     // linear cell id
+    int32_t cell;     // linear cell id, -1 = invalid index
+    int32_t cx, cy, cz, pad;  // cell coordinates
 };
 
 __device__ __forceinline__ float rfl(float v) {
@@ -322,7 +323,7 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // the four partial ranges of row r, looks them up in sub_start and writes
 // row_start / row_pref (exclusive prefix of run lengths) / n_rows.
 __device__ __forceinline__ void rows_cull(const SceneView& sc, const SpinParams& p,
-                                          const GroupImg* gi, const int* gcell, int ng,
+                                          const GroupImg* gi, const int* gcx, int ng,
                                           const int lo[3], const int hi[3], int* part_x0,
                                           int* part_x1) {
     const int t = threadIdx.x;
@@ -377,16 +378,26 @@ __device__ __forceinline__ void rows_cull(const SceneView& sc, const SpinParams&
             const double fb = floor((xb - (double)sc.origin[0]) * (inv_h * kSubX));
             const int a = (int)fmax(-1.0, fmin(fa, 1.0e9));
             const int b = (int)fmax(-1.0, fmin(fb, 1.0e9));
-            int gx, gy, gz;
-            cell_xyz(gcell[g], sc.dims, gx, gy, gz);
             if (p.reach == 0) {
                 // single-cell scene: the paper's loop over all M points
                 x0 = 0;
                 x1 = kSubX - 1;
                 continue;
             }
-            x0 = min(x0, max(a, (gx - p.reach) * kSubX));
-            x1 = max(x1, min(b, (gx + p.reach) * kSubX + kSubX - 1));
+            x0 = min(x0, max(a, (gcx[g] - p.reach) * kSubX));
+            x1 = max(x1, min(b, (gcx[g] + p.reach) * kSubX + kSubX - 1));
+        }
+        // this thread's part of the row's run, as point indices
+        x0 = max(x0, 0);
+        x1 = min(x1, sc.dims[0] * kSubX - 1);
+        if (x1 >= x0) {
+            const int base = (cz * sc.dims[1] + cy) * sc.dims[0] * kSubX;
+            const int st = sc.sub_start[base + x0];
+            x1 = sc.sub_start[base + x1 + 1];
+            x0 = st;
+        } else {
+            x0 = 0x7fffffff;
+            x1 = -1;
         }
     }
     part_x0[t] = x0;
@@ -403,20 +414,17 @@ __device__ __forceinline__ void rows_emit(const SceneView& sc, const int lo[3], 
     const int n_rows = ny_rows * nz_rows;
     int len = 0, start = 0;
     if (lane < n_rows) {
+        // the partial runs are key ranges of one row, so the point range of
+        // their span is [min of starts, max of ends)
         int x0 = part_x0[lane], x1 = part_x1[lane];
 #pragma unroll
         for (int q = 1; q < kBlock / 64; ++q) {
             x0 = min(x0, part_x0[lane + 64 * q]);
             x1 = max(x1, part_x1[lane + 64 * q]);
         }
-        x0 = max(x0, 0);
-        x1 = min(x1, sc.dims[0] * kSubX - 1);
-        if (x1 >= x0) {
-            const int cy = lo[1] + lane % ny_rows;
-            const int cz = lo[2] + lane / ny_rows;
-            const int base = (cz * sc.dims[1] + cy) * sc.dims[0] * kSubX;
-            start = sc.sub_start[base + x0];
-            len = sc.sub_start[base + x1 + 1] - start;
+        if (x1 > x0) {
+            start = x0;
+            len = x1 - x0;
         }
     }
     // inclusive scan of len over the wave
@@ -510,7 +518,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
             const int nb = min(kInfo, c_end - b0);
             __syncthreads();  // s_info reuse
             if (tid < nb) {
-                const int w = b0 + tid;
+                int w = b0 + tid;
+                if (it.spread_full > 1 && w < it.spread_full * 64)
+                    w = (int)(((long long)(w >> 6) * it.spread_mult) % it.spread_full) * 64 + (w & 63);
                 const int out = it.perm ? it.perm[w] : w;
                 const int o = it.oriented[out];
                 ImgInfo inf;
@@ -521,12 +531,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     inf.px = a.x; inf.py = a.y; inf.pz = a.z;
                     inf.nx = n.x; inf.ny = n.y; inf.nz = n.z;
                     inf.cell = __float_as_int(a.w);
+                    cell_xyz(inf.cell, sc.dims, inf.cx, inf.cy, inf.cz);
                     inf.out = out;
                 } else {
                     const float qnan = __int_as_float(0x7fc00000);
                     inf.px = inf.py = inf.pz = qnan;
                     inf.nx = inf.ny = inf.nz = qnan;
                     inf.cell = -1;
+                    inf.cx = inf.cy = inf.cz = 0;
                     inf.out = -1 - out;  // invalid: encode the output position
                 }
                 s_info[tid] = inf;
@@ -540,10 +552,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                 int hi[3] = {-1, -1, -1};
                 int ng = 0;
                 while (ng < G_item && cur + ng < nb) {
-                    const int cell = s_info[cur + ng].cell;
-                    if (cell >= 0) {
-                        int c[3];
-                        cell_xyz(cell, sc.dims, c[0], c[1], c[2]);
+                    const ImgInfo& ci = s_info[cur + ng];
+                    if (ci.cell >= 0) {
+                        const int c[3] = {ci.cx, ci.cy, ci.cz};
                         int nlo[3], nhi[3];
                         bool ok = true;
 #pragma unroll
@@ -558,16 +569,17 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     }
                     ++ng;
                 }
-                int gcell[kMaxGroup];
+                ng = rfl(ng);
+                int gcx[kMaxGroup];
                 GroupImg gi[kMaxGroup];
 #pragma unroll
                 for (int g = 0; g < kMaxGroup; ++g) {
-                    const ImgInfo inf = s_info[cur + (g < ng ? g : 0)];
-                    gcell[g] = inf.cell >= 0 ? inf.cell : 0;
+                    if (g >= ng) break;
+                    const ImgInfo inf = s_info[cur + g];
+                    gcx[g] = rfl(inf.cx);
                     gi[g].px = rfl(inf.px); gi[g].py = rfl(inf.py); gi[g].pz = rfl(inf.pz);
                     gi[g].nx = rfl(inf.nx); gi[g].ny = rfl(inf.ny); gi[g].nz = rfl(inf.nz);
                 }
-                ng = rfl(ng);
                 const bool any_valid = hi[0] >= 0;
                 int rlo[3], rhi[3];
                 for (int a = 0; a < 3; ++a) {
@@ -582,7 +594,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                     for (int i = tid; i < n4; i += kBlock) a4[i] = make_uint4(0, 0, 0, 0);
                     if (tid < kMaxGroup) s_cnt[tid] = 0;
                 }
-                rows_cull(sc, p, gi, gcell, ng, rlo, rhi, s_part_x0, s_part_x1);
+                rows_cull(sc, p, gi, gcx, ng, rlo, rhi, s_part_x0, s_part_x1);
                 __syncthreads();
                 if (tid < 64)
                     rows_emit(sc, rlo, rhi, any_valid, s_part_x0, s_part_x1, s_row_start,

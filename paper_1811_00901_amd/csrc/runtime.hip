@@ -391,6 +391,17 @@ namespace si {
 // scalar registers; W = 64 images are 16 KB each, so two per pass.
 int default_group(int W) { return W >= 64 ? 2 : 4; }
 
+int32_t spread_mult(int64_t full) {
+    if (full <= 1 || full >= INT32_MAX) return 0;
+    int64_t m = (int64_t)llround(0.6180339887498949 * (double)full) | 1;
+    auto gcd = [](int64_t a, int64_t b) {
+        while (b) { const int64_t t = a % b; a = b; b = t; }
+        return a;
+    };
+    while (gcd(m, full) != 1) m += 2;
+    return (int32_t)(m % full);
+}
+
 // Largest group <= the requested one whose accumulators fit the LDS limit.
 int fit_group(DeviceState* st, int group, int max_w2) {
     const size_t static_lds = 20480;  // kernel's own shared arrays (~17 KB), rounded up
@@ -474,8 +485,8 @@ si_status check_sched(const si_sched* sc) {
     if (sc->fac_divisor > 0.0f && sc->fac_divisor < 1.0f)
         return fail(SI_E_INVALID, "fac_divisor must be >= 1");
     if (sc->group < 0 || sc->group > kMaxGroup) return fail(SI_E_INVALID, "group must be in [0, 8]");
-    if (sc->order != SI_ORDER_CELL && sc->order != SI_ORDER_GIVEN)
-        return fail(SI_E_INVALID, "order must be SI_ORDER_CELL or SI_ORDER_GIVEN");
+    if (sc->order != SI_ORDER_SPREAD && sc->order != SI_ORDER_CELL && sc->order != SI_ORDER_GIVEN)
+        return fail(SI_E_INVALID, "order must be SI_ORDER_SPREAD, SI_ORDER_CELL or SI_ORDER_GIVEN");
     return SI_OK;
 }
 
@@ -590,9 +601,14 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     if (kind != SI_SCHED_LEARNED) {
         rc = get_table(st, kind, N, n_wg, sched->min_chunk, sched->fac_divisor, &chunks, &n_chunks);
         if (rc != SI_OK) return rc;
-        if (sched->order == SI_ORDER_CELL && scene->n_cells > 1) {
+        if (sched->order != SI_ORDER_GIVEN && scene->n_cells > 1) {
             rc = cell_order(*scene, oriented_idx, N, s, &order_mem, &d.single.perm);
             if (rc != SI_OK) return rc;
+            if (sched->order == SI_ORDER_SPREAD) {
+                d.single.spread_full = (int32_t)(N / 64);
+                d.single.spread_mult = spread_mult(N / 64);
+                if (d.single.spread_mult == 0) d.single.spread_full = 0;
+            }
         }
     }
     d.chunks = chunks;

@@ -90,6 +90,10 @@ struct Item {
     uint32_t* counts;
     int64_t N;
     const int32_t* perm;  // optional iteration -> output position map (learned order)
+    // SI_ORDER_SPREAD: loop position w < 64 spread_full is read from
+    // position 64 ((w / 64) spread_mult mod spread_full) + w mod 64 of perm
+    int32_t spread_full;  // 0 = off
+    int32_t spread_mult;  // coprime to spread_full
 };
 
 struct LaunchDesc {
@@ -171,6 +175,9 @@ si_status make_params(const si_params* prm, SpinParams* out, double* radius);
 si_status check_sched(const si_sched* sc);
 SceneView view_of(const Scene& s);
 int default_group(int W);
+// Stride of SI_ORDER_SPREAD for `full` units: near 0.618 full, coprime to it
+// (0 when there is nothing to spread).
+int32_t spread_mult(int64_t full);
 int fit_group(DeviceState* st, int group, int max_w2);
 int auto_workgroups(DeviceState* st, int max_w2, int group);
 si_status cell_order(const Scene& sc, const int32_t* oriented, int64_t N, hipStream_t s,

@@ -194,7 +194,7 @@ def test_batched_learned(env, use_graph):
     feats = si.si_features(batch[0]["scene"], batch[0]["idx"], batch[0]["params"])
     si.si_cost_model_train(trained, feats, ref[0][1], epochs=3, lr=2e-3, batch=256)
     for model in (si.si_cost_model_create(20), trained):
-        for order in ("cell", "given"):
+        for order in ("spread", "cell", "given"):
             for P in (200, 1500):
                 for b in batch:
                     b["img"].fill_(-1.0)

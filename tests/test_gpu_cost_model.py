@@ -108,7 +108,7 @@ def test_learned_schedule_images_identical(env, prims):
     print("\n[case] learned schedule", flush=True)
     m = si.si_cost_model_create(3)
     si.si_cost_model_train(m, prims["feats"], prims["cnt"], epochs=2, lr=2e-3, batch=2048)
-    for order in ("cell", "given"):
+    for order in ("spread", "cell", "given"):
         img, cnt, st = si.si_generate(prims["scene"], prims["idx"], prims["params"],
                                       si.Sched("learned", model=m, order=order), stats=True)
         torch.cuda.synchronize()

@@ -118,8 +118,10 @@ def test_prims_small_all_schedules(env, mode):
         else:
             np.testing.assert_array_equal(img, base[0])
             np.testing.assert_array_equal(cnt, base[1])
-    # the paper's loop order (oriented_idx as given) and other group sizes
-    for kw in (dict(order="given"), dict(group=1), dict(group=3, order="given")):
+    # the paper's loop order (oriented_idx as given), contiguous cell order
+    # and other group sizes
+    for kw in (dict(order="given"), dict(order="cell"), dict(group=1),
+               dict(group=3, order="given"), dict(group=2, order="cell")):
         img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, mode, "fac", **kw)
         np.testing.assert_array_equal(img, base[0])
         np.testing.assert_array_equal(cnt, base[1])
@@ -280,3 +282,28 @@ def test_repeat_and_permutation_invariance(env):
     c = run(env, xyz[perm], nrm[perm], inv[idx], 32, 0.02, S60, "bilinear", "gss")
     np.testing.assert_array_equal(a[0], c[0])
     np.testing.assert_array_equal(a[1], c[1])
+
+
+def test_spread_order_covers_every_image(env):
+    """SI_ORDER_SPREAD reads units of 64 cell-ordered iterations with a
+    stride coprime to their number: every image is written once, for loop
+    lengths around unit boundaries and a single full unit (spread off), and
+    equals the given-order result for every schedule."""
+    torch, si, _ = env
+    print_case("spread order sizes")
+    xyz, nrm = sg.config_scene("prims100k", M=20000)
+    params = si.Params(16, 0.02, S60)
+    scene = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(),
+                              si.si_support_radius(params))
+    for N in (1, 63, 64, 65, 127, 128, 129, 64 * 97 + 5, 9000):
+        idx = torch.from_numpy(np.random.default_rng(N).permutation(20000)[:N].astype(np.int32)).cuda()
+        ref, rcnt, _ = si.si_generate(scene, idx, params, si.Sched("fac", order="given"))
+        for kind in ("static", "ss", "gss", "fac"):
+            img = torch.full((N, 16, 16), -1.0, dtype=torch.float32, device="cuda")
+            cnt = torch.full((N,), -1, dtype=torch.int32, device="cuda")
+            _, _, st = si.si_generate(scene, idx, params, si.Sched(kind, num_workgroups=61), img,
+                                      cnt, stats=True)
+            torch.cuda.synchronize()
+            assert torch.equal(img, ref) and torch.equal(cnt, rcnt), (N, kind)
+            assert st["pairs_in_support"] == int(rcnt.to(torch.int64).sum()), (N, kind)
+    scene.free()
