@@ -103,7 +103,7 @@ typedef struct si_params {
  *   group           images that share one pass over their common candidate
  *                   points (1..8); 0 = library default
  *   order           SI_ORDER_SPREAD (0): the oriented points sorted by grid
- *                   cell, in units of 64 consecutive iterations, and the
+ *                   cell, in units of 8 consecutive iterations, and the
  *                   units taken with a stride coprime to their number, so
  *                   that every part of the loop holds units from the whole
  *                   scene (chunks of neighbouring images keep sharing

@@ -182,7 +182,7 @@ class Sched:
     model: "CostModel | None" = None
     fallback_to_fac: bool = True
     group: int = 0
-    # "spread": units of 64 cell-ordered iterations spread over the loop;
+    # "spread": units of 8 cell-ordered iterations spread over the loop;
     # "cell": loop over points sorted by grid cell; "given": oriented_idx order
     order: str = "spread"
 

@@ -190,8 +190,8 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
     f.ordered = sched->order != SI_ORDER_GIVEN && f.total_cells > (int64_t)f.items.size();
     if (f.ordered && sched->order == SI_ORDER_SPREAD && !f.learned) {
         for (Item& it : f.items) {
-            it.spread_mult = spread_mult(it.N / 64);
-            it.spread_full = it.spread_mult ? (int32_t)(it.N / 64) : 0;
+            it.spread_mult = spread_mult(it.N / kSpreadUnit);
+            it.spread_full = it.spread_mult ? (int32_t)(it.N / kSpreadUnit) : 0;
         }
     }
     if (f.learned) {

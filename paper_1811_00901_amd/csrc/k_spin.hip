@@ -519,8 +519,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
             __syncthreads();  // s_info reuse
             if (tid < nb) {
                 int w = b0 + tid;
-                if (it.spread_full > 1 && w < it.spread_full * 64)
-                    w = (int)(((long long)(w >> 6) * it.spread_mult) % it.spread_full) * 64 + (w & 63);
+                if (it.spread_full > 1 && w < it.spread_full * kSpreadUnit)
+                    w = (int)(((long long)(w / kSpreadUnit) * it.spread_mult) % it.spread_full) *
+                            kSpreadUnit +
+                        (w & (kSpreadUnit - 1));
                 const int out = it.perm ? it.perm[w] : w;
                 const int o = it.oriented[out];
                 ImgInfo inf;

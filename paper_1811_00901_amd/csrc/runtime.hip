@@ -605,8 +605,8 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
             rc = cell_order(*scene, oriented_idx, N, s, &order_mem, &d.single.perm);
             if (rc != SI_OK) return rc;
             if (sched->order == SI_ORDER_SPREAD) {
-                d.single.spread_full = (int32_t)(N / 64);
-                d.single.spread_mult = spread_mult(N / 64);
+                d.single.spread_full = (int32_t)(N / kSpreadUnit);
+                d.single.spread_mult = spread_mult(N / kSpreadUnit);
                 if (d.single.spread_mult == 0) d.single.spread_full = 0;
             }
         }

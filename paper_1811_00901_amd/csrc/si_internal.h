@@ -32,6 +32,8 @@ constexpr int kSub = 3;
 // key = cell * kSubX + floor(kSubX * frac(x / h)), so that a row's candidate
 // run can be cut at quarter-cell resolution.
 constexpr int kSubX = 4;
+// Iterations per unit of the spread cell order (a power of two).
+constexpr int kSpreadUnit = 8;
 // Cap on the number of grid cells of one scene; a larger box gets bigger cells.
 constexpr int64_t kMaxCells = int64_t(1) << 25;
 
@@ -90,8 +92,9 @@ struct Item {
     uint32_t* counts;
     int64_t N;
     const int32_t* perm;  // optional iteration -> output position map (learned order)
-    // SI_ORDER_SPREAD: loop position w < 64 spread_full is read from
-    // position 64 ((w / 64) spread_mult mod spread_full) + w mod 64 of perm
+    // SI_ORDER_SPREAD: loop position w < U spread_full is read from
+    // position U ((w / U) spread_mult mod spread_full) + w mod U of perm,
+    // U = kSpreadUnit
     int32_t spread_full;  // 0 = off
     int32_t spread_mult;  // coprime to spread_full
 };
