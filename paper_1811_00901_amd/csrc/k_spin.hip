@@ -234,8 +234,23 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
     const int total = row_pref[n_rows];
     gf32x4* gpos = (gf32x4*)sc.pos;
     gf32x4* gnrm = (gf32x4*)sc.nrm;
-    // row cursor: rows [r_lo, r_hi) of the flattened candidate list start at r_st
-    int r = 0, r_lo = 0, r_hi = row_pref[1], r_st = row_start[0];
+    // each wave takes a contiguous quarter of the candidate list (a multiple
+    // of 64) and walks it 64 at a time, so a lane's row cursor crosses few
+    // row ends per step
+    const int quarter = ((total + kBlock - 1) / kBlock) * 64;
+    const int w_beg = min(total, wave * quarter), w_end = min(total, w_beg + quarter);
+    // row cursor: rows [r_lo, r_hi) of the flattened candidate list start at
+    // r_st; first row: the last r with row_pref[r] <= this lane's first k
+    int r = 0;
+    {
+        const int k0 = min(w_beg + lane, max(total - 1, 0));
+        int hi = max(n_rows - 1, 0);
+        while (r < hi) {
+            const int mid = (r + hi + 1) >> 1;
+            if (row_pref[mid] <= k0) r = mid; else hi = mid - 1;
+        }
+    }
+    int r_lo = row_pref[r], r_hi = row_pref[r + 1], r_st = row_start[r];
     auto fetch = [&](int k, f32x4& x, f32x4& m) {
         while (k >= r_hi) {
             ++r;
@@ -250,15 +265,15 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
     int qn = 0;
     const bool angle_on = rfl(p.angle_on) != 0;
     f32x4 xn = {0.0f, 0.0f, 0.0f, 0.0f}, mn = xn;
-    int kb = wave * 64;
-    bool vn = kb + lane < total;
+    int kb = w_beg;
+    bool vn = kb + lane < w_end;
     if (vn) fetch(kb + lane, xn, mn);
-    for (; kb < total; kb += kBlock) {
+    for (; kb < w_end; kb += 64) {
         const f32x4 x = xn, m = mn;
         const bool valid = vn;
         const uint64_t vmask = __builtin_amdgcn_ballot_w64(valid);
-        vn = kb + kBlock + lane < total;
-        if (vn) fetch(kb + kBlock + lane, xn, mn);
+        vn = kb + 64 + lane < w_end;
+        if (vn) fetch(kb + 64 + lane, xn, mn);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (g < ng) {
