@@ -25,7 +25,7 @@ Also reported (outside the timed steps):
     bounded sample of the main workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--no-schedules] [--no-batch] [--no-extent]
+                    [--no-schedules] [--no-batch] [--no-extent] [--no-paper-shape]
                     [--copy-calibration BYTES]
 """
 from __future__ import annotations
@@ -98,6 +98,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-schedules", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-paper-shape", action="store_true")
     ap.add_argument("--no-extent", action="store_true",
                     help="stop after the timed steps (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -253,6 +254,42 @@ def batched(torch, si, sg, model):
     return out
 
 
+# The paper's throughput, derived from its weak-scaling text (Section 5.1):
+# 64K images in 20.5 s with SS on 160 Xeon E5-2640 cores, every image testing
+# all of ~826K points -- end-to-end wall time including MPI.  Context only.
+PAPER_TESTS_PER_S_160_CORES_SS = 64_000 * 826_000 / 20.5
+
+
+def paper_shape(torch, si, sg):
+    """The shape of the paper's experiments: 826K points, the first 10 %
+    oriented, W = 5, B = 0.1 x mean nearest-neighbour spacing, S = 2 pi,
+    brute force over all points (a single-cell scene); STATIC, SS and FAC."""
+    cfg = sg.CONFIGS["paper826k"]
+    xyz, nrm = sg.config_scene("paper826k")
+    M, N = xyz.shape[0], cfg.N
+    B = 0.1 * sg.mean_nn_spacing(xyz)
+    params = si.Params(cfg.W, B, cfg.support_angle)
+    scene = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(), 0.0)
+    idx = torch.arange(N, dtype=torch.int32, device="cuda")
+    img = torch.empty((N, cfg.W, cfg.W), dtype=torch.float32, device="cuda")
+    cnt = torch.empty((N,), dtype=torch.int32, device="cuda")
+    out = {"workload": f"paper826k: {M} points, first {N} oriented, W={cfg.W}, B={B:.6f} "
+                       f"(0.1 x mean nearest-neighbour spacing), S=2 pi, brute force",
+           "pair_tests": N * M}
+    for kind in ("static", "ss", "fac"):
+        sch = si.Sched(kind)
+        ms = timed(torch, lambda: si.si_generate(scene, idx, params, sch, img, cnt), reps=5, warm=1)
+        out[kind] = {"ms": ms, "pair_tests_per_s": N * M / (ms["median"] * 1e-3),
+                     "images_per_s": N / (ms["median"] * 1e-3)}
+    out["in_support_pairs"] = int(cnt.to(torch.int64).sum())
+    out["paper_context"] = {
+        "pair_tests_per_s": PAPER_TESTS_PER_S_160_CORES_SS,
+        "hardware": "160 Xeon E5-2640 cores (8 nodes), MPI, EPSIA-SS, Ramesses ~826K points",
+        "ratio_fac_to_paper": out["fac"]["pair_tests_per_s"] / PAPER_TESTS_PER_S_160_CORES_SS}
+    scene.free()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,20 +383,39 @@ def main():
     del ext_img
     ops = OPS_PER_EXTENT_PAIR * extent_pairs + OPS_PER_SUPPORT_PAIR * pairs
     achieved = ops / (kernel_ms * 1e-3)
+    # measured device ceilings (the published peak bounds them)
+    probes = {k: si.si_peak_probe(k) for k in ("valu", "lds_atomic_seq", "lds_atomic_random",
+                                                 "hbm_copy")}
+    atomics = ATOMICS_PER_SUPPORT_PAIR * pairs
+    traffic = measured_traffic()
     roofline = {
         "bound": "alu",
         "achieved": achieved / 1e12,
         "peak": PEAK_VALU_OPS / 1e12,
         "unit": "TOP/s",
         "frac": achieved / PEAK_VALU_OPS,
-        "traffic": measured_traffic(),
+        "traffic": traffic,
         "kernel": "k_spin",
         "kernel_ms": kernel_ms,
         "in_extent_pairs": extent_pairs,
         "in_support_pairs": pairs,
         "pairs_tested": int(st["pairs_tested"]),
-        "lds_atomics_per_s": ATOMICS_PER_SUPPORT_PAIR * pairs / (kernel_ms * 1e-3),
+        "lds_atomics_per_s": atomics / (kernel_ms * 1e-3),
+        "measured_peaks": {"valu_lane_ops_per_s": probes["valu"],
+                           "lds_atomics_per_s_conflict_free": probes["lds_atomic_seq"],
+                           "lds_atomics_per_s_random_1024_bins": probes["lds_atomic_random"],
+                           "hbm_bytes_per_s_copy": probes["hbm_copy"]},
+        "frac_of_measured_valu": achieved / probes["valu"],
+        "frac_of_measured_lds_atomics": (atomics / (kernel_ms * 1e-3)) / probes["lds_atomic_random"],
+        # L2<->fabric bytes per second against an HBM copy: above 1 means most
+        # of the traffic is served by the MALL, not HBM
+        "fabric_rate_vs_hbm_copy": (traffic / (kernel_ms * 1e-3) / probes["hbm_copy"]
+                                    if traffic else None),
+        # T_roof = max(algorithmic VALU work / measured VALU peak,
+        #              LDS atomics / measured random-bin atomic peak)
+        "t_roof_ms": 1e3 * max(ops / probes["valu"], atomics / probes["lds_atomic_random"]),
     }
+    roofline["frac_of_t_roof"] = roofline["t_roof_ms"] / kernel_ms
 
     # ---- learned cost model ----
     model, cm_info = None, None
@@ -421,6 +477,14 @@ def main():
         batch = batched(torch, si, sg, model)
         log(f"[bench] batched: {batch}")
 
+    # ---- the paper's workload shape (context) ----
+    paper = None
+    if not args.no_paper_shape:
+        log("[bench] paper-shape run")
+        paper = paper_shape(torch, si, sg)
+        log(f"[bench] paper shape: FAC {paper['fac']['pair_tests_per_s']:.3g} pair tests/s "
+            f"({paper['paper_context']['ratio_fac_to_paper']:.0f}x the paper's 160 cores)")
+
     # ---- FP64 CPU oracle on a bounded sample of the main workload ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -470,6 +534,7 @@ def main():
         "schedules": sched_res,
         "cost_model": cm_info,
         "batched": batch,
+        "paper_shape": paper,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

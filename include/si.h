@@ -361,6 +361,30 @@ const char* si_status_string(si_status status);
 const char* si_last_error(void);
 int32_t si_abi_version(void);
 
+/*
+ * Measured throughput ceilings of the device, for reading the spin kernel's
+ * roofline (the VALU lane-operations of its pair tests and binning, its LDS
+ * atomics, its HBM image stores).  One warm-up and one timed launch, HIP
+ * events; synchronises the stream.  *value (host) receives
+ *   SI_PROBE_VALU                FP32 FMA lane-operations per second (16
+ *                                independent chains per lane, no packed
+ *                                instructions: the code the kernel emits)
+ *   SI_PROBE_LDS_ATOMIC_SEQ      ds_add_u32 per second, 64 consecutive words
+ *                                per wave-instruction (conflict free)
+ *   SI_PROBE_LDS_ATOMIC_RANDOM   ds_add_u32 per second, random words of a
+ *                                1,024-bin image (the binning pattern)
+ *   SI_PROBE_HBM_COPY            bytes per second read plus written by a
+ *                                1 GiB float4 copy
+ * The probe allocates and frees its own device memory (stream-ordered).
+ */
+enum {
+    SI_PROBE_VALU = 0,
+    SI_PROBE_LDS_ATOMIC_SEQ = 1,
+    SI_PROBE_LDS_ATOMIC_RANDOM = 2,
+    SI_PROBE_HBM_COPY = 3
+};
+si_status si_peak_probe(int32_t kind, double* value, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

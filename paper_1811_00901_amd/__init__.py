@@ -25,13 +25,14 @@ __all__ = [
     "si_build_scene", "si_generate", "si_generate_batched", "si_features",
     "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict", "si_cost_model_gradient",
     "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
-    "si_set_kernel_events", "si_autotune",
-    "SCHED", "MODE",
+    "si_set_kernel_events", "si_autotune", "si_peak_probe",
+    "SCHED", "MODE", "PROBE",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libspinimg.so")
 
 SCHED = {"static": 0, "ss": 1, "gss": 2, "fac": 3, "learned": 4}
+PROBE = {"valu": 0, "lds_atomic_seq": 1, "lds_atomic_random": 2, "hbm_copy": 3}
 MODE = {"bilinear": 0, "ceil": 1}
 ORDER = {"spread": 0, "given": 1, "cell": 2}
 STATUS = {0: "SI_OK", -1: "SI_E_INVALID", -2: "SI_E_OOM", -3: "SI_E_DEVICE", -4: "SI_E_UNSUPPORTED"}
@@ -113,6 +114,7 @@ def lib():
             "si_status_string": (ctypes.c_char_p, [I32]),
             "si_last_error": (ctypes.c_char_p, []),
             "si_abi_version": (I32, []),
+            "si_peak_probe": (I32, [I32, ctypes.POINTER(ctypes.c_double), P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -158,6 +160,14 @@ def si_set_kernel_events(begin, end):
 
 def si_abi_version() -> int:
     return int(lib().si_abi_version())
+
+
+def si_peak_probe(kind: str, stream=None) -> float:
+    """Measured device ceiling: 'valu' (FP32 FMA lane-ops/s), 'lds_atomic_seq'
+    / 'lds_atomic_random' (ds_add_u32/s), 'hbm_copy' (bytes/s read + written)."""
+    v = ctypes.c_double()
+    _check(lib().si_peak_probe(PROBE[kind], ctypes.byref(v), _stream(stream)))
+    return float(v.value)
 
 
 @dataclass

@@ -35,6 +35,7 @@ __all__ = [
     "config_scene",
     "batch_specs",
     "batch_scene",
+    "mean_nn_spacing",
     "CONFIGS",
 ]
 
@@ -214,6 +215,11 @@ CONFIGS = {
     "sphere2k": SceneConfig("sphere2k", 2000, 2000, 16, 0.05, float(np.float32(math.pi / 3)), 1),
     "prims100k": SceneConfig("prims100k", 100_000, 65_536, 32, 0.02, float(np.float32(math.pi / 3)), 2),
     "clustered2m": SceneConfig("clustered2m", 2_000_000, 2_000_000, 32, 0.02, float(np.float32(math.pi / 3)), 3),
+    # the shape of the paper's experiments (826K points, the first 10 % oriented,
+    # W = 5, B = 0.1 x mesh resolution, S = 2 pi, brute force): bin is NaN here
+    # and is 0.1 x mean_nn_spacing of the generated points
+    "paper826k": SceneConfig("paper826k", 826_000, 82_600, 5, float("nan"),
+                             float(np.float32(2 * math.pi)), 10),
 }
 
 
@@ -228,7 +234,20 @@ def config_scene(name: str, M: int | None = None):
         return primitives_scene(m, 20, cfg.seed, box=10.0)
     if name == "clustered2m":
         return primitives_scene(m, 400, cfg.seed, box=40.0, clusters=16, cluster_sigma=1.0)
+    if name == "paper826k":
+        return primitives_scene(m, 165, cfg.seed, box=20.0)
     raise KeyError(name)
+
+
+def mean_nn_spacing(xyz: np.ndarray, sample: int = 20_000, seed: int = 0) -> float:
+    """Mean distance from a point to its nearest other point (the "mesh
+    resolution"), estimated on a seeded sample of the points."""
+    from scipy.spatial import cKDTree
+    pts = np.asarray(xyz, dtype=np.float64)
+    tree = cKDTree(pts)
+    idx = rng(seed).choice(len(pts), min(sample, len(pts)), replace=False)
+    d, _ = tree.query(pts[idx], k=2)
+    return float(d[:, 1].mean())
 
 
 def batch_specs(n_scenes: int = 256, base_seed: int = 4000,
