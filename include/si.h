@@ -235,7 +235,12 @@ typedef struct si_batch_item {
  * schedule whose chunks never span two scenes.  use_graph = 1 captures the
  * launch in a HIP graph that is cached and replayed while the item list
  * (pointers, sizes, params) and schedule are unchanged.  sched->kind is any
- * SI_SCHED_* (LEARNED uses sched->model on every scene).  Every item is
+ * SI_SCHED_*.  SI_SCHED_LEARNED plans the whole batch on the device before
+ * the launch (inside the graph): features and predicted costs of every
+ * image, units of 16 iterations that never cross an item, one
+ * longest-first order of all units, factoring on predicted cost into
+ * chunks, and each chunk split into its runs of one item; at most 4,096
+ * workgroups (1,024 for si_generate).  Every item is
  * validated as in si_generate; results are identical to one si_generate per
  * item.  Items with N == 0 are skipped.  Without a graph the call stages its
  * tables and synchronises the stream once before launching; the first call
@@ -255,8 +260,8 @@ si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
  * LEARNED: 1.5, 2, 3, 4) and min_chunk (dynamic techniques: 0, 4, 16), by two
  * sweeps of coordinate descent from the library's defaults for the workload,
  * at most max_trials timed candidates (each the median of two launches after
- * a warm-up).  Every candidate's
- * images and counts must give the same 64-bit checksum as the first one,
+ * a warm-up).  Every candidate's images and counts must give the same 64-bit
+ * checksum as the first one,
  * else SI_E_DEVICE.  The winner is written to *best (kind and order filled,
  * model NULL) and its time to *best_ms (host, may be NULL).  Winners are
  * cached per (device, kind, use_graph, image widths, size class) in memory
