@@ -240,8 +240,7 @@ typedef struct si_batch_item {
  * image, units of 16 iterations that never cross an item, one
  * longest-first order of all units, factoring on predicted cost into
  * chunks, and each chunk split into its runs of one item; at most 4,096
- * workgroups (1,024 for si_generate).  Every item is
- * validated as in si_generate; results are identical to one si_generate per
+ * workgroups, as in si_generate.  Every item is validated as in si_generate; results are identical to one si_generate per
  * item.  Items with N == 0 are skipped.  Without a graph the call stages its
  * tables and synchronises the stream once before launching; the first call
  * with a new item list in graph mode also synchronises (capture).  The graph
@@ -256,7 +255,7 @@ si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
  * Autotuner: picks the launch parameters of a workload (the items as for
  * si_generate_batched; one item for a single scene) for scheduling technique
  * `kind`.  Tuned: group (images per shared candidate pass, from 1, 2, 4, 6,
- * 8), num_workgroups (2, 3, 4, 6 or 8 per compute unit), fac_divisor (FAC and
+ * 8), num_workgroups (2, 3, 4, 5, 6 or 8 per compute unit), fac_divisor (FAC and
  * LEARNED: 1.5, 2, 3, 4) and min_chunk (dynamic techniques: 0, 4, 16), by two
  * sweeps of coordinate descent from the library's defaults for the workload,
  * at most max_trials timed candidates (each the median of two launches after

@@ -252,7 +252,7 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
             rc = try_set(c);
         }
         // persistent workgroups per CU
-        for (int per_cu : {4, 6, 3, 8, 2}) {
+        for (int per_cu : {4, 5, 6, 3, 8, 2}) {
             if (rc != SI_OK || st->n_cu * per_cu == cur.num_workgroups) continue;
             si_sched c = cur;
             c.num_workgroups = st->n_cu * per_cu;

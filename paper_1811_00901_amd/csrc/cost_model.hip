@@ -393,7 +393,9 @@ __global__ void __launch_bounds__(256) k_unit_gather(const int32_t* __restrict__
 
 // Single block: factoring on predicted cost over the LPT order (cpre, ipre:
 // exclusive prefix sums of cost and iterations, n_units + 1 entries), the
-// chunk table and its length.
+// chunk table and its length.  Thread t computes chunks t*kPerThread+1 ..
+// (t+1)*kPerThread of each batch of P <= kMaxLearnedP.
+constexpr int kPerThread = kMaxLearnedP / 1024;
 __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restrict__ cpre,
                                                          const int64_t* __restrict__ ipre,
                                                          int64_t n_units, int P, float divisor,
@@ -403,7 +405,7 @@ __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restri
     const int64_t total = cpre[n_units];
     __shared__ int64_t start;
     __shared__ int emitted;
-    __shared__ int64_t ends[1025];
+    __shared__ int64_t ends[kMaxLearnedP + 1];
     __shared__ int pos[1024];
     if (tid == 0) {
         start = 0;
@@ -411,13 +413,14 @@ __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restri
     }
     __syncthreads();
     const double x = divisor > 0.0f ? (double)divisor : 2.0;
-    const int j = tid + 1;  // this thread's chunk of the batch (P <= 1024)
     while (start < n_units) {
         const int64_t st = start;
         const int64_t R = total - cpre[st];
         const int64_t cb = max((int64_t)1, (int64_t)ceil((double)R / (x * (double)P)));
         // end of chunk j (1..P): first k > st with cpre[k] - cpre[st] >= j * cb, else n_units
-        if (j <= P) {
+        for (int r = 0; r < kPerThread; ++r) {
+            const int j = tid * kPerThread + r + 1;
+            if (j > P) break;
             const int64_t target = cpre[st] + (int64_t)j * cb;
             int64_t lo = st + 1, hi = n_units;
             while (lo < hi) {
@@ -429,8 +432,12 @@ __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restri
         if (tid == 0) ends[0] = st;
         __syncthreads();
         // non-empty chunks of the batch, written in order (block prefix sum)
-        const int f = (j <= P && ends[j] > ends[j - 1]) ? 1 : 0;
-        pos[tid] = f;
+        int mine = 0;
+        for (int r = 0; r < kPerThread; ++r) {
+            const int j = tid * kPerThread + r + 1;
+            if (j <= P && ends[j] > ends[j - 1]) ++mine;
+        }
+        pos[tid] = mine;
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
             const int t = tid >= off ? pos[tid - off] : 0;
@@ -438,12 +445,16 @@ __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restri
             pos[tid] += t;
             __syncthreads();
         }
-        if (f) {
-            Chunk c;
-            c.item = 0;
-            c.start = (int32_t)ipre[ends[j - 1]];
-            c.end = (int32_t)ipre[ends[j]];
-            chunks[emitted + pos[tid] - 1] = c;
+        int w = emitted + pos[tid] - mine;
+        for (int r = 0; r < kPerThread; ++r) {
+            const int j = tid * kPerThread + r + 1;
+            if (j <= P && ends[j] > ends[j - 1]) {
+                Chunk c;
+                c.item = 0;
+                c.start = (int32_t)ipre[ends[j - 1]];
+                c.end = (int32_t)ipre[ends[j]];
+                chunks[w++] = c;
+            }
         }
         __syncthreads();
         if (tid == 0) {
@@ -706,7 +717,8 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
                         LearnedPlan* plan, hipStream_t s) {
     const si_cost_model* model = sched->model;
     if (!model) return fail(SI_E_UNSUPPORTED, "learned schedule without a model");
-    if (n_wg > 1024) return fail(SI_E_INVALID, "the learned schedule supports at most 1024 workgroups");
+    if (n_wg > kMaxLearnedP)
+        return fail(SI_E_INVALID, "the learned schedule supports at most 4096 workgroups");
     const int64_t n_units = (N + kUnit - 1) / kUnit;
     const int64_t n_tiles = (n_units + kTile - 1) / kTile;
     const int64_t nt = scan_tmp_elems(scene->n_cells);

@@ -102,41 +102,61 @@ __device__ __forceinline__ void cell_xyz(int cell, const int* dims, int& cx, int
     cz = t / dims[1];
 }
 
-// Accumulate one in-support pair, given beta and alpha^2, into a u32 or u64
-// LDS image.  Bilinear: the four 16.16 weights are rounded so that they sum
-// to exactly 65536; they tolerate the 1-ulp hardware square root (a one-ulp
-// change of u moves at most one quantisation step).  Ceil: bin += 65536, with
-// the correctly rounded square root since ceil(alpha/B) jumps at integers.
-// Every path that bins a pair uses this function, so results do not depend
-// on which path ran.
+// Position of an in-support pair in the image, given beta and alpha^2.
+// Bilinear: 16.16 fixed-point V = round(v 2^16), U = round(u 2^16) of
+// v = W/2 - beta/B, u = alpha/B, kept below (W - 1) 2^16 so that the 2 x 2
+// footprint stays inside; they tolerate the 1-ulp hardware square root (a
+// one-ulp change of u moves at most one quantisation step).  alpha^2 of an
+// in-support pair is finite, so the clamp at zero is a median.
+__device__ __forceinline__ void bilinear_pos(const SpinParams& p, float beta, float a2,
+                                             uint32_t& V, uint32_t& U) {
+    const float s = 65536.0f;
+    const float top = (float)(((p.W - 1) << 16) - 1);
+    a2 = __builtin_amdgcn_fmed3f(a2, 0.0f, 3.0e38f);
+    const float vf = fmaf(-beta, p.inv_bin * s, fmaf(p.half, s, 0.5f));
+    const float uf = fmaf(__builtin_amdgcn_sqrtf(a2), p.inv_bin * s, 0.5f);
+    V = (uint32_t)__builtin_amdgcn_fmed3f(vf, 0.0f, top);
+    U = (uint32_t)__builtin_amdgcn_fmed3f(uf, 0.0f, top);
+}
+// The four weights of (V, U), rounded so that they sum to exactly 65536:
+// w00 at (row, col), w01 at (row, col + 1), w10 at (row + 1, col), w11 at
+// (row + 1, col + 1) with row = V >> 16, col = U >> 16.
+__device__ __forceinline__ void bilinear_weights(uint32_t V, uint32_t U, uint32_t& w00,
+                                                 uint32_t& w01, uint32_t& w10, uint32_t& w11) {
+    const uint32_t qa = V & 0xffffu, qb = U & 0xffffu;
+    w11 = (__umul24(qa, qb) + 32768u) >> 16;
+    w10 = qa - w11;
+    w01 = qb - w11;
+    w00 = 65536u - qb - w10;
+}
+// Ceil: bin (k, l) = (ceil v, ceil u) clamped to the image, with the
+// correctly rounded square root since ceil(alpha/B) jumps at integers.
+__device__ __forceinline__ void ceil_pos(const SpinParams& p, float beta, float a2, int& k, int& l) {
+    a2 = __builtin_amdgcn_fmed3f(a2, 0.0f, 3.0e38f);
+    const float v = fmaf(-beta, p.inv_bin, p.half);
+    const float u = sqrtf(a2) * p.inv_bin;
+    k = min(max((int)ceilf(v), 0), p.W - 1);
+    l = min(max((int)ceilf(u), 0), p.W - 1);
+}
+
+// Accumulate one in-support pair into a u32 or u64 LDS image.  Every path
+// that bins a pair computes its position and weights with the functions
+// above, so results do not depend on which path ran.
 template <int MODE, typename Acc>
 __device__ __forceinline__ void bin_pair(Acc* img, const SpinParams& p, float beta, float a2) {
     const int W = p.W;
-    a2 = fmaxf(a2, 0.0f);
     if (MODE == SI_BIN_BILINEAR) {
-        // 16.16 fixed-point positions V = round(v 2^16), U = round(u 2^16),
-        // kept below (W - 1) 2^16 so that the 2 x 2 footprint stays inside
-        const float s = 65536.0f;
-        const float top = (float)(((W - 1) << 16) - 1);
-        const float vf = fmaf(-beta, p.inv_bin * s, fmaf(p.half, s, 0.5f));
-        const float uf = fmaf(__builtin_amdgcn_sqrtf(a2), p.inv_bin * s, 0.5f);
-        const uint32_t V = (uint32_t)__builtin_amdgcn_fmed3f(vf, 0.0f, top);
-        const uint32_t U = (uint32_t)__builtin_amdgcn_fmed3f(uf, 0.0f, top);
-        const uint32_t qa = V & 0xffffu, qb = U & 0xffffu;
-        const uint32_t q11 = (__umul24(qa, qb) + 32768u) >> 16;
-        const uint32_t w10 = qa - q11, w01 = qb - q11;
+        uint32_t V, U, w00, w01, w10, w11;
+        bilinear_pos(p, beta, a2, V, U);
+        bilinear_weights(V, U, w00, w01, w10, w11);
         Acc* r0 = img + __umul24(V >> 16, (uint32_t)W) + (U >> 16);
-        atomicAdd(r0, (Acc)(65536u - qb - w10));
+        atomicAdd(r0, (Acc)w00);
         atomicAdd(r0 + 1, (Acc)w01);
         atomicAdd(r0 + W, (Acc)w10);
-        atomicAdd(r0 + W + 1, (Acc)q11);
+        atomicAdd(r0 + W + 1, (Acc)w11);
     } else {
-        const float v = fmaf(-beta, p.inv_bin, p.half);
-        const float u = sqrtf(a2) * p.inv_bin;
-        int k = (int)ceilf(v);
-        int l = (int)ceilf(u);
-        k = min(max(k, 0), W - 1);
-        l = min(max(l, 0), W - 1);
+        int k, l;
+        ceil_pos(p, beta, a2, k, l);
         atomicAdd(img + k * W + l, (Acc)65536u);
     }
 }
@@ -188,31 +208,73 @@ __device__ __forceinline__ void candidate_pass(const SceneView& sc, const SpinPa
     }
 }
 
-// Queue of one wave's in-support pairs: (beta, alpha^2) and the image slot.
-constexpr int kQueue = 256;  // entries per wave
+// Queue of one wave's in-support pairs, three arrays of kQueue words: beta,
+// alpha^2 and the LDS byte address of the image's accumulators, so that one
+// address serves an entry's three words.
+constexpr int kQueue = 224;  // entries per wave
+constexpr int kRounds = (kQueue + 63) / 64;  // binning rounds of a full queue
+struct WaveQueue {
+    float beta[kQueue];
+    float a2[kQueue];
+    uint32_t img[kQueue];
+};
 
 typedef __attribute__((address_space(1))) const f32x4 gf32x4;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+__device__ __forceinline__ uint32_t lds_address(const void* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+__device__ __forceinline__ uint32_t* lds_pointer(uint32_t a) {
+    return (uint32_t*)(lds_u32*)(uintptr_t)a;
+}
 
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
-// Bin the queued pairs of this wave densely (lane e takes entries e, e+64, ...).
+// Bin the queued pairs of this wave densely: lane l takes entries l*T ..
+// l*T+T-1 (T = rounds), so entries appended together (neighbouring points,
+// often the same bins) go to different rounds.
 template <int MODE>
-__device__ __forceinline__ void flush_queue(const SpinParams& p, uint32_t* acc, const float2* q_ba,
-                                            const uint32_t* q_g, int qn) {
+__device__ __forceinline__ void flush_queue(const SpinParams& p, const WaveQueue* q, int qn) {
     const int lane = threadIdx.x & 63;
-    const uint32_t w2 = (uint32_t)(p.W * p.W) + 4u;  // padded image stride
+    const uint32_t row_bytes = (uint32_t)p.W * 4u;
     wave_sync_lds();
-    // lane l takes entries l*T .. l*T+T-1 (T = rounds): entries appended
-    // together (neighbouring points, often the same bins) go to different rounds
+    // every round's entry is read before any is binned (indices clamped to
+    // the queue; entries at or beyond qn are read but not binned)
     const int T = (qn + 63) >> 6;
-    for (int t = 0; t < T; ++t) {
+    float bq[kRounds], aq[kRounds];
+    uint32_t iq[kRounds];
+#pragma unroll
+    for (int t = 0; t < kRounds; ++t) {
+        const int e = min(lane * T + t, kQueue - 1);
+        bq[t] = q->beta[e];
+        aq[t] = q->a2[e];
+        iq[t] = q->img[e];
+    }
+#pragma unroll
+    for (int t = 0; t < kRounds; ++t) {
         const int e = lane * T + t;
-        if (e < qn) {
-            const float2 ba = q_ba[e];
-            bin_pair<MODE>(acc + __umul24(q_g[e], w2), p, ba.x, ba.y);
+        if (t < T && e < qn) {
+            const float beta = bq[t], a2 = aq[t];
+            const uint32_t img = iq[t];
+            if (MODE == SI_BIN_BILINEAR) {
+                uint32_t V, U, w00, w01, w10, w11;
+                bilinear_pos(p, beta, a2, V, U);
+                bilinear_weights(V, U, w00, w01, w10, w11);
+                uint32_t* r0 = lds_pointer(img + __umul24(V >> 16, row_bytes) + ((U >> 16) << 2));
+                atomicAdd(r0, w00);
+                atomicAdd(r0 + 1, w01);
+                uint32_t* r1 = lds_pointer(img + __umul24(V >> 16, row_bytes) + row_bytes + ((U >> 16) << 2));
+                atomicAdd(r1, w10);
+                atomicAdd(r1 + 1, w11);
+            } else {
+                int k, l;
+                ceil_pos(p, beta, a2, k, l);
+                atomicAdd(lds_pointer(img + (uint32_t)(k * p.W + l) * 4u), 65536u);
+            }
         }
     }
     wave_sync_lds();
@@ -220,27 +282,33 @@ __device__ __forceinline__ void flush_queue(const SpinParams& p, uint32_t* acc, 
 
 // Test every candidate of the group's rows against `ng` images; pairs in
 // support are appended to the wave's LDS queue and binned when it fills.
-// Each lane walks candidates k = wave*64 + lane, +256, ... with the next
-// candidate's loads issued before the current one is tested.
+// Each wave takes a contiguous quarter of the candidate list (a multiple of
+// 64) and walks it 64 at a time, the next candidates' loads issued before the
+// current ones are tested.  The loop bounds and the queue fill are
+// wave-uniform, so loop control stays scalar.
 // cnt: per-image in-support counts of this wave (wave-uniform).
-template <int MODE, int G>
+template <int MODE, int G, bool ANGLE>
 __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const SpinParams& p,
                                                  const GroupImg* gi, int ng, uint32_t* acc,
                                                  const int* row_start, const int* row_pref,
-                                                 int n_rows, float2* q_ba, uint32_t* q_g,
-                                                 uint32_t* cnt) {
+                                                 int n_rows, WaveQueue* q, uint32_t* cnt) {
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int total = row_pref[n_rows];
-    gf32x4* gpos = (gf32x4*)sc.pos;
-    gf32x4* gnrm = (gf32x4*)sc.nrm;
-    // each wave takes a contiguous quarter of the candidate list (a multiple
-    // of 64) and walks it 64 at a time, so a lane's row cursor crosses few
-    // row ends per step
+    const int wave = rfl((int)(threadIdx.x >> 6));
+    const int total = rfl(row_pref[n_rows]);
+    // the wave's queue at a scalar LDS address, so that appends compute one
+    // vector address per lane
+    q = (WaveQueue*)lds_pointer((uint32_t)rfl((int)lds_address(q)));
+    const char* gpos = (const char*)sc.pos;
+    const char* gnrm = (const char*)sc.nrm;
+    const int w2p = p.W * p.W + 4;  // padded image stride
+    uint32_t img_at[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) img_at[g] = lds_address(acc + g * w2p);
     const int quarter = ((total + kBlock - 1) / kBlock) * 64;
     const int w_beg = min(total, wave * quarter), w_end = min(total, w_beg + quarter);
-    // row cursor: rows [r_lo, r_hi) of the flattened candidate list start at
-    // r_st; first row: the last r with row_pref[r] <= this lane's first k
+    // row cursor: the lane's current row ends at candidate r_hi, and its
+    // candidate k is point k + r_off; first row: the last r with
+    // row_pref[r] <= this lane's first k
     int r = 0;
     {
         const int k0 = min(w_beg + lane, max(total - 1, 0));
@@ -250,30 +318,27 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
             if (row_pref[mid] <= k0) r = mid; else hi = mid - 1;
         }
     }
-    int r_lo = row_pref[r], r_hi = row_pref[r + 1], r_st = row_start[r];
+    int r_hi = row_pref[r + 1], r_off = row_start[r] - row_pref[r];
     auto fetch = [&](int k, f32x4& x, f32x4& m) {
         while (k >= r_hi) {
             ++r;
-            r_lo = r_hi;
+            r_off = row_start[r] - r_hi;
             r_hi = row_pref[r + 1];
-            r_st = row_start[r];
         }
-        const int j = r_st + (k - r_lo);
-        x = gpos[j];
-        m = gnrm[j];
+        const uint32_t off = (uint32_t)(k + r_off) << 4;
+        x = *(gf32x4*)(gpos + off);
+        m = *(gf32x4*)(gnrm + off);
     };
     int qn = 0;
-    const bool angle_on = rfl(p.angle_on) != 0;
     f32x4 xn = {0.0f, 0.0f, 0.0f, 0.0f}, mn = xn;
     int kb = w_beg;
-    bool vn = kb + lane < w_end;
-    if (vn) fetch(kb + lane, xn, mn);
+    if (lane < w_end - kb) fetch(kb + lane, xn, mn);
     for (; kb < w_end; kb += 64) {
         const f32x4 x = xn, m = mn;
-        const bool valid = vn;
+        const int lim = w_end - kb;
+        const bool valid = lane < lim;
         const uint64_t vmask = __builtin_amdgcn_ballot_w64(valid);
-        vn = kb + 64 + lane < w_end;
-        if (vn) fetch(kb + 64 + lane, xn, mn);
+        if (lane < lim - 64) fetch(kb + 64 + lane, xn, mn);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (g < ng) {
@@ -293,7 +358,7 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
                 uint64_t mask = __builtin_amdgcn_ballot_w64(b0) & __builtin_amdgcn_ballot_w64(b1) &
                                 __builtin_amdgcn_ballot_w64(b2) & vmask;
                 bool in = b0 & b1 & b2 & valid;
-                if (angle_on) {
+                if (ANGLE) {
                     const float c = fmaf(gi[g].nz, m[2], fmaf(gi[g].ny, m[1], gi[g].nx * m[0]));
                     const bool b3 = c >= p.cos_s;
                     mask &= __builtin_amdgcn_ballot_w64(b3);
@@ -301,24 +366,26 @@ __device__ __forceinline__ void candidate_pass_q(const SceneView& sc, const Spin
                 }
                 if (mask) {
                     if (in) {
-                        const int slot = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                                  (uint32_t)(mask >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                        q_ba[slot] = make_float2(beta, a2);
-                        q_g[slot] = (uint32_t)g;
+                        // rank among the passing lanes; the queue's fill is
+                        // added to the scalar base
+                        const uint32_t slot = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                        (q->beta + qn)[slot] = beta;
+                        (q->a2 + qn)[slot] = a2;
+                        (q->img + qn)[slot] = img_at[g];
                     }
                     const int c = __popcll(mask);
                     qn += c;
                     cnt[g] += c;
-                    if (qn > kQueue - 64) {
-                        flush_queue<MODE>(p, acc, q_ba, q_g, qn);
+                    if (__builtin_expect(qn > kQueue - 64, 0)) {
+                        flush_queue<MODE>(p, q, qn);
                         qn = 0;
                     }
                 }
             }
         }
     }
-    if (qn) flush_queue<MODE>(p, acc, q_ba, q_g, qn);
+    if (qn) flush_queue<MODE>(p, q, qn);
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -460,33 +527,43 @@ __device__ __forceinline__ void rows_emit(const SceneView& sc, const int lo[3], 
 }
 
 template <int G>
-__device__ __forceinline__ void run_group_pass(int mode, const SceneView& sc, const SpinParams& p,
+__device__ __forceinline__ void run_group_pass(const SceneView& sc, const SpinParams& p,
                                                const GroupImg* gi, int ng, uint32_t* acc,
                                                const int* row_start, const int* row_pref,
-                                               int n_rows, float2* q_ba, uint32_t* q_g,
-                                               uint32_t* cnt) {
-    if (mode == SI_BIN_BILINEAR)
-        candidate_pass_q<SI_BIN_BILINEAR, G>(sc, p, gi, ng, acc, row_start, row_pref, n_rows,
-                                             q_ba, q_g, cnt);
-    else
-        candidate_pass_q<SI_BIN_CEIL, G>(sc, p, gi, ng, acc, row_start, row_pref, n_rows, q_ba,
-                                         q_g, cnt);
+                                               int n_rows, WaveQueue* q, uint32_t* cnt) {
+    if (p.mode == SI_BIN_BILINEAR) {
+        if (p.angle_on)
+            candidate_pass_q<SI_BIN_BILINEAR, G, true>(sc, p, gi, ng, acc, row_start, row_pref,
+                                                       n_rows, q, cnt);
+        else
+            candidate_pass_q<SI_BIN_BILINEAR, G, false>(sc, p, gi, ng, acc, row_start, row_pref,
+                                                        n_rows, q, cnt);
+    } else {
+        if (p.angle_on)
+            candidate_pass_q<SI_BIN_CEIL, G, true>(sc, p, gi, ng, acc, row_start, row_pref,
+                                                   n_rows, q, cnt);
+        else
+            candidate_pass_q<SI_BIN_CEIL, G, false>(sc, p, gi, ng, acc, row_start, row_pref,
+                                                    n_rows, q, cnt);
+    }
 }
 
 }  // namespace
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_spin(LaunchDesc d) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) k_spin(LaunchDesc d) {
     extern __shared__ uint4 acc_lds[];
     uint32_t* acc = reinterpret_cast<uint32_t*>(acc_lds);
     __shared__ ImgInfo s_info[kInfo];
     __shared__ int s_row_start[kMaxRows];
     __shared__ int s_row_pref[kMaxRows + 1];
     __shared__ int s_n_rows;
-    __shared__ int s_part_x0[kBlock], s_part_x1[kBlock];
     __shared__ uint32_t s_cnt[kMaxGroup];
     __shared__ int s_step;
-    __shared__ float2 s_q_ba[kBlock / 64][kQueue];
-    __shared__ uint32_t s_q_g[kBlock / 64][kQueue];
+    __shared__ WaveQueue s_q[kBlock / 64];
+    // the row culling's partial runs live in the queues, which are empty
+    // between candidate passes (barriers separate the two uses)
+    int* s_part_x0 = reinterpret_cast<int*>(&s_q[0]);
+    int* s_part_x1 = s_part_x0 + kBlock;
 
     const int tid = threadIdx.x;
     const uint64_t t_begin = wall_clock64();
@@ -623,20 +700,19 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
                 uint32_t cnt[kMaxGroup];
 #pragma unroll
                 for (int g = 0; g < kMaxGroup; ++g) cnt[g] = 0;
-                float2* q_ba = s_q_ba[tid >> 6];
-                uint32_t* q_g = s_q_g[tid >> 6];
+                WaveQueue* q = &s_q[tid >> 6];
                 if (ng > 4)
-                    run_group_pass<8>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
-                                      n_rows, q_ba, q_g, cnt);
+                    run_group_pass<8>(sc, p, gi, ng, acc, s_row_start, s_row_pref, n_rows, q,
+                                      cnt);
                 else if (ng > 2)
-                    run_group_pass<4>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
-                                      n_rows, q_ba, q_g, cnt);
+                    run_group_pass<4>(sc, p, gi, ng, acc, s_row_start, s_row_pref, n_rows, q,
+                                      cnt);
                 else if (ng > 1)
-                    run_group_pass<2>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
-                                      n_rows, q_ba, q_g, cnt);
+                    run_group_pass<2>(sc, p, gi, ng, acc, s_row_start, s_row_pref, n_rows, q,
+                                      cnt);
                 else
-                    run_group_pass<1>(p.mode, sc, p, gi, ng, acc, s_row_start, s_row_pref,
-                                      n_rows, q_ba, q_g, cnt);
+                    run_group_pass<1>(sc, p, gi, ng, acc, s_row_start, s_row_pref, n_rows, q,
+                                      cnt);
 #pragma unroll
                 for (int g = 0; g < kMaxGroup; ++g) {
                     if (g < ng && (tid & 63) == 0 && cnt[g]) atomicAdd(&s_cnt[g], cnt[g]);
@@ -729,11 +805,29 @@ size_t spin_lds_bytes(int max_w2, int group) {
     return (size_t)slots * (size_t)(max_w2 + 4) * sizeof(uint32_t) + 16;
 }
 
+// Workgroups of k_spin that one CU holds at once: the occupancy calculator's
+// answer, capped by the CU's LDS counted in allocation blocks of 1,280 bytes.
+// The calculator alone over-counts on gfx950: 32,384 bytes per workgroup fit
+// four to a 160 KB CU, not five (the fifth workgroup of every CU only starts
+// when another ends), while 30,848 bytes fit five; 1,280-byte blocks
+// reproduce both.
 int spin_max_wg_per_cu(int max_w2, int group) {
+    const size_t dyn = spin_lds_bytes(max_w2, group);
     int n = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void*>(k_spin), kBlock, spin_lds_bytes(max_w2, group));
+        &n, reinterpret_cast<const void*>(k_spin), kBlock, dyn);
     if (e != hipSuccess || n < 1) n = 1;
+    hipFuncAttributes fa;
+    int dev = 0, cu_lds = 0;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_spin)) == hipSuccess &&
+        hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+            hipSuccess &&
+        cu_lds > 0) {
+        constexpr size_t kLdsBlock = 1280;
+        const size_t per_wg = (fa.sharedSizeBytes + dyn + kLdsBlock - 1) / kLdsBlock * kLdsBlock;
+        n = std::max(1, std::min(n, (int)((size_t)cu_lds / per_wg)));
+    }
     return n;
 }
 

@@ -404,7 +404,7 @@ int32_t spread_mult(int64_t full) {
 
 // Largest group <= the requested one whose accumulators fit the LDS limit.
 int fit_group(DeviceState* st, int group, int max_w2) {
-    const size_t static_lds = 20480;  // kernel's own shared arrays (~17 KB), rounded up
+    const size_t static_lds = 20480;  // kernel's own shared arrays (~14 KB), rounded up
     while (group > 1 && spin_lds_bytes(max_w2, group) + static_lds > (size_t)st->max_lds) --group;
     return group;
 }
