@@ -181,9 +181,12 @@ typedef struct si_scene_info {
  * cell (brute force over all M points, the paper's O(N M) loop).
  *   points_xyz, normals_xyz  device, M x 3 float32, row-major; read only
  *   M                        number of oriented points, > 0, < 2^31
- * Synchronises the stream once (to read the bounding box).  Returns
- * SI_E_INVALID for M <= 0, NULL pointers or a non-finite radius; a NaN
- * coordinate is placed in cell 0 and is never in support of anything.
+ * Synchronises the stream once (to read the bounding box); the rest of the
+ * build is queued on hip_stream, so the scene is ready for work queued after
+ * it on that stream (other streams must wait for it, e.g. on an event).  The
+ * scene's device arrays come from the device's stream-ordered memory pool.
+ * Returns SI_E_INVALID for M <= 0, NULL pointers or a non-finite radius; a
+ * NaN coordinate is placed in cell 0 and is never in support of anything.
  */
 si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int64_t M,
                          float max_support_radius, void* hip_stream, si_scene** out);

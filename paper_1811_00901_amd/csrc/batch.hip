@@ -26,7 +26,7 @@ namespace {
 struct Flat {
     std::vector<Item> items;
     std::vector<int64_t> item_off;   // n + 1
-    std::vector<int64_t> cell_base;  // n + 1
+    std::vector<int64_t> key_base;   // n + 1: prefix of the items' scene sizes
     std::vector<Chunk> chunks;
     std::vector<int32_t> wg_first;   // static only, n_wg + 1
     int max_w2 = 0;
@@ -36,6 +36,7 @@ struct Flat {
     bool ordered = false;
     int64_t total_N = 0;
     int64_t total_cells = 0;
+    int64_t total_keys = 0;
     // SI_SCHED_LEARNED: the plan is computed on the device before each launch
     bool learned = false;
     const si_cost_model* model = nullptr;
@@ -51,7 +52,7 @@ struct FlatMem {
     size_t bytes = 0;
     Item* items = nullptr;
     int64_t* item_off = nullptr;
-    int64_t* cell_base = nullptr;
+    int64_t* key_base = nullptr;
     Chunk* chunks = nullptr;
     int32_t* wg_first = nullptr;
     int32_t* perm = nullptr;
@@ -77,7 +78,7 @@ size_t layout(const Flat& f, FlatMem& m, char* base) {
     const size_t n = f.items.size();
     m.items = (Item*)take(sizeof(Item) * n);
     m.item_off = (int64_t*)take(sizeof(int64_t) * (n + 1));
-    m.cell_base = (int64_t*)take(sizeof(int64_t) * (n + 1));
+    m.key_base = (int64_t*)take(sizeof(int64_t) * (n + 1));
     m.chunks = (Chunk*)take(sizeof(Chunk) * f.chunks.size());
     m.wg_first = (int32_t*)take(sizeof(int32_t) * f.wg_first.size());
     m.stats = (unsigned long long*)take(sizeof(unsigned long long) * (4 + (size_t)f.n_wg));
@@ -85,9 +86,9 @@ size_t layout(const Flat& f, FlatMem& m, char* base) {
         m.perm = (int32_t*)take(sizeof(int32_t) * f.total_N);
         m.key = (int32_t*)take(sizeof(int32_t) * f.total_N);
         m.rank = (int32_t*)take(sizeof(int32_t) * f.total_N);
-        m.counts = (int32_t*)take(sizeof(int32_t) * f.total_cells);
-        m.starts = (int32_t*)take(sizeof(int32_t) * (f.total_cells + 1));
-        m.tmp = (int32_t*)take(sizeof(int32_t) * scan_tmp_elems(f.total_cells));
+        m.counts = (int32_t*)take(sizeof(int32_t) * f.total_keys);
+        m.starts = (int32_t*)take(sizeof(int32_t) * (f.total_keys + 1));
+        m.tmp = (int32_t*)take(sizeof(int32_t) * scan_tmp_elems(f.total_keys));
     }
     if (f.learned) {
         LearnedMulti size_only;
@@ -129,7 +130,7 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
     int dev = 0;
     SI_HIP(hipGetDevice(&dev));
     f.item_off.push_back(0);
-    f.cell_base.push_back(0);
+    f.key_base.push_back(0);
     for (int32_t k = 0; k < n_items; ++k) {
         const si_batch_item& b = items[k];
         if (b.N == 0) continue;
@@ -162,13 +163,14 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
         it.perm = nullptr;
         f.items.push_back(it);
         f.item_off.push_back(f.item_off.back() + b.N);
-        f.cell_base.push_back(f.cell_base.back() + sc.n_cells);
+        f.key_base.push_back(f.key_base.back() + sc.M);
+        f.total_cells += sc.n_cells;
         f.max_w2 = std::max(f.max_w2, p.W * p.W);
     }
     f.total_N = f.item_off.back();
-    f.total_cells = f.cell_base.back();
-    if (f.total_N >= INT32_MAX || f.total_cells >= INT32_MAX)
-        return fail(SI_E_INVALID, "batch too large (2^31 images or cells)");
+    f.total_keys = f.key_base.back();
+    if (f.total_N >= INT32_MAX || f.total_keys >= INT32_MAX)
+        return fail(SI_E_INVALID, "batch too large (2^31 images or scene points)");
     if (f.items.empty()) return SI_OK;
     f.kind = sched->kind;
     if (f.kind == SI_SCHED_LEARNED) {
@@ -220,7 +222,7 @@ si_status upload(const Flat& f, FlatMem& m, hipStream_t s) {
                           hipMemcpyHostToDevice, s));
     SI_HIP(hipMemcpyAsync(m.item_off, f.item_off.data(), sizeof(int64_t) * f.item_off.size(),
                           hipMemcpyHostToDevice, s));
-    SI_HIP(hipMemcpyAsync(m.cell_base, f.cell_base.data(), sizeof(int64_t) * f.cell_base.size(),
+    SI_HIP(hipMemcpyAsync(m.key_base, f.key_base.data(), sizeof(int64_t) * f.key_base.size(),
                           hipMemcpyHostToDevice, s));
     if (!f.chunks.empty())
         SI_HIP(hipMemcpyAsync(m.chunks, f.chunks.data(), sizeof(Chunk) * f.chunks.size(),
@@ -272,8 +274,8 @@ hipError_t enqueue(const Flat& f, const FlatMem& m, const LaunchDesc& d, bool st
     hipError_t e = hipSuccess;
     if (stats) e = launch_fill(reinterpret_cast<int32_t*>(m.stats), 2 * (4 + (int64_t)f.n_wg), 0, s);
     if (e == hipSuccess && f.ordered)
-        e = launch_cell_order_multi(m.items, m.item_off, m.cell_base, (int)f.items.size(),
-                                    f.total_N, f.total_cells, m.key, m.rank, m.counts, m.starts,
+        e = launch_cell_order_multi(m.items, m.item_off, m.key_base, (int)f.items.size(),
+                                    f.total_N, f.total_keys, m.key, m.rank, m.counts, m.starts,
                                     m.tmp, m.perm, s);
     if (e == hipSuccess && f.learned)
         e = learned_multi_enqueue(f.model, m.lm, m.items, m.item_off, (int)f.items.size(),

@@ -721,15 +721,15 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
         return fail(SI_E_INVALID, "the learned schedule supports at most 4096 workgroups");
     const int64_t n_units = (N + kUnit - 1) / kUnit;
     const int64_t n_tiles = (n_units + kTile - 1) / kTile;
-    const int64_t nt = scan_tmp_elems(scene->n_cells);
+    const int64_t nt = scan_tmp_elems(scene->M);
     // one stream-ordered block for every temporary
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) & ~(size_t)255; return r; };
     const size_t o_perm0 = take(sizeof(int32_t) * N);
     const size_t o_key = take(sizeof(int32_t) * N);
     const size_t o_rank = take(sizeof(int32_t) * N);
-    const size_t o_counts = take(sizeof(int32_t) * scene->n_cells);
-    const size_t o_starts = take(sizeof(int32_t) * (scene->n_cells + 1));
+    const size_t o_counts = take(sizeof(int32_t) * scene->M);
+    const size_t o_starts = take(sizeof(int32_t) * (scene->M + 1));
     const size_t o_tmp = take(sizeof(int32_t) * nt);
     const size_t o_feats = take(sizeof(float) * kNF * N);
     const size_t o_pred = take(sizeof(float) * N);

@@ -216,15 +216,14 @@ __global__ void __launch_bounds__(256) k_fill_i32(int32_t* __restrict__ p, int64
 
 // Key (cell of the oriented point) and rank within its cell for each iteration.
 __global__ void __launch_bounds__(256) k_order_keys(const int32_t* __restrict__ oriented, int64_t N,
-                                                    const int32_t* __restrict__ inv,
-                                                    const float4* __restrict__ pos, int64_t M,
+                                                    const int32_t* __restrict__ inv, int64_t M,
                                                     int32_t* __restrict__ key,
                                                     int32_t* __restrict__ rank,
                                                     int32_t* __restrict__ counts) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= N) return;
     const int o = oriented[i];
-    const int c = (o >= 0 && o < M) ? __float_as_int(pos[inv[o]].w) : 0;
+    const int c = (o >= 0 && o < M) ? inv[o] : 0;
     key[i] = c;
     rank[i] = atomicAdd(counts + c, 1);
 }
@@ -249,7 +248,7 @@ __device__ __forceinline__ int find_item(const int64_t* off, int n, int64_t t) {
 
 __global__ void __launch_bounds__(256) k_order_keys_multi(const Item* __restrict__ items,
                                                           const int64_t* __restrict__ item_off,
-                                                          const int64_t* __restrict__ cell_base,
+                                                          const int64_t* __restrict__ key_base,
                                                           int n_items, int64_t total_N,
                                                           int32_t* __restrict__ key,
                                                           int32_t* __restrict__ rank,
@@ -259,8 +258,8 @@ __global__ void __launch_bounds__(256) k_order_keys_multi(const Item* __restrict
     const int i = find_item(item_off, n_items, t);
     const Item& it = items[i];
     const int o = it.oriented[t - item_off[i]];
-    const int c = (o >= 0 && o < it.scene.M) ? __float_as_int(it.scene.pos[it.scene.inv[o]].w) : 0;
-    const int64_t k = cell_base[i] + c;
+    const int c = (o >= 0 && o < it.scene.M) ? it.scene.inv[o] : 0;
+    const int64_t k = key_base[i] + c;
     key[t] = (int32_t)k;
     rank[t] = atomicAdd(counts + k, 1);
 }
@@ -280,16 +279,16 @@ __global__ void __launch_bounds__(256) k_order_scatter_multi(const int32_t* __re
 }  // namespace
 
 hipError_t launch_cell_order_multi(const Item* items, const int64_t* item_off,
-                                   const int64_t* cell_base, int n_items, int64_t total_N,
-                                   int64_t total_cells, int32_t* key, int32_t* rank,
+                                   const int64_t* key_base, int n_items, int64_t total_N,
+                                   int64_t total_keys, int32_t* key, int32_t* rank,
                                    int32_t* counts, int32_t* starts, int32_t* tmp, int32_t* perm,
                                    hipStream_t s) {
-    hipError_t e = launch_fill(counts, total_cells, 0, s);
+    hipError_t e = launch_fill(counts, total_keys, 0, s);
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((total_N + 255) / 256);
-    hipLaunchKernelGGL(k_order_keys_multi, dim3(nb), dim3(256), 0, s, items, item_off, cell_base,
+    hipLaunchKernelGGL(k_order_keys_multi, dim3(nb), dim3(256), 0, s, items, item_off, key_base,
                        n_items, total_N, key, rank, counts);
-    e = launch_scan(counts, starts, total_cells, tmp, scan_tmp_elems(total_cells), s);
+    e = launch_scan(counts, starts, total_keys, tmp, scan_tmp_elems(total_keys), s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_order_scatter_multi, dim3(nb), dim3(256), 0, s, key, rank, item_off,
                        n_items, total_N, starts, perm);
@@ -306,12 +305,12 @@ hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 hipError_t launch_cell_order(const int32_t* oriented, int64_t N, const Scene& sc, int32_t* key,
                              int32_t* rank, int32_t* counts, int32_t* starts, int32_t* tmp,
                              int32_t* perm, hipStream_t s) {
-    hipError_t e = launch_fill(counts, sc.n_cells, 0, s);
+    hipError_t e = launch_fill(counts, sc.M, 0, s);
     if (e != hipSuccess) return e;
     const unsigned nb = (unsigned)((N + 255) / 256);
-    hipLaunchKernelGGL(k_order_keys, dim3(nb), dim3(256), 0, s, oriented, N, sc.inv, sc.pos, sc.M,
-                       key, rank, counts);
-    e = launch_scan(counts, starts, sc.n_cells, tmp, scan_tmp_elems(sc.n_cells), s);
+    hipLaunchKernelGGL(k_order_keys, dim3(nb), dim3(256), 0, s, oriented, N, sc.inv, sc.M, key,
+                       rank, counts);
+    e = launch_scan(counts, starts, sc.M, tmp, scan_tmp_elems(sc.M), s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, key, rank, N, starts, perm);
     return hipGetLastError();

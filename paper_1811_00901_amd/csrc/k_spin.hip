@@ -641,14 +641,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
 
             int cur = 0;
             while (cur < nb) {
-                // ---- form a group (every thread computes the same answer) ----
+                // ---- form a group (every wave computes the same answer) ----
+                // lane l of each wave holds staged image l (kInfo = 64 lanes);
+                // the serial scan below reads it with readlane, so its
+                // decisions are scalar and wait on no LDS round trip
+                const int l = tid & 63;
+                const ImgInfo li = s_info[l < nb ? l : 0];
                 int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
                 int hi[3] = {-1, -1, -1};
                 int ng = 0;
                 while (ng < G_item && cur + ng < nb) {
-                    const ImgInfo& ci = s_info[cur + ng];
-                    if (ci.cell >= 0) {
-                        const int c[3] = {ci.cx, ci.cy, ci.cz};
+                    const int i = cur + ng;
+                    if (__builtin_amdgcn_readlane(li.cell, i) >= 0) {
+                        const int c[3] = {__builtin_amdgcn_readlane(li.cx, i),
+                                          __builtin_amdgcn_readlane(li.cy, i),
+                                          __builtin_amdgcn_readlane(li.cz, i)};
                         int nlo[3], nhi[3];
                         bool ok = true;
 #pragma unroll
@@ -663,16 +670,19 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
                     }
                     ++ng;
                 }
-                ng = rfl(ng);
                 int gcx[kMaxGroup];
                 GroupImg gi[kMaxGroup];
 #pragma unroll
                 for (int g = 0; g < kMaxGroup; ++g) {
                     if (g >= ng) break;
-                    const ImgInfo inf = s_info[cur + g];
-                    gcx[g] = rfl(inf.cx);
-                    gi[g].px = rfl(inf.px); gi[g].py = rfl(inf.py); gi[g].pz = rfl(inf.pz);
-                    gi[g].nx = rfl(inf.nx); gi[g].ny = rfl(inf.ny); gi[g].nz = rfl(inf.nz);
+                    const int i = cur + g;
+                    gcx[g] = __builtin_amdgcn_readlane(li.cx, i);
+                    gi[g].px = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(li.px), i));
+                    gi[g].py = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(li.py), i));
+                    gi[g].pz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(li.pz), i));
+                    gi[g].nx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(li.nx), i));
+                    gi[g].ny = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(li.ny), i));
+                    gi[g].nz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(li.nz), i));
                 }
                 const bool any_valid = hi[0] >= 0;
                 int rlo[3], rhi[3];

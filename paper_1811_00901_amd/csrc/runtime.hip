@@ -223,14 +223,15 @@ SceneView view_of(const Scene& s) {
     return v;
 }
 
-static void free_scene_mem(Scene* s) {
-    if (!s) return;
-    (void)hipFree(s->pos);
-    (void)hipFree(s->nrm);
-    (void)hipFree(s->sub_start);
-    (void)hipFree(s->inv);
-    s->pos = s->nrm = nullptr;
-    s->sub_start = s->inv = nullptr;
+// The scene's arrays come from the device's stream-ordered pool (which keeps
+// freed memory cached), so building a scene per frame costs no allocation
+// round trips.  Frees are ordered on `stream`.
+static void free_scene_mem(Scene* sc, hipStream_t stream) {
+    if (!sc) return;
+    if (sc->mem) (void)hipFreeAsync(sc->mem, stream);
+    sc->mem = nullptr;
+    sc->pos = sc->nrm = nullptr;
+    sc->sub_start = sc->inv = nullptr;
 }
 
 }  // namespace si
@@ -256,15 +257,15 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     sc->M = M;
     SI_HIP(hipGetDevice(&sc->device));
 
-    // ---- bounding box (one synchronisation) ----
+    // ---- bounding box (the one synchronisation) ----
     float* bb = nullptr;
-    hipError_t e = hipMalloc(&bb, sizeof(float) * (8 + 6 * 1024));
-    if (e != hipSuccess) { delete sc; return hip_fail(e, "hipMalloc(bbox)"); }
+    hipError_t e = hipMallocAsync((void**)&bb, sizeof(float) * (8 + 6 * 1024), s);
+    if (e != hipSuccess) { delete sc; return hip_fail(e, "hipMallocAsync(bbox)"); }
     float hb[6];
     e = launch_bbox(points_xyz, M, bb, s);
     if (e == hipSuccess) e = hipMemcpyAsync(hb, bb, sizeof(hb), hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(bb, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(bb);
     if (e != hipSuccess) { delete sc; return hip_fail(e, "scene bounding box"); }
 
     double lo[3], ext[3];
@@ -305,30 +306,41 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     int32_t *key_of = nullptr, *rank = nullptr, *counts = nullptr, *tmp = nullptr;
     const int64_t n_keys = sc->n_cells * kSubX;
     const int64_t ntmp = scan_tmp_elems(n_keys);
+    // two pool allocations: the scene's arrays, and temporaries that return
+    // to the pool once the stream has used them
+    auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_pos = rup(sizeof(float4) * M), b_inv = rup(sizeof(int32_t) * M);
+    const size_t b_sub = rup(sizeof(int32_t) * (n_keys + 1));
+    const size_t b_key = rup(sizeof(int32_t) * n_keys);
+    char* tmem = nullptr;
+    e = hipMallocAsync(&sc->mem, 2 * b_pos + b_inv + b_sub, s);
+    if (e == hipSuccess) {
+        char* m = static_cast<char*>(sc->mem);
+        sc->pos = reinterpret_cast<float4*>(m);
+        sc->nrm = reinterpret_cast<float4*>(m + b_pos);
+        sc->inv = reinterpret_cast<int32_t*>(m + 2 * b_pos);
+        sc->sub_start = reinterpret_cast<int32_t*>(m + 2 * b_pos + b_inv);
+        e = hipMallocAsync((void**)&tmem, 2 * b_inv + b_key + rup(sizeof(int32_t) * ntmp), s);
+    }
+    if (e == hipSuccess) {
+        key_of = reinterpret_cast<int32_t*>(tmem);
+        rank = reinterpret_cast<int32_t*>(tmem + b_inv);
+        counts = reinterpret_cast<int32_t*>(tmem + 2 * b_inv);
+        tmp = reinterpret_cast<int32_t*>(tmem + 2 * b_inv + b_key);
+    }
     auto cleanup = [&]() {
-        (void)hipFree(key_of);
-        (void)hipFree(rank);
-        (void)hipFree(counts);
-        (void)hipFree(tmp);
+        if (tmem) (void)hipFreeAsync(tmem, s);
     };
-    e = hipMalloc(&sc->pos, sizeof(float4) * M);
-    if (e == hipSuccess) e = hipMalloc(&sc->nrm, sizeof(float4) * M);
-    if (e == hipSuccess) e = hipMalloc(&sc->inv, sizeof(int32_t) * M);
-    if (e == hipSuccess) e = hipMalloc(&sc->sub_start, sizeof(int32_t) * (n_keys + 1));
-    if (e == hipSuccess) e = hipMalloc(&key_of, sizeof(int32_t) * M);
-    if (e == hipSuccess) e = hipMalloc(&rank, sizeof(int32_t) * M);
-    if (e == hipSuccess) e = hipMalloc(&counts, sizeof(int32_t) * n_keys);
-    if (e == hipSuccess) e = hipMalloc(&tmp, sizeof(int32_t) * ntmp);
     if (e == hipSuccess) e = launch_fill(counts, n_keys, 0, s);
     if (e == hipSuccess) e = launch_bin_points(points_xyz, M, *sc, key_of, rank, counts, s);
     if (e == hipSuccess) e = launch_scan(counts, sc->sub_start, n_keys, tmp, ntmp, s);
     if (e == hipSuccess)
         e = launch_scatter(points_xyz, normals_xyz, M, key_of, rank, sc->sub_start, *sc, s);
-    // temporaries are released once the stream has used them
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
     cleanup();
     if (e != hipSuccess) {
-        free_scene_mem(sc);
+        (void)hipStreamSynchronize(s);
+        free_scene_mem(sc, s);
         delete sc;
         return hip_fail(e, "scene build");
     }
@@ -338,7 +350,11 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
 
 void si_free_scene(si_scene* scene) {
     if (!scene) return;
-    free_scene_mem(scene);
+    // work using the scene has completed (caller's contract); the device-wide
+    // synchronisation also covers the build's own kernels, which may still be
+    // queued on a stream that does not synchronise with the null stream
+    (void)hipDeviceSynchronize();
+    free_scene_mem(scene, nullptr);
     delete scene;
 }
 
@@ -494,16 +510,16 @@ si_status check_sched(const si_sched* sc) {
 // memory released (stream-ordered) by the caller after the launch.
 si_status cell_order(const Scene& sc, const int32_t* oriented, int64_t N, hipStream_t s,
                      int32_t** mem_out, const int32_t** perm_out) {
-    const int64_t nt = scan_tmp_elems(sc.n_cells);
-    const int64_t words = 3 * N + sc.n_cells + (sc.n_cells + 1) + nt;
+    const int64_t nt = scan_tmp_elems(sc.M);
+    const int64_t words = 3 * N + sc.M + (sc.M + 1) + nt;
     int32_t* mem = nullptr;
     SI_HIP(hipMallocAsync((void**)&mem, sizeof(int32_t) * words, s));
     int32_t* perm = mem;
     int32_t* key = perm + N;
     int32_t* rank = key + N;
     int32_t* counts = rank + N;
-    int32_t* starts = counts + sc.n_cells;
-    int32_t* tmp = starts + sc.n_cells + 1;
+    int32_t* starts = counts + sc.M;
+    int32_t* tmp = starts + sc.M + 1;
     hipError_t e = launch_cell_order(oriented, N, sc, key, rank, counts, starts, tmp, perm, s);
     if (e != hipSuccess) {
         (void)hipFreeAsync(mem, s);
@@ -515,7 +531,18 @@ si_status cell_order(const Scene& sc, const int32_t* oriented, int64_t N, hipStr
 }
 
 int auto_workgroups(DeviceState* st, int max_w2, int group) {
-    const int per_cu = std::min(8, spin_max_wg_per_cu(max_w2, group));
+    const auto key = std::make_pair(max_w2, group);
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = st->wg_per_cu.find(key);
+        if (it != st->wg_per_cu.end()) per_cu = it->second;
+    }
+    if (per_cu == 0) {
+        per_cu = std::min(8, spin_max_wg_per_cu(max_w2, group));
+        std::lock_guard<std::mutex> lk(g_mu);
+        st->wg_per_cu[key] = per_cu;
+    }
     return std::max(1, st->n_cu * per_cu);
 }
 

@@ -49,6 +49,7 @@ struct Scene {
     float max_radius = 0;        // <= 0: brute force, single cell
     int64_t n_cells = 1;
     int device = 0;
+    void* mem = nullptr;         // one pool allocation holding the four arrays
 };
 
 // --------------------------------------------------------------- kernels --
@@ -139,19 +140,21 @@ int64_t scan_tmp_elems(int64_t n);
 // 64-bit exclusive scan, out[n] = total; tmp holds scan_tmp_elems(n) values.
 hipError_t launch_scan64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
-// perm: iterations sorted by the cell of their oriented point (counting sort;
-// order within a cell is arbitrary).  Temporaries: key, rank (N), counts
-// (n_cells), starts (n_cells + 1), tmp (scan_tmp_elems(n_cells)).
+// perm: iterations sorted by the position of their oriented point in the
+// scene's sorted order (cell, then quarter of the cell along x), by a
+// counting sort over the M positions; duplicates of one point are in
+// arbitrary order.  Temporaries: key, rank (N), counts (M), starts (M + 1),
+// tmp (scan_tmp_elems(M)).
 hipError_t launch_cell_order(const int32_t* oriented, int64_t N, const Scene& sc, int32_t* key,
                              int32_t* rank, int32_t* counts, int32_t* starts, int32_t* tmp,
                              int32_t* perm, hipStream_t s);
 // Same for a batch: iteration t of the concatenated loop belongs to the item
-// with item_off[i] <= t < item_off[i+1]; keys are cell_base[i] + cell, and
-// perm[t'] receives the item-local iteration index.  total_cells = sum of the
-// items' cell counts.
+// with item_off[i] <= t < item_off[i+1]; keys are key_base[i] + position, and
+// perm[t'] receives the item-local iteration index.  total_keys = sum of the
+// items' scene sizes M.
 hipError_t launch_cell_order_multi(const Item* items, const int64_t* item_off,
-                                   const int64_t* cell_base, int n_items, int64_t total_N,
-                                   int64_t total_cells, int32_t* key, int32_t* rank,
+                                   const int64_t* key_base, int n_items, int64_t total_N,
+                                   int64_t total_keys, int32_t* key, int32_t* rank,
                                    int32_t* counts, int32_t* starts, int32_t* tmp, int32_t* perm,
                                    hipStream_t s);
 hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const int32_t* key_of,
@@ -168,6 +171,8 @@ struct DeviceState {
     uint32_t next_slot = 0;
     // chunk-table cache: (kind, N, P, min_chunk, divisor bits) -> device table
     std::map<std::tuple<int, int64_t, int, int, uint32_t>, std::pair<Chunk*, int>> tables;
+    // spin-kernel workgroups per CU: (max W^2, group) -> count
+    std::map<std::pair<int, int>, int> wg_per_cu;
 };
 
 si_status device_state(DeviceState** out);
