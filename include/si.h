@@ -102,15 +102,16 @@ typedef struct si_params {
  *   fallback_to_fac SI_SCHED_LEARNED without a model: 1 = run FAC, 0 = error
  *   group           images that share one pass over their common candidate
  *                   points (1..8); 0 = library default
- *   order           SI_ORDER_SPREAD (0): the oriented points sorted by grid
- *                   cell, in units of 8 consecutive iterations, and the
+ *   order           SI_ORDER_SPREAD (0): the oriented points sorted by their
+ *                   place in the scene (grid cell, then quarter of the cell
+ *                   along x), in units of 8 consecutive iterations, and the
  *                   units taken with a stride coprime to their number, so
  *                   that every part of the loop holds units from the whole
  *                   scene (chunks of neighbouring images keep sharing
  *                   candidates, while costs stop clustering along the loop;
- *                   SI_SCHED_LEARNED builds its own order from the cell
- *                   order); SI_ORDER_CELL (2): the loop runs over the oriented points
- *                   sorted by grid cell, so that neighbouring images share
+ *                   SI_SCHED_LEARNED builds its own order from the sorted
+ *                   one); SI_ORDER_CELL (2): the loop runs over the oriented
+ *                   points in that sorted order, so that neighbouring images share
  *                   candidates (iterations of a DOALL loop may run in any
  *                   order); SI_ORDER_GIVEN (1): in the order of oriented_idx,
  *                   as the paper's loop i = 0..N-1.  Chunks are contiguous
