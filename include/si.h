@@ -322,6 +322,17 @@ si_status si_cost_model_gradient(const si_cost_model* model, const float* feats,
 si_status si_cost_model_predict(const si_cost_model* model, const float* feats, int64_t n,
                                 float* pred_counts, void* hip_stream);
 
+/*
+ * The same predictions as the learned schedule's planner computes them:
+ * fp16 operands and fp32 accumulation on the matrix cores (features,
+ * weights and hidden activations rounded to fp16; biases, sums and the
+ * output in fp32).  The planner only groups predicted unit costs into 32
+ * buckets per octave, far coarser than this rounding.  Arguments as for
+ * si_cost_model_predict.
+ */
+si_status si_cost_model_predict_planner(const si_cost_model* model, const float* feats, int64_t n,
+                                        float* pred_counts, void* hip_stream);
+
 /* Copy the 5,057 parameters (W1 64x12, b1 64, W2 64x64, b2 64, w3 64, b3 1, in
  * that order, row-major) between the model and a host array. */
 si_status si_cost_model_get_params(const si_cost_model* model, float* host_params, int64_t n);

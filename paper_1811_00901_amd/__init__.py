@@ -23,7 +23,8 @@ import torch
 __all__ = [
     "SiError", "Params", "Sched", "Scene", "CostModel", "lib",
     "si_build_scene", "si_generate", "si_generate_batched", "si_features",
-    "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict", "si_cost_model_gradient",
+    "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
+    "si_cost_model_predict_planner", "si_cost_model_gradient",
     "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
     "si_set_kernel_events", "si_autotune", "si_peak_probe",
     "SCHED", "MODE", "PROBE",
@@ -101,6 +102,7 @@ def lib():
             "si_free_cost_model": (None, [P]),
             "si_cost_model_train": (I32, [P, P, P, I64, I32, F, I32, P, P]),
             "si_cost_model_predict": (I32, [P, P, I64, P, P]),
+            "si_cost_model_predict_planner": (I32, [P, P, I64, P, P]),
             "si_cost_model_gradient": (I32, [P, P, P, I64, P, P, P]),
             "si_cost_model_get_params": (I32, [P, P, I64]),
             "si_cost_model_set_params": (I32, [P, P, I64]),
@@ -428,6 +430,17 @@ def si_cost_model_predict(model: CostModel, feats: torch.Tensor, stream=None) ->
     if n:
         _check(lib().si_cost_model_predict(model.handle, _dev_ptr(feats, torch.float32, "feats", (n, 12)),
                                            n, _dev_ptr(out, torch.float32, "pred"), _stream(stream)))
+    return out
+
+
+def si_cost_model_predict_planner(model: CostModel, feats: torch.Tensor, stream=None) -> torch.Tensor:
+    """Predictions as the learned schedule's planner computes them (fp16 matrix-core products)."""
+    n = int(feats.shape[0])
+    out = torch.empty((n,), dtype=torch.float32, device=feats.device)
+    if n:
+        _check(lib().si_cost_model_predict_planner(
+            model.handle, _dev_ptr(feats, torch.float32, "feats", (n, 12)), n,
+            _dev_ptr(out, torch.float32, "pred"), _stream(stream)))
     return out
 
 

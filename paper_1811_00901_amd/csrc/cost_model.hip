@@ -128,6 +128,18 @@ __global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* _
     features_of(sc, oriented[i], f11, feats + kNF * i);
 }
 
+// Features of loop position t (iteration perm[t], or t) into feats[t]: in the
+// cell order, the lanes of a wave read the same grid rows.
+__global__ void __launch_bounds__(256) k_features_loop(SceneView sc,
+                                                       const int32_t* __restrict__ oriented,
+                                                       const int32_t* __restrict__ perm,
+                                                       int64_t N, float f11,
+                                                       float* __restrict__ feats) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    features_of(sc, oriented[perm ? perm[t] : t], f11, feats + kNF * t);
+}
+
 // ------------------------------------------------------------- MLP forward --
 // pred[i] = max(expm1(net(feats[i])), 0); with `out_raw` the raw network
 // output is written instead.
@@ -157,6 +169,99 @@ __global__ void __launch_bounds__(256) k_mlp_predict(const float* __restrict__ p
         out = fmaf(P[oW3 + j], fmaxf(z, 0.0f), out);
     }
     pred[i] = out_raw ? out : fmaxf(expm1f(out), 0.0f);
+}
+
+// -------------------------------------------- MLP forward on matrix cores --
+// The learned schedule's planner evaluates the network with fp16 operands and
+// fp32 accumulation on MFMA (v_mfma_f32_16x16x16_f16): per wave, 16 images at
+// a time, products taken transposed (weights x activations) so that each
+// layer's 16 x 16 output tiles are already the next layer's operand tiles:
+//   H1^T = relu(W1 X^T + b1)    4 MFMA (neuron tiles t, K = 12 padded to 16)
+//   H2^T = relu(W2 H1^T + b2)   16 MFMA (neuron tiles u, K steps s)
+//   out  = w3 . H2^T + b3       per-lane dot products and two lane swaps
+// Operand layout of the 16x16x16 product (wave of 64): lane l holds row
+// l % 16 of A and column l % 16 of B at K = 4 (l / 16) .. + 3; the 16 x 16
+// result has column l % 16, rows 4 (l / 16) .. + 3 in lane l.  Only the
+// planner uses this path: the ordering it feeds groups costs 32 buckets per
+// octave, far coarser than the fp16 rounding.
+typedef _Float16 h16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4m __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_mlp_predict_mfma(const float* __restrict__ params,
+                                                          const float* __restrict__ feats,
+                                                          int64_t n, float* __restrict__ pred,
+                                                          int out_raw) {
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, kb = lane >> 4;  // row/column within a tile, K block
+    // weights as A operands, biases and w3 at this lane's result rows
+    h16x4 a1[4], a2[4][4];
+    float b1[4][4], b2[4][4], w3[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * kb + i;
+            a1[t][i] = (_Float16)(k < kNF ? params[oW1 + (16 * t + r16) * kNF + k] : 0.0f);
+            b1[t][i] = params[oB1 + 16 * t + 4 * kb + i];
+            b2[t][i] = params[oB2 + 16 * t + 4 * kb + i];
+            w3[t][i] = params[oW3 + 16 * t + 4 * kb + i];
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                a2[t][s2][i] = (_Float16)params[oW2 + (16 * t + r16) * kH + 16 * s2 + 4 * kb + i];
+    }
+    const float b3 = params[oB3];
+    const int64_t n_tiles = (n + 15) / 16;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
+        const int64_t img = tile * 16 + r16;
+        // B operand of layer 1: features 4 kb .. 4 kb + 3 of image img
+        h16x4 x;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * kb + i;
+            x[i] = (_Float16)(img < n && k < kNF ? feats[kNF * img + k] : 0.0f);
+        }
+        h16x4 h1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f32x4m d = {0.0f, 0.0f, 0.0f, 0.0f};
+            d = __builtin_amdgcn_mfma_f32_16x16x16f16(a1[t], x, d, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h1[t][i] = (_Float16)fmaxf(d[i] + b1[t][i], 0.0f);
+        }
+        float part = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            f32x4m d = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2)
+                d = __builtin_amdgcn_mfma_f32_16x16x16f16(a2[u][s2], h1[s2], d, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part = fmaf(w3[u][i], fmaxf(d[i] + b2[u][i], 0.0f), part);
+        }
+        // the four lanes of image r16 hold the four quarters of the dot product
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (kb == 0 && img < n) {
+            const float out = part + b3;
+            pred[img] = out_raw ? out : fmaxf(expm1f(out), 0.0f);
+        }
+    }
+}
+
+hipError_t launch_mlp_predict_mfma(const float* params, const float* feats, int64_t n,
+                                   float* pred, int out_raw, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    // every wave loads the weights once: about 32 tiles of 16 images per wave
+    const int64_t tiles = (n + 15) / 16;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 127) / 128, 1024));
+    hipLaunchKernelGGL(k_mlp_predict_mfma, dim3(blocks), dim3(256), 0, s, params, feats, n, pred,
+                       out_raw);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- gradient --
@@ -391,6 +496,58 @@ __global__ void __launch_bounds__(256) k_unit_gather(const int32_t* __restrict__
     ival[k] = min((int64_t)kUnit, N - u * kUnit);
 }
 
+// Search structure for factoring on cost: the exclusive cost prefix cpre
+// (nondecreasing, n + 1 entries) sampled every `stride` entries into LDS, so
+// that finding the first entry >= a target takes a binary search in LDS and
+// one over a window of `stride` entries in global memory.
+constexpr int kCostSamples = 4096;
+struct CostIndex {
+    const int64_t* cpre;
+    int64_t n;
+    int64_t stride;
+    int ns;          // samples: entry min(i * stride, n) for i < ns
+    int64_t* samp;   // LDS, ns values
+};
+
+// Fill the index (all threads of the block; a barrier follows).
+__device__ CostIndex cost_index(const int64_t* cpre, int64_t n, int64_t* samp) {
+    CostIndex ix;
+    ix.cpre = cpre;
+    ix.n = n;
+    ix.stride = max((int64_t)1, (n + kCostSamples - 2) / (kCostSamples - 1));
+    ix.ns = (int)((n + ix.stride - 1) / ix.stride) + 1;
+    ix.samp = samp;
+    for (int i = threadIdx.x; i < ix.ns; i += blockDim.x)
+        samp[i] = cpre[min((int64_t)i * ix.stride, n)];
+    __syncthreads();
+    return ix;
+}
+
+// First k in [0, n] with cpre[k] >= target, or n + 1 if there is none.
+__device__ int64_t first_at_least(const CostIndex& ix, int64_t target) {
+    if (ix.samp[0] >= target) return 0;
+    int lo = 0, hi = ix.ns - 1;  // largest sample below the target
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ix.samp[mid] < target) lo = mid; else hi = mid - 1;
+    }
+    if (lo == ix.ns - 1) return ix.n + 1;
+    int64_t a = (int64_t)lo * ix.stride + 1;
+    int64_t b = min((int64_t)(lo + 1) * ix.stride, ix.n);  // cpre[b] >= target
+    while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (ix.cpre[mid] >= target) b = mid; else a = mid + 1;
+    }
+    return a;
+}
+
+// End of chunk j of the batch starting at st with chunk cost cb: the first
+// k in [st + 1, n) with cpre[k] - cpre[st] >= j * cb, else n.
+__device__ __forceinline__ int64_t chunk_end(const CostIndex& ix, int64_t st, int64_t c_st,
+                                             int64_t j, int64_t cb) {
+    return min(ix.n, max(st + 1, first_at_least(ix, c_st + j * cb)));
+}
+
 // Single block: factoring on predicted cost over the LPT order (cpre, ipre:
 // exclusive prefix sums of cost and iterations, n_units + 1 entries), the
 // chunk table and its length.  Thread t computes chunks t*kPerThread+1 ..
@@ -405,33 +562,27 @@ __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restri
     const int64_t total = cpre[n_units];
     __shared__ int64_t start;
     __shared__ int emitted;
-    __shared__ int64_t ends[kMaxLearnedP + 1];
+    __shared__ int32_t ends[kMaxLearnedP + 1];
     __shared__ int pos[1024];
+    __shared__ int64_t samp[kCostSamples];
     if (tid == 0) {
         start = 0;
         emitted = 0;
     }
-    __syncthreads();
+    const CostIndex ix = cost_index(cpre, n_units, samp);
     const double x = divisor > 0.0f ? (double)divisor : 2.0;
     while (start < n_units) {
         const int64_t st = start;
-        const int64_t R = total - cpre[st];
+        const int64_t c_st = cpre[st];
+        const int64_t R = total - c_st;
         const int64_t cb = max((int64_t)1, (int64_t)ceil((double)R / (x * (double)P)));
-        // end of chunk j (1..P): first k > st with cpre[k] - cpre[st] >= j * cb, else n_units
-        for (int r = 0; r < kPerThread; ++r) {
-            const int j = tid * kPerThread + r + 1;
-            if (j > P) break;
-            const int64_t target = cpre[st] + (int64_t)j * cb;
-            int64_t lo = st + 1, hi = n_units;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (cpre[mid] >= target) hi = mid; else lo = mid + 1;
-            }
-            ends[j] = lo;
-        }
-        if (tid == 0) ends[0] = st;
+        // end of chunk j (1..P): first k > st with cpre[k] - cpre[st] >= j * cb,
+        // else n_units (every thread takes every 1024th j: independent searches)
+        for (int j = tid + 1; j <= P; j += 1024) ends[j] = (int32_t)chunk_end(ix, st, c_st, j, cb);
+        if (tid == 0) ends[0] = (int32_t)st;
         __syncthreads();
-        // non-empty chunks of the batch, written in order (block prefix sum)
+        // non-empty chunks of the batch, written in order (block prefix sum
+        // over runs of kPerThread consecutive j)
         int mine = 0;
         for (int r = 0; r < kPerThread; ++r) {
             const int j = tid * kPerThread + r + 1;
@@ -567,22 +718,16 @@ __global__ void __launch_bounds__(1024) k_learned_cuts(const int64_t* __restrict
     const int tid = threadIdx.x;
     const int64_t total = cpre[n_units];
     __shared__ int64_t start;
+    __shared__ int64_t samp[kCostSamples];
     if (tid == 0) start = 0;
-    __syncthreads();
+    const CostIndex ix = cost_index(cpre, n_units, samp);
     const double x = divisor > 0.0f ? (double)divisor : 2.0;
     while (start < n_units) {
         const int64_t st = start;
-        const int64_t R = total - cpre[st];
+        const int64_t c_st = cpre[st];
+        const int64_t R = total - c_st;
         const int64_t cb = max((int64_t)1, (int64_t)ceil((double)R / (x * (double)P)));
-        for (int j = tid + 1; j <= P; j += 1024) {
-            const int64_t target = cpre[st] + (int64_t)j * cb;
-            int64_t lo = st + 1, hi = n_units;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (cpre[mid] >= target) hi = mid; else lo = mid + 1;
-            }
-            ends[j] = lo;
-        }
+        for (int j = tid + 1; j <= P; j += 1024) ends[j] = chunk_end(ix, st, c_st, j, cb);
         if (tid == 0) ends[0] = st;
         __syncthreads();
         for (int j = tid + 1; j <= P; j += 1024)
@@ -761,13 +906,17 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
     float* feats = reinterpret_cast<float*>(mem + o_feats);
     float* pred = reinterpret_cast<float*>(mem + o_pred);
     if (e == hipSuccess) {
-        si_status rc = features_launch(*scene, oriented, N, params, feats, s);
-        if (rc != SI_OK) e = hipErrorLaunchFailure;
+        // features and predictions in loop order (perm0 applied here)
+        SpinParams p;
+        double R;
+        if (make_params(params, &p, &R) != SI_OK) e = hipErrorInvalidValue;
+        if (e == hipSuccess)
+            hipLaunchKernelGGL(k_features_loop, dim3(nblocks(N)), dim3(256), 0, s, view_of(*scene),
+                               oriented, perm0, N, (float)(R / (kSub * scene->h)), feats);
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_mlp_predict, dim3(nblocks(N)), dim3(256), 0, s, model->params, feats,
-                           N, pred, 0);
-        hipLaunchKernelGGL(k_unit_cost, dim3(nblocks(n_units)), dim3(256), 0, s, pred, perm0, N,
+        e = launch_mlp_predict_mfma(model->params, feats, N, pred, 0, s);
+        hipLaunchKernelGGL(k_unit_cost, dim3(nblocks(n_units)), dim3(256), 0, s, pred, nullptr, N,
                            n_units, reinterpret_cast<uint32_t*>(mem + o_qcost), I(o_ukey));
         hipLaunchKernelGGL(k_unit_hist, dim3((unsigned)n_tiles), dim3(kTile), 0, s, I(o_ukey),
                            n_units, I(o_hist), I(o_urank));
@@ -780,7 +929,7 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
         hipLaunchKernelGGL(k_unit_gather, dim3(nblocks(n_units)), dim3(256), 0, s, I(o_order),
                            reinterpret_cast<uint32_t*>(mem + o_qcost), n_units, N, L(o_cval),
                            L(o_ival));
-        e = launch_scan64(L(o_cval), L(o_cpre), n_units, L(o_stmp), s);
+        if (e == hipSuccess) e = launch_scan64(L(o_cval), L(o_cpre), n_units, L(o_stmp), s);
         if (e == hipSuccess) e = launch_scan64(L(o_ival), L(o_ipre), n_units, L(o_stmp), s);
         hipLaunchKernelGGL(k_learned_chunks, dim3(1), dim3(1024), 0, s, L(o_cpre), L(o_ipre),
                            n_units, n_wg, sched->fac_divisor,
@@ -867,8 +1016,8 @@ hipError_t learned_multi_enqueue(const si_cost_model* model, const LearnedMulti&
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_features_multi, dim3(nblocks(total_N)), dim3(256), 0, s, items, item_off,
                        n_items, perm_cell, b.f11, total_N, b.feats);
-    hipLaunchKernelGGL(k_mlp_predict, dim3(nblocks(total_N)), dim3(256), 0, s, model->params,
-                       b.feats, total_N, b.pred, 0);
+    e = launch_mlp_predict_mfma(model->params, b.feats, total_N, b.pred, 0, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_unit_cost_multi, dim3(nblocks(n_units)), dim3(256), 0, s, b.pred,
                        b.unit_off, item_off, n_items, n_units, b.qcost, b.ukey, b.ulen, b.uitem,
                        b.hcount, b.hlen);
@@ -1045,6 +1194,14 @@ si_status si_cost_model_predict(const si_cost_model* m, const float* feats, int6
     hipLaunchKernelGGL(k_mlp_predict, dim3(nblocks(n)), dim3(256), 0, (hipStream_t)hip_stream,
                        m->params, feats, n, pred_counts, 0);
     SI_HIP(hipGetLastError());
+    return SI_OK;
+}
+
+si_status si_cost_model_predict_planner(const si_cost_model* m, const float* feats, int64_t n,
+                                        float* pred_counts, void* hip_stream) {
+    if (!m || (n > 0 && (!feats || !pred_counts))) return fail(SI_E_INVALID, "bad arguments");
+    if (n <= 0) return SI_OK;
+    SI_HIP(launch_mlp_predict_mfma(m->params, feats, n, pred_counts, 0, (hipStream_t)hip_stream));
     return SI_OK;
 }
 

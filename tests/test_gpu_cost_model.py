@@ -74,6 +74,45 @@ def test_gradient_and_forward_vs_oracle(env, prims):
     np.testing.assert_allclose(pred, np.maximum(np.expm1(out), 0), rtol=1e-4, atol=1e-3)
 
 
+def test_planner_predictions_within_fp16_bound(env, prims):
+    """The planner's matrix-core evaluation (fp16 operands, fp32 sums) stays
+    within the error bound that fp16 rounding (unit roundoff u = 2^-11) of the
+    features, weights and hidden activations allows, propagated through the
+    network in absolute values; fp32 sums add a small relative slack."""
+    torch, si, _ = env
+    print("\n[case] planner predictions", flush=True)
+    m = si.si_cost_model_create(13)
+    si.si_cost_model_train(m, prims["feats"], prims["cnt"], epochs=2, lr=2e-3, batch=2048)
+    theta = m.get_params().astype(np.float64)
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(theta)
+    X = prims["feats"].cpu().numpy().astype(np.float64)
+    out, (_, _, h1, _, _) = mlp.forward(theta, X)
+    u = 2.0 ** -11
+    # layer 1: x and W1 rounded to fp16; fp32 sums of at most 64 terms: 64 * 2^-24 ~ 3.8e-6 relative to the sum of
+    # magnitudes, taken as 1e-5 for the matrix cores' own summation order
+    e1 = (2 * u + u * u) * (np.abs(X) @ np.abs(W1).T) + 1e-5 * (np.abs(X) @ np.abs(W1).T + np.abs(b1))
+    # h1 rounded to fp16 after the ReLU (which does not enlarge errors)
+    e1 = e1 + u * (h1 + e1)
+    # layer 2: W2 rounded, h1 carries e1
+    a2 = (h1 + e1) @ np.abs(W2).T
+    e2 = e1 @ np.abs(W2).T + u * a2 + 1e-5 * (a2 + np.abs(b2))
+    e_out = e2 @ np.abs(w3) + 1e-5 * (np.abs(h1 @ W2.T) @ np.abs(w3) + np.abs(b3) + 1.0)
+    got = si.si_cost_model_predict_planner(m, prims["feats"]).cpu().numpy().astype(np.float64)
+    lo = np.maximum(np.expm1(out - e_out), 0.0) * (1 - 1e-5)
+    hi = np.maximum(np.expm1(out + e_out), 0.0) * (1 + 1e-5) + 1e-6
+    bad = np.nonzero((got < lo) | (got > hi))[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], lo[bad[:5]], hi[bad[:5]])
+    # what the planner uses the predictions for: unit costs in buckets of
+    # ln(2) / 32 in log space.  The observed deviation (log1p of the
+    # prediction against the oracle's output, where both are positive) is a
+    # small fraction of a bucket.
+    pos = (out > 0.05) & (got > 0)
+    dev = np.abs(np.log1p(got[pos]) - out[pos])
+    print(f"deviation in log space: median {np.median(dev):.2e}, p99 {np.quantile(dev, 0.99):.2e}, "
+          f"worst-case bound median {np.median(e_out):.2e}")
+    assert np.median(dev) < math.log(2) / 32 / 8 and np.quantile(dev, 0.99) < math.log(2) / 32
+
+
 def test_training_save_load_and_reproducibility(env, prims, tmp_path):
     torch, si, _ = env
     print("\n[case] training", flush=True)
