@@ -287,6 +287,15 @@ si_status si_features(const si_scene* scene, const int32_t* oriented_idx, int64_
                       const si_params* params, float* feats_out, void* hip_stream);
 
 /*
+ * The same features for many scenes at once, as the batched learned
+ * schedule computes them: feats_out (device) receives sum(N) x 12 floats,
+ * the items' rows one after the other in item order (items with N == 0 add
+ * none).  The items' output buffers are not used.  Synchronises the stream.
+ */
+si_status si_features_batched(const si_batch_item* items, int32_t n_items, float* feats_out,
+                              void* hip_stream);
+
+/*
  * Learned per-image cost model: an MLP 12 -> 64 -> 64 -> 1 (ReLU, float32)
  * predicting log(1 + in-support count) from the features above.
  */
@@ -328,7 +337,8 @@ si_status si_cost_model_predict(const si_cost_model* model, const float* feats, 
  * weights and hidden activations rounded to fp16; biases, sums and the
  * output in fp32).  The planner only groups predicted unit costs into 32
  * buckets per octave, far coarser than this rounding.  Arguments as for
- * si_cost_model_predict.
+ * si_cost_model_predict; feats must be 16-byte aligned (SI_E_INVALID
+ * otherwise).
  */
 si_status si_cost_model_predict_planner(const si_cost_model* model, const float* feats, int64_t n,
                                         float* pred_counts, void* hip_stream);

@@ -25,7 +25,7 @@ __all__ = [
     "si_build_scene", "si_generate", "si_generate_batched", "si_features",
     "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
     "si_cost_model_predict_planner", "si_cost_model_gradient",
-    "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
+    "si_features_batched", "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
     "si_set_kernel_events", "si_autotune", "si_peak_probe",
     "SCHED", "MODE", "PROBE",
 ]
@@ -98,6 +98,7 @@ def lib():
             "si_generate_batched": (I32, [ctypes.POINTER(c_batch_item), I32, ctypes.POINTER(c_sched),
                                           I32, ctypes.POINTER(c_stats), P]),
             "si_features": (I32, [P, P, I64, ctypes.POINTER(c_params), P, P]),
+            "si_features_batched": (I32, [P, I32, P, P]),
             "si_cost_model_create": (I32, [U64, ctypes.POINTER(P)]),
             "si_free_cost_model": (None, [P]),
             "si_cost_model_train": (I32, [P, P, P, I64, I32, F, I32, P, P]),
@@ -339,6 +340,18 @@ def si_autotune(items, kind: str = "fac", use_graph: bool = True, max_trials: in
     sched = Sched(inv[best.kind], best.num_workgroups, best.min_chunk, best.fac_divisor,
                   None, True, best.group, {v: k for k, v in ORDER.items()}[best.order])
     return sched, float(ms.value)
+
+
+def si_features_batched(items, stream=None) -> torch.Tensor:
+    """Features of all items' images (list as for si_generate_batched), item after item."""
+    total = sum(int(it[1].shape[0]) for it in items)
+    dev = items[0][1].device if items else torch.device("cuda")
+    out = torch.empty((total, 12), dtype=torch.float32, device=dev)
+    if total:
+        arr = _batch_array(items)
+        _check(lib().si_features_batched(arr, len(items), _dev_ptr(out, torch.float32, "feats_out"),
+                                         _stream(stream)))
+    return out
 
 
 def si_features(scene: Scene, oriented_idx: torch.Tensor, params: Params, stream=None) -> torch.Tensor:

@@ -43,6 +43,8 @@ struct Flat {
     float divisor = 0.0f;
     std::vector<int64_t> unit_off;  // n + 1
     std::vector<float> f11;         // n
+    std::vector<int64_t> sat_off;   // 3 (n + 1)
+    int64_t sat_pass[3] = {0, 0, 0};
     int64_t n_units = 0;
 };
 
@@ -93,8 +95,9 @@ size_t layout(const Flat& f, FlatMem& m, char* base) {
     if (f.learned) {
         LearnedMulti size_only;
         const int ni = (int)f.items.size();
-        char* lb = take(learned_multi_layout(ni, f.total_N, f.n_units, f.n_wg, size_only, nullptr));
-        if (base) learned_multi_layout(ni, f.total_N, f.n_units, f.n_wg, m.lm, lb);
+        char* lb = take(learned_multi_layout(ni, f.total_N, f.n_units, f.n_wg, f.sat_pass,
+                                             size_only, nullptr));
+        if (base) learned_multi_layout(ni, f.total_N, f.n_units, f.n_wg, f.sat_pass, m.lm, lb);
     }
     m.base = base;
     m.bytes = o;
@@ -204,6 +207,10 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
         for (const Item& it : f.items) Ns.push_back(it.N);
         f.unit_off.resize(f.items.size() + 1);
         f.n_units = learned_units(Ns.data(), (int)Ns.size(), f.unit_off.data());
+        f.sat_off.resize(3 * (f.items.size() + 1));
+        const size_t n1 = f.items.size() + 1;
+        sat_offsets(f.items.data(), (int)f.items.size(), f.sat_off.data());
+        for (int k = 0; k < 3; ++k) f.sat_pass[k] = f.sat_off[(k + 1) * n1 - 1];
         f.divisor = sched->fac_divisor;
     } else {
         flat_chunks(f, sched->min_chunk, sched->fac_divisor);
@@ -231,6 +238,8 @@ si_status upload(const Flat& f, FlatMem& m, hipStream_t s) {
         SI_HIP(hipMemcpyAsync(m.lm.unit_off, f.unit_off.data(), sizeof(int64_t) * f.unit_off.size(),
                               hipMemcpyHostToDevice, s));
         SI_HIP(hipMemcpyAsync(m.lm.f11, f.f11.data(), sizeof(float) * f.f11.size(),
+                              hipMemcpyHostToDevice, s));
+        SI_HIP(hipMemcpyAsync(m.lm.sat_off, f.sat_off.data(), sizeof(int64_t) * f.sat_off.size(),
                               hipMemcpyHostToDevice, s));
     }
     if (!f.wg_first.empty())
@@ -523,4 +532,67 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
     float ms = 0.0f;
     SI_HIP(hipEventElapsedTime(&ms, e->ev0, e->ev1));
     return read_stats(st, e->flat, e->mem, ms, stats, s);
+}
+
+// Features of every image of many scenes in one pass of launches (the
+// batched learned planner's kernels, in item order).
+extern "C" si_status si_features_batched(const si_batch_item* items, int32_t n_items,
+                                         float* feats_out, void* hip_stream) {
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(SI_E_INVALID, "bad item list");
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<Item> its;
+    std::vector<int64_t> off(1, 0);
+    std::vector<float> f11;
+    for (int32_t k = 0; k < n_items; ++k) {
+        const si_batch_item& b = items[k];
+        if (b.N == 0) continue;
+        if (!b.scene || !b.oriented_idx || b.N < 0 || b.N >= INT32_MAX)
+            return fail(SI_E_INVALID, "batch item " + std::to_string(k) + ": bad scene, indices or N");
+        SpinParams p;
+        double R;
+        si_status rc = make_params(&b.params, &p, &R);
+        if (rc != SI_OK) return rc;
+        Item it;
+        memset(&it, 0, sizeof(it));
+        it.scene = view_of(*b.scene);
+        it.oriented = b.oriented_idx;
+        it.N = b.N;
+        its.push_back(it);
+        off.push_back(off.back() + b.N);
+        f11.push_back((float)(R / (kSub * b.scene->h)));
+    }
+    const int n = (int)its.size();
+    const int64_t total = off.back();
+    if (total == 0) return SI_OK;
+    if (!feats_out) return fail(SI_E_INVALID, "feats_out is NULL");
+    if (total >= INT32_MAX) return fail(SI_E_INVALID, "too many images");
+    std::vector<int64_t> sat_off(3 * (n + 1));
+    const int64_t sat_total = sat_offsets(its.data(), n, sat_off.data());
+    const int64_t pass_n[3] = {sat_off[n], sat_off[2 * n + 1], sat_off[3 * n + 2]};
+    auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_it = rup(sizeof(Item) * n), b_off = rup(sizeof(int64_t) * (n + 1));
+    const size_t b_f = rup(sizeof(float) * n), b_so = rup(sizeof(int64_t) * sat_off.size());
+    char* mem = nullptr;
+    SI_HIP(hipMallocAsync((void**)&mem, b_it + b_off + b_f + b_so + sizeof(int32_t) * sat_total, s));
+    Item* d_it = reinterpret_cast<Item*>(mem);
+    int64_t* d_off = reinterpret_cast<int64_t*>(mem + b_it);
+    float* d_f11 = reinterpret_cast<float*>(mem + b_it + b_off);
+    int64_t* d_so = reinterpret_cast<int64_t*>(mem + b_it + b_off + b_f);
+    int32_t* d_sat = reinterpret_cast<int32_t*>(mem + b_it + b_off + b_f + b_so);
+    hipError_t e = hipMemcpyAsync(d_it, its.data(), sizeof(Item) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_f11, f11.data(), sizeof(float) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_so, sat_off.data(), sizeof(int64_t) * sat_off.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_features_multi(d_it, d_off, n, nullptr, d_f11, d_so, d_sat, pass_n, total,
+                                  feats_out, s);
+    // the host tables are staged from pageable memory: wait before they go
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFreeAsync(mem, s);
+    if (e != hipSuccess) return hip_fail(e, "batched features");
+    return SI_OK;
 }

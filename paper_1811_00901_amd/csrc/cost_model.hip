@@ -50,8 +50,103 @@ constexpr int kKeys = 1024;              // LPT key buckets (32 per octave of co
 constexpr int kTile = 256;               // units per sort tile
 
 // ---------------------------------------------------------------- features --
-// The 12 features of oriented point o of the scene into f.
-__device__ void features_of(const SceneView& sc, int o, float f11, float* f) {
+// Summed-volume table of a grid's cell counts: S(z, y, x) = points in the
+// cells with cz < z, cy < y, cx < x, for 0 <= z <= dz, 0 <= y <= dy,
+// 0 <= x <= dx, at ((z (dy + 1) + y) (dx + 1) + x).  Three passes: the
+// counts along x come straight from the scene's key starts (a prefix along
+// each row), then running sums along y and along z.
+__host__ __device__ inline int64_t sat_entries(const int32_t* dims) {
+    return (int64_t)(dims[0] + 1) * (dims[1] + 1) * (dims[2] + 1);
+}
+
+__device__ void sat_x_entry(const SceneView& sc, int32_t* S, int64_t e) {
+    const int64_t X = sc.dims[0] + 1, Y = sc.dims[1] + 1;
+    const int x = (int)(e % X);
+    const int64_t t = e / X;
+    const int y = (int)(t % Y), z = (int)(t / Y);
+    int32_t v = 0;
+    if (y > 0 && z > 0) {
+        const int64_t row = ((int64_t)(z - 1) * sc.dims[1] + (y - 1)) * sc.dims[0];
+        v = sc.sub_start[(row + x) * kSubX] - sc.sub_start[row * kSubX];
+    }
+    S[e] = v;
+}
+
+// Running sum of len entries base, base + stride, ... (eight loads in flight).
+__device__ void sat_column(int32_t* S, int64_t base, int64_t stride, int len) {
+    int32_t run = 0;
+    int k = 0;
+    for (; k + 8 <= len; k += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = S[base + (k + j) * stride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            run += v[j];
+            S[base + (k + j) * stride] = run;
+        }
+    }
+    for (; k < len; ++k) {
+        run += S[base + k * stride];
+        S[base + k * stride] = run;
+    }
+}
+
+// axis 0: pass along x (entries); 1: running sums along y (columns z, x);
+// 2: along z (columns y, x)
+__device__ void sat_step(const SceneView& sc, int32_t* S, int axis, int64_t t) {
+    const int64_t X = sc.dims[0] + 1, Y = sc.dims[1] + 1, Z = sc.dims[2] + 1;
+    if (axis == 0) {
+        sat_x_entry(sc, S, t);
+    } else if (axis == 1) {
+        sat_column(S, (t / X) * Y * X + t % X, X, (int)Y);
+    } else {
+        sat_column(S, t, X * Y, (int)Z);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sat(SceneView sc, int32_t* __restrict__ S, int axis,
+                                             int64_t n) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < n) sat_step(sc, S, axis, t);
+}
+
+// The same over the items of a batch: off holds 3 (n_items + 1) prefix
+// offsets (entries, y columns, z columns); item i's table starts at entry
+// off[i].
+__device__ __forceinline__ int find_off3(const int64_t* off, int n, int64_t t) {
+    int lo = 0, hi = n - 1;  // largest i with off[i] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_sat_multi(const Item* __restrict__ items, int n_items,
+                                                   const int64_t* __restrict__ off,
+                                                   int32_t* __restrict__ S, int axis) {
+    const int64_t* o = off + (size_t)axis * (n_items + 1);
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= o[n_items]) return;
+    const int i = find_off3(o, n_items, t);
+    sat_step(items[i].scene, S + off[i], axis, t - o[i]);
+}
+
+hipError_t launch_sat(const SceneView& sc, int32_t* S, hipStream_t s) {
+    const int64_t X = sc.dims[0] + 1, Y = sc.dims[1] + 1, Z = sc.dims[2] + 1;
+    const int64_t n[3] = {X * Y * Z, X * Z, X * Y};
+    for (int axis = 0; axis < 3; ++axis)
+        hipLaunchKernelGGL(k_sat, dim3((unsigned)((n[axis] + 255) / 256)), dim3(256), 0, s, sc, S,
+                           axis, n[axis]);
+    return hipGetLastError();
+}
+
+// The 12 features of oriented point o of the scene into f: from S, the
+// scene's summed-volume table (TABLE), or by summing the block's grid rows
+// directly (the same integer counts).
+template <bool TABLE>
+__device__ void features_of(const SceneView& sc, const int32_t* S, int o, float f11, float* f) {
     if (o < 0 || o >= sc.M) {
         for (int k = 0; k < kNF; ++k) f[k] = 0.0f;
         return;
@@ -64,28 +159,50 @@ __device__ void features_of(const SceneView& sc, int o, float f11, float* f) {
                       cell / (sc.dims[0] * sc.dims[1])};
     const int half = kSub / 2;
     // point counts of the 3 x 3 x 3 coarse cells around p: coarse offset d
-    // covers fine cells c + kSub d - half .. c + kSub d + half on each axis;
-    // each fine row (y, z) contributes to three coarse cells through four
-    // cell boundaries along x (every kSubX-th entry of sub_start)
+    // covers fine cells c + kSub d - half .. c + kSub d + half on each axis
+    // (clipped to the grid), from the table at the 4 x 4 x 4 coarse corners
+    int bnd[3][4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int e[4] = {c[a] - kSub - half, c[a] - half, c[a] + half + 1, c[a] + kSub + half + 1};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bnd[a][b] = min(max(e[b], 0), sc.dims[a]);
+    }
     int occ[3][3][3] = {};
-    const int xb[4] = {c[0] - kSub - half, c[0] - half, c[0] + half + 1, c[0] + kSub + half + 1};
-    int xc[4];
+    if (TABLE) {
+        const int64_t X = sc.dims[0] + 1, Y = sc.dims[1] + 1;
+        int V[4][4][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) xc[b] = min(max(xb[b], 0), sc.dims[0]);
-    for (int zz = -kSub - half; zz <= kSub + half; ++zz) {
-        const int z = c[2] + zz;
-        if (z < 0 || z >= sc.dims[2]) continue;
-        const int dz = (zz + half + kSub) / kSub;  // 0, 1, 2 for offsets -1, 0, +1
-        for (int yy = -kSub - half; yy <= kSub + half; ++yy) {
-            const int y = c[1] + yy;
-            if (y < 0 || y >= sc.dims[1]) continue;
-            const int dy = (yy + half + kSub) / kSub;
-            const int row = (z * sc.dims[1] + y) * sc.dims[0];
-            int e[4];
+        for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) e[b] = sc.sub_start[(row + xc[b]) * kSubX];
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) occ[dz][dy][dx] += e[dx + 1] - e[dx];
+                for (int i = 0; i < 4; ++i)
+                    V[k][j][i] = S[((int64_t)bnd[2][k] * Y + bnd[1][j]) * X + bnd[0][i]];
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+                    occ[dz][dy][dx] = V[dz + 1][dy + 1][dx + 1] - V[dz][dy + 1][dx + 1] -
+                                      V[dz + 1][dy][dx + 1] - V[dz + 1][dy + 1][dx] +
+                                      V[dz][dy][dx + 1] + V[dz][dy + 1][dx] +
+                                      V[dz + 1][dy][dx] - V[dz][dy][dx];
+    } else {
+        // without a table: each fine row (y, z) of the block adds its counts
+        // between the four x boundaries (every kSubX-th entry of sub_start)
+        for (int z = bnd[2][0]; z < bnd[2][3]; ++z) {
+            const int dz = z < bnd[2][1] ? 0 : (z < bnd[2][2] ? 1 : 2);
+            for (int y = bnd[1][0]; y < bnd[1][3]; ++y) {
+                const int dy = y < bnd[1][1] ? 0 : (y < bnd[1][2] ? 1 : 2);
+                const int64_t row = ((int64_t)z * sc.dims[1] + y) * sc.dims[0];
+                int e[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) e[b] = sc.sub_start[(row + bnd[0][b]) * kSubX];
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) occ[dz][dy][dx] += e[dx + 1] - e[dx];
+            }
         }
     }
     float shell[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -121,23 +238,27 @@ __device__ void features_of(const SceneView& sc, int o, float f11, float* f) {
     f[11] = f11;
 }
 
-__global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* __restrict__ oriented,
+template <bool TABLE>
+__global__ void __launch_bounds__(256) k_features(SceneView sc, const int32_t* __restrict__ S,
+                                                  const int32_t* __restrict__ oriented,
                                                   int64_t N, float f11, float* __restrict__ feats) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= N) return;
-    features_of(sc, oriented[i], f11, feats + kNF * i);
+    features_of<TABLE>(sc, S, oriented[i], f11, feats + kNF * i);
 }
 
 // Features of loop position t (iteration perm[t], or t) into feats[t]: in the
 // cell order, the lanes of a wave read the same grid rows.
+template <bool TABLE>
 __global__ void __launch_bounds__(256) k_features_loop(SceneView sc,
+                                                       const int32_t* __restrict__ S,
                                                        const int32_t* __restrict__ oriented,
                                                        const int32_t* __restrict__ perm,
                                                        int64_t N, float f11,
                                                        float* __restrict__ feats) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= N) return;
-    features_of(sc, oriented[perm ? perm[t] : t], f11, feats + kNF * t);
+    features_of<TABLE>(sc, S, oriented[perm ? perm[t] : t], f11, feats + kNF * t);
 }
 
 // ------------------------------------------------------------- MLP forward --
@@ -216,15 +337,25 @@ __global__ void __launch_bounds__(256) k_mlp_predict_mfma(const float* __restric
     const int64_t n_tiles = (n + 15) / 16;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // features 4 kb .. 4 kb + 3 of this lane's image of a tile (one 16-byte
+    // load; K block 3 is the zero padding), the next tile's fetched while the
+    // current one is computed
+    auto load_x = [&](int64_t tile) {
+        f32x4m v = {0.0f, 0.0f, 0.0f, 0.0f};
+        const int64_t img = tile * 16 + r16;
+        if (tile < n_tiles && img < n && kb < kNF / 4)
+            v = *reinterpret_cast<const f32x4m*>(feats + kNF * img + 4 * kb);
+        return v;
+    };
+    f32x4m xn = load_x(wave);
     for (int64_t tile = wave; tile < n_tiles; tile += n_waves) {
         const int64_t img = tile * 16 + r16;
-        // B operand of layer 1: features 4 kb .. 4 kb + 3 of image img
+        const f32x4m xf = xn;
+        xn = load_x(tile + n_waves);
+        // B operand of layer 1
         h16x4 x;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = 4 * kb + i;
-            x[i] = (_Float16)(img < n && k < kNF ? feats[kNF * img + k] : 0.0f);
-        }
+        for (int i = 0; i < 4; ++i) x[i] = (_Float16)xf[i];
         h16x4 h1[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -653,19 +784,51 @@ __device__ __forceinline__ int find_off(const int64_t* off, int n, int64_t t) {
 
 // Features of flattened iteration t (the image of item i's iteration
 // perm_cell[t], or t - item_off[i] without a cell order).
+template <bool TABLE>
 __global__ void __launch_bounds__(256) k_features_multi(const Item* __restrict__ items,
                                                         const int64_t* __restrict__ item_off,
                                                         int n_items,
                                                         const int32_t* __restrict__ perm_cell,
                                                         const float* __restrict__ f11,
+                                                        const int64_t* __restrict__ sat_off,
+                                                        const int32_t* __restrict__ sat,
                                                         int64_t total_N, float* __restrict__ feats) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= total_N) return;
     const int i = find_off(item_off, n_items, t);
     const Item& it = items[i];
     const int w = perm_cell ? perm_cell[t] : (int)(t - item_off[i]);
-    features_of(it.scene, it.oriented[w], f11[i], feats + kNF * t);
+    // items with a table have entries in it; the other launch takes the rest
+    if ((sat_off[i + 1] > sat_off[i]) != TABLE) return;
+    features_of<TABLE>(it.scene, sat + sat_off[i], it.oriented[w], f11[i], feats + kNF * t);
 }
+
+}  // namespace
+
+// Summed-volume tables of the items' grids (sat_off: entry and column
+// offsets as sat_offsets writes them), then the features of every loop
+// position t of the concatenated items (item-local iteration perm_cell[t],
+// or t - item_off[i]) into feats[t].
+hipError_t launch_features_multi(const Item* items, const int64_t* item_off, int n_items,
+                                 const int32_t* perm_cell, const float* f11,
+                                 const int64_t* sat_off, int32_t* sat, const int64_t pass_n[3],
+                                 int64_t total_N, float* feats, hipStream_t s) {
+    // pass_n: entries, y columns and z columns over all items (host copies of
+    // the last offsets)
+    for (int axis = 0; axis < 3; ++axis)
+        if (pass_n[axis] > 0)
+            hipLaunchKernelGGL(k_sat_multi, dim3((unsigned)((pass_n[axis] + 255) / 256)), dim3(256),
+                               0, s, items, n_items, sat_off, sat, axis);
+    const dim3 grid((unsigned)((total_N + 255) / 256));
+    if (pass_n[0] > 0)
+        hipLaunchKernelGGL(k_features_multi<true>, grid, dim3(256), 0, s, items, item_off, n_items,
+                           perm_cell, f11, sat_off, sat, total_N, feats);
+    hipLaunchKernelGGL(k_features_multi<false>, grid, dim3(256), 0, s, items, item_off, n_items,
+                       perm_cell, f11, sat_off, sat, total_N, feats);
+    return hipGetLastError();
+}
+
+namespace {
 
 // Cost and key of unit u (as k_unit_cost), its length and item, and the
 // per-(item, key) unit and iteration counts.
@@ -851,9 +1014,24 @@ si_status features_launch(const Scene& sc, const int32_t* oriented, int64_t N,
     si_status rc = make_params(params, &p, &R);
     if (rc != SI_OK) return rc;
     const float f11 = (float)(R / (kSub * sc.h));
-    hipLaunchKernelGGL(k_features, dim3(nblocks(N)), dim3(256), 0, s, view_of(sc), oriented, N, f11,
-                       feats);
-    SI_HIP(hipGetLastError());
+    const SceneView v = view_of(sc);
+    int32_t* S = nullptr;
+    hipError_t e = hipSuccess;
+    if (use_feature_table(v.dims, N)) {
+        SI_HIP(hipMallocAsync((void**)&S, sizeof(int32_t) * sat_entries(v.dims), s));
+        e = launch_sat(v, S, s);
+    }
+    if (e == hipSuccess) {
+        if (S)
+            hipLaunchKernelGGL(k_features<true>, dim3(nblocks(N)), dim3(256), 0, s, v, S, oriented,
+                               N, f11, feats);
+        else
+            hipLaunchKernelGGL(k_features<false>, dim3(nblocks(N)), dim3(256), 0, s, v, S,
+                               oriented, N, f11, feats);
+        e = hipGetLastError();
+    }
+    if (S) (void)hipFreeAsync(S, s);
+    if (e != hipSuccess) return hip_fail(e, "features");
     return SI_OK;
 }
 
@@ -877,6 +1055,8 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
     const size_t o_starts = take(sizeof(int32_t) * (scene->M + 1));
     const size_t o_tmp = take(sizeof(int32_t) * nt);
     const size_t o_feats = take(sizeof(float) * kNF * N);
+    const bool table = use_feature_table(scene->dims, N);
+    const size_t o_sat = take(sizeof(int32_t) * (table ? sat_entries(scene->dims) : 1));
     const size_t o_pred = take(sizeof(float) * N);
     const size_t o_qcost = take(sizeof(uint32_t) * n_units);
     const size_t o_ukey = take(sizeof(int32_t) * n_units);
@@ -910,9 +1090,16 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
         SpinParams p;
         double R;
         if (make_params(params, &p, &R) != SI_OK) e = hipErrorInvalidValue;
-        if (e == hipSuccess)
-            hipLaunchKernelGGL(k_features_loop, dim3(nblocks(N)), dim3(256), 0, s, view_of(*scene),
-                               oriented, perm0, N, (float)(R / (kSub * scene->h)), feats);
+        const SceneView v = view_of(*scene);
+        int32_t* S = table ? reinterpret_cast<int32_t*>(mem + o_sat) : nullptr;
+        if (e == hipSuccess && S) e = launch_sat(v, S, s);
+        const float f11 = (float)(R / (kSub * scene->h));
+        if (e == hipSuccess && S)
+            hipLaunchKernelGGL(k_features_loop<true>, dim3(nblocks(N)), dim3(256), 0, s, v, S,
+                               oriented, perm0, N, f11, feats);
+        else if (e == hipSuccess)
+            hipLaunchKernelGGL(k_features_loop<false>, dim3(nblocks(N)), dim3(256), 0, s, v, S,
+                               oriented, perm0, N, f11, feats);
     }
     if (e == hipSuccess) {
         e = launch_mlp_predict_mfma(model->params, feats, N, pred, 0, s);
@@ -960,8 +1147,34 @@ int64_t learned_units(const int64_t* item_N, int n_items, int64_t* unit_off) {
     return u;
 }
 
+bool use_feature_table(const int32_t* dims, int64_t N) {
+    // measured on clustered2m: about 6 ns per table entry to build, then 33 ns
+    // per image, against 123 ns per image summing grid rows
+    if (const char* f = getenv("SI_FEATURES_TABLE")) {
+        if (!strcmp(f, "always")) return true;
+        if (!strcmp(f, "never")) return false;
+    }
+    return sat_entries(dims) <= 15 * N;
+}
+
+int64_t sat_offsets(const Item* items, int n_items, int64_t* off) {
+    int64_t* e = off;
+    int64_t* y = off + (n_items + 1);
+    int64_t* z = off + 2 * (n_items + 1);
+    e[0] = y[0] = z[0] = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const int32_t* d = items[i].scene.dims;
+        const bool t = use_feature_table(d, items[i].N);
+        e[i + 1] = e[i] + (t ? sat_entries(d) : 0);
+        y[i + 1] = y[i] + (t ? (int64_t)(d[0] + 1) * (d[2] + 1) : 0);
+        z[i + 1] = z[i] + (t ? (int64_t)(d[0] + 1) * (d[1] + 1) : 0);
+    }
+    return e[n_items];
+}
+
 size_t learned_multi_layout(int n_items, int64_t total_N, int64_t n_units, int P,
-                            LearnedMulti& b, char* base) {
+                            const int64_t sat_pass[3], LearnedMulti& b, char* base) {
+    const int64_t sat_total = sat_pass[0];
     size_t o = 0;
     auto take = [&](size_t bytes) {
         char* p = base ? base + o : nullptr;
@@ -1001,6 +1214,9 @@ size_t learned_multi_layout(int n_items, int64_t total_N, int64_t n_units, int P
     b.perm = (int32_t*)take(sizeof(int32_t) * total_N);
     b.chunks = (Chunk*)take(sizeof(Chunk) * n_units);
     b.n_chunks = (int32_t*)take(sizeof(int32_t));
+    b.sat_off = (int64_t*)take(sizeof(int64_t) * 3 * (n_items + 1));
+    b.sat = (int32_t*)take(sizeof(int32_t) * sat_total);
+    for (int k = 0; k < 3; ++k) b.sat_pass[k] = sat_pass[k];
     return o;
 }
 
@@ -1014,8 +1230,9 @@ hipError_t learned_multi_enqueue(const si_cost_model* model, const LearnedMulti&
     if (e == hipSuccess) e = launch_fill(b.hlen, ik, 0, s);
     if (e == hipSuccess) e = launch_fill(b.cut, n_units, 0, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_features_multi, dim3(nblocks(total_N)), dim3(256), 0, s, items, item_off,
-                       n_items, perm_cell, b.f11, total_N, b.feats);
+    e = launch_features_multi(items, item_off, n_items, perm_cell, b.f11, b.sat_off, b.sat,
+                              b.sat_pass, total_N, b.feats, s);
+    if (e != hipSuccess) return e;
     e = launch_mlp_predict_mfma(model->params, b.feats, total_N, b.pred, 0, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_unit_cost_multi, dim3(nblocks(n_units)), dim3(256), 0, s, b.pred,
@@ -1201,6 +1418,8 @@ si_status si_cost_model_predict_planner(const si_cost_model* m, const float* fea
                                         float* pred_counts, void* hip_stream) {
     if (!m || (n > 0 && (!feats || !pred_counts))) return fail(SI_E_INVALID, "bad arguments");
     if (n <= 0) return SI_OK;
+    if (reinterpret_cast<uintptr_t>(feats) & 15)
+        return fail(SI_E_INVALID, "feats must be 16-byte aligned");
     SI_HIP(launch_mlp_predict_mfma(m->params, feats, n, pred_counts, 0, (hipStream_t)hip_stream));
     return SI_OK;
 }

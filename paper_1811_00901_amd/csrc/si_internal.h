@@ -232,10 +232,27 @@ struct LearnedMulti {
     int32_t* perm = nullptr;
     Chunk* chunks = nullptr;
     int32_t* n_chunks = nullptr;
+    // summed-volume tables of the items' grids: entry offsets, and the column
+    // offsets of the y and z passes, 3 x (n_items + 1) int64; the tables
+    int64_t* sat_off = nullptr;
+    int32_t* sat = nullptr;
+    int64_t sat_pass[3] = {0, 0, 0};  // entries, y columns, z columns
 };
 int64_t learned_units(const int64_t* item_N, int n_items, int64_t* unit_off_host);
+// Host offsets of the items' summed-volume tables: sat_off_host gets
+// 3 x (n_items + 1) entries (entries, y columns, z columns); returns the
+// total number of table entries.
+int64_t sat_offsets(const Item* items, int n_items, int64_t* sat_off_host);
+// Whether the features of N images of a grid of these dims come from a
+// summed-volume table (built per call) rather than from summing grid rows;
+// SI_FEATURES_TABLE = always / never overrides, for tests.
+bool use_feature_table(const int32_t* dims, int64_t N);
+hipError_t launch_features_multi(const Item* items, const int64_t* item_off, int n_items,
+                                 const int32_t* perm_cell, const float* f11,
+                                 const int64_t* sat_off, int32_t* sat, const int64_t pass_n[3],
+                                 int64_t total_N, float* feats, hipStream_t s);
 size_t learned_multi_layout(int n_items, int64_t total_N, int64_t n_units, int P,
-                            LearnedMulti& b, char* base);
+                            const int64_t sat_pass[3], LearnedMulti& b, char* base);
 hipError_t learned_multi_enqueue(const si_cost_model* model, const LearnedMulti& b,
                                  const Item* items, const int64_t* item_off, int n_items,
                                  const int32_t* perm_cell, int64_t total_N, int64_t n_units, int P,

@@ -216,3 +216,30 @@ def test_batched_learned(env, use_graph):
     with pytest.raises(si.SiError):
         si.si_generate_batched(items_of(batch), si.Sched("learned", fallback_to_fac=False),
                                use_graph=use_graph)
+
+
+def test_batched_features_equal_per_scene(env, monkeypatch):
+    """The batched learned planner's features (per-item summed-volume tables,
+    one launch per pass for all items) equal si_features of each scene, bit
+    for bit: both are integer box counts through the same arithmetic.  One
+    scene is brute force (a single cell), one item is empty."""
+    torch, si, _ = env
+    print("\n[case] batched features", flush=True)
+    batch = make_batch(torch, si, n_scenes=9, seed=4400, brute=(4,))
+    items = items_of(batch)
+    empty = (batch[0]["scene"], batch[0]["idx"][:0], batch[0]["params"],
+             batch[0]["img"][:0], batch[0]["cnt"][:0])
+    items.insert(3, empty)
+    got = si.si_features_batched(items)
+    exp = torch.cat([si.si_features(b["scene"], b["idx"], b["params"]) for b in batch])
+    torch.cuda.synchronize()
+    assert got.shape == exp.shape
+    assert torch.equal(got, exp)
+    # the batch mixes scenes that take the summed-volume table with scenes
+    # that sum grid rows; forcing either path for all gives the same features
+    for mode in ("always", "never"):
+        monkeypatch.setenv("SI_FEATURES_TABLE", mode)
+        forced = si.si_features_batched(items)
+        torch.cuda.synchronize()
+        assert torch.equal(forced, exp)
+    monkeypatch.delenv("SI_FEATURES_TABLE")

@@ -54,6 +54,22 @@ def test_features_vs_oracle(env, prims):
     np.testing.assert_allclose(got, exp, rtol=2e-5, atol=2e-6)
 
 
+def test_features_table_and_rows_agree(env, prims, monkeypatch):
+    """Features from the summed-volume table and from summing grid rows are the
+    same integer box counts, so the two paths agree bit for bit (the library
+    picks one per scene by its grid size and image count)."""
+    torch, si, _ = env
+    print("\n[case] features: table against rows", flush=True)
+    out = {}
+    for mode in ("always", "never"):
+        monkeypatch.setenv("SI_FEATURES_TABLE", mode)
+        out[mode] = si.si_features(prims["scene"], prims["idx"], prims["params"])
+    monkeypatch.delenv("SI_FEATURES_TABLE")
+    torch.cuda.synchronize()
+    assert torch.equal(out["always"], out["never"])
+    assert torch.equal(out["always"], prims["feats"])
+
+
 def test_gradient_and_forward_vs_oracle(env, prims):
     torch, si, _ = env
     print("\n[case] gradient", flush=True)
