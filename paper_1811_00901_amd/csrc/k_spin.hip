@@ -37,6 +37,7 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kInfo = 64;     // images whose descriptors are staged at once
+static_assert(kInfo == 64, "group formation reads staged image l from lane l of a wave");
 constexpr int kMaxRows = 64;  // candidate rows per group (one lane each)
 
 struct __attribute__((aligned(16))) ImgInfo {
