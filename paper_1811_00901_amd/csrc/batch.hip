@@ -465,7 +465,7 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
         FlatMem m;
         const size_t bytes = layout(f, m, nullptr);
         char* base = nullptr;
-        SI_HIP(hipMallocAsync((void**)&base, bytes, s));
+        SI_HIP(pool_alloc((void**)&base, bytes, s));
         layout(f, m, base);
         rc = upload(f, m, s);
         // the staged host tables are about to go out of scope
@@ -573,7 +573,7 @@ extern "C" si_status si_features_batched(const si_batch_item* items, int32_t n_i
     const size_t b_it = rup(sizeof(Item) * n), b_off = rup(sizeof(int64_t) * (n + 1));
     const size_t b_f = rup(sizeof(float) * n), b_so = rup(sizeof(int64_t) * sat_off.size());
     char* mem = nullptr;
-    SI_HIP(hipMallocAsync((void**)&mem, b_it + b_off + b_f + b_so + sizeof(int32_t) * sat_total, s));
+    SI_HIP(pool_alloc((void**)&mem, b_it + b_off + b_f + b_so + sizeof(int32_t) * sat_total, s));
     Item* d_it = reinterpret_cast<Item*>(mem);
     int64_t* d_off = reinterpret_cast<int64_t*>(mem + b_it);
     float* d_f11 = reinterpret_cast<float*>(mem + b_it + b_off);

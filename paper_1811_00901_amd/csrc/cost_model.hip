@@ -1018,7 +1018,7 @@ si_status features_launch(const Scene& sc, const int32_t* oriented, int64_t N,
     int32_t* S = nullptr;
     hipError_t e = hipSuccess;
     if (use_feature_table(v.dims, N)) {
-        SI_HIP(hipMallocAsync((void**)&S, sizeof(int32_t) * sat_entries(v.dims), s));
+        SI_HIP(pool_alloc((void**)&S, sizeof(int32_t) * sat_entries(v.dims), s));
         e = launch_sat(v, S, s);
     }
     if (e == hipSuccess) {
@@ -1074,7 +1074,7 @@ si_status learned_table(DeviceState*, const Scene* scene, const int32_t* oriente
     const size_t o_nch = take(sizeof(int32_t));
     const size_t o_perm = take(sizeof(int32_t) * N);
     char* mem = nullptr;
-    SI_HIP(hipMallocAsync((void**)&mem, o, s));
+    SI_HIP(pool_alloc((void**)&mem, o, s));
     auto I = [&](size_t off) { return reinterpret_cast<int32_t*>(mem + off); };
     int32_t* perm0 = nullptr;
     hipError_t e = hipSuccess;
@@ -1327,7 +1327,7 @@ si_status si_cost_model_gradient(const si_cost_model* m, const float* feats, con
     hipStream_t s = (hipStream_t)hip_stream;
     const int nblk = (int)((n + kGradSamples - 1) / kGradSamples);
     float* mem = nullptr;
-    SI_HIP(hipMallocAsync((void**)&mem, sizeof(float) * ((size_t)nblk * (kNP + 1) + kNP + 1), s));
+    SI_HIP(pool_alloc((void**)&mem, sizeof(float) * ((size_t)nblk * (kNP + 1) + kNP + 1), s));
     float* part = mem;
     float* grad = mem + (size_t)nblk * (kNP + 1);
     float* loss = grad + kNP;
@@ -1358,7 +1358,7 @@ si_status si_cost_model_train(si_cost_model* m, const float* feats, const uint32
     const int nblk_max = (batch + kGradSamples - 1) / kGradSamples;
     size_t words = (size_t)nblk_max * (kNP + 1) + kNP + (size_t)std::max(epochs, 1) + (size_t)n;
     float* mem = nullptr;
-    SI_HIP(hipMallocAsync((void**)&mem, sizeof(float) * words, s));
+    SI_HIP(pool_alloc((void**)&mem, sizeof(float) * words, s));
     float* part = mem;
     float* grad = part + (size_t)nblk_max * (kNP + 1);
     float* losses = grad + kNP;

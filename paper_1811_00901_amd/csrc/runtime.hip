@@ -33,6 +33,16 @@ si_status hip_fail(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? SI_E_OOM : SI_E_DEVICE;
 }
 
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
+    if (const char* lim = getenv("SI_TEST_ALLOC_FAIL")) {
+        if (bytes >= (size_t)strtoull(lim, nullptr, 10)) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    return hipMallocAsync(p, bytes, s);
+}
+
 // caller-supplied events recorded around spin-kernel launches (this thread)
 static thread_local hipEvent_t g_ev_begin = nullptr;
 static thread_local hipEvent_t g_ev_end = nullptr;
@@ -259,8 +269,8 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
 
     // ---- bounding box (the one synchronisation) ----
     float* bb = nullptr;
-    hipError_t e = hipMallocAsync((void**)&bb, sizeof(float) * (8 + 6 * 1024), s);
-    if (e != hipSuccess) { delete sc; return hip_fail(e, "hipMallocAsync(bbox)"); }
+    hipError_t e = pool_alloc((void**)&bb, sizeof(float) * (8 + 6 * 1024), s);
+    if (e != hipSuccess) { delete sc; return hip_fail(e, "bounding-box scratch"); }
     float hb[6];
     e = launch_bbox(points_xyz, M, bb, s);
     if (e == hipSuccess) e = hipMemcpyAsync(hb, bb, sizeof(hb), hipMemcpyDeviceToHost, s);
@@ -313,14 +323,14 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     const size_t b_sub = rup(sizeof(int32_t) * (n_keys + 1));
     const size_t b_key = rup(sizeof(int32_t) * n_keys);
     char* tmem = nullptr;
-    e = hipMallocAsync(&sc->mem, 2 * b_pos + b_inv + b_sub, s);
+    e = pool_alloc(&sc->mem, 2 * b_pos + b_inv + b_sub, s);
     if (e == hipSuccess) {
         char* m = static_cast<char*>(sc->mem);
         sc->pos = reinterpret_cast<float4*>(m);
         sc->nrm = reinterpret_cast<float4*>(m + b_pos);
         sc->inv = reinterpret_cast<int32_t*>(m + 2 * b_pos);
         sc->sub_start = reinterpret_cast<int32_t*>(m + 2 * b_pos + b_inv);
-        e = hipMallocAsync((void**)&tmem, 2 * b_inv + b_key + rup(sizeof(int32_t) * ntmp), s);
+        e = pool_alloc((void**)&tmem, 2 * b_inv + b_key + rup(sizeof(int32_t) * ntmp), s);
     }
     if (e == hipSuccess) {
         key_of = reinterpret_cast<int32_t*>(tmem);
@@ -513,7 +523,7 @@ si_status cell_order(const Scene& sc, const int32_t* oriented, int64_t N, hipStr
     const int64_t nt = scan_tmp_elems(sc.M);
     const int64_t words = 3 * N + sc.M + (sc.M + 1) + nt;
     int32_t* mem = nullptr;
-    SI_HIP(hipMallocAsync((void**)&mem, sizeof(int32_t) * words, s));
+    SI_HIP(pool_alloc((void**)&mem, sizeof(int32_t) * words, s));
     int32_t* perm = mem;
     int32_t* key = perm + N;
     int32_t* rank = key + N;

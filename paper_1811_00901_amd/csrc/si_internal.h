@@ -176,6 +176,11 @@ struct DeviceState {
 };
 
 si_status device_state(DeviceState** out);
+// Stream-ordered allocation from the device's memory pool.  The environment
+// variable SI_TEST_ALLOC_FAIL, set to a byte count, makes every request of at
+// least that many bytes fail with hipErrorOutOfMemory: a test hook for the
+// out-of-memory paths.
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
 // events registered by si_set_kernel_events on this thread (or null)
 void user_kernel_events(hipEvent_t* begin, hipEvent_t* end);
 uint32_t* take_counter(DeviceState* st);

@@ -248,6 +248,69 @@ def test_invalid_arguments(env):
     assert st["sched_used"] == 3   # fell back to FAC
 
 
+def test_out_of_memory_is_reported(env, monkeypatch):
+    """A failed device allocation surfaces as SI_E_OOM (through the
+    library's allocation hook), leaves nothing half-built, and the next
+    calls work as before."""
+    print_case("out of memory")
+    torch, si, _ = env
+    xyz, nrm = sg.uniform_box_scene(2000, seed=5, box=2.0)
+    params = si.Params(16, 0.02, S60)
+    radius = si.si_support_radius(params)
+    idx = to_dev(torch, np.arange(0, 2000, 3, dtype=np.int32))
+    oom = next(k for k, v in si.STATUS.items() if v == "SI_E_OOM")
+    monkeypatch.setenv("SI_TEST_ALLOC_FAIL", "1")
+    with pytest.raises(si.SiError) as ei:
+        si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), radius)
+    assert ei.value.status == oom
+    monkeypatch.delenv("SI_TEST_ALLOC_FAIL")
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), radius)
+    ref_img, ref_cnt, _ = si.si_generate(scene, idx, params, si.Sched("fac"))
+    # the loop order's temporaries and the features' table fail the same way
+    monkeypatch.setenv("SI_TEST_ALLOC_FAIL", "1")
+    with pytest.raises(si.SiError) as ei:
+        si.si_generate(scene, idx, params, si.Sched("fac"))
+    assert ei.value.status == oom
+    with pytest.raises(si.SiError) as ei:
+        si.si_features(scene, idx, params)
+    assert ei.value.status == oom
+    monkeypatch.delenv("SI_TEST_ALLOC_FAIL")
+    img, cnt, _ = si.si_generate(scene, idx, params, si.Sched("fac"))
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref_img) and torch.equal(cnt, ref_cnt)
+
+
+def test_generation_is_asynchronous_on_its_stream(env):
+    """si_generate only queues work on the given stream: it returns before the
+    launch has finished, another stream is not held up, and the result equals
+    that of the default stream."""
+    print_case("stream asynchrony")
+    torch, si, _ = env
+    xyz, nrm = sg.config_scene("prims100k", M=60000)
+    params = si.Params(32, 0.02, S60)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(params))
+    idx = to_dev(torch, np.arange(60000, dtype=np.int32))
+    ref_img, ref_cnt, _ = si.si_generate(scene, idx, params, si.Sched("fac"))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    img = torch.empty_like(ref_img)
+    cnt = torch.empty_like(ref_cnt)
+    done = torch.cuda.Event()
+    with torch.cuda.stream(side):
+        # queue a long stretch of work behind the launch on the side stream
+        for _ in range(10):
+            si.si_generate(scene, idx, params, si.Sched("fac"), img, cnt, stream=side)
+        done.record(side)
+        queued_before_finish = not done.query()
+    # the default stream runs its own small work meanwhile
+    other = torch.ones(1 << 20, device="cuda").sum()
+    torch.cuda.current_stream().synchronize()
+    assert float(other) == float(1 << 20)
+    side.synchronize()
+    assert queued_before_finish
+    assert torch.equal(img, ref_img) and torch.equal(cnt, ref_cnt)
+
+
 def test_overflow_path_identical(env):
     """Forcing every image through the 64-bit re-accumulation path gives the
     same images and counts."""
