@@ -192,6 +192,35 @@ typedef struct si_scene_info {
 si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int64_t M,
                          float max_support_radius, void* hip_stream, si_scene** out);
 
+/* One scene of si_build_scenes: the arguments of si_build_scene. */
+typedef struct si_scene_desc {
+    const float* points_xyz;    /* device, M x 3 float32; read only */
+    const float* normals_xyz;   /* device, M x 3 float32; read only */
+    int64_t M;                  /* > 0, < 2^31 */
+    float max_support_radius;   /* as for si_build_scene */
+} si_scene_desc;
+
+/*
+ * Build n scenes at once (for batches of many scenes, si_generate_batched):
+ * each out[i] is the scene si_build_scene builds from descs[i] -- the same
+ * grid and the same points in every cell key; points of one key may lie in
+ * another order, which no image, count or feature depends on.  The work is
+ * a fixed number of launches for all scenes together (bounding boxes, then
+ * binning, scan and scatter in sub-batches of at most 2^27 cell keys and
+ * 2^28 points, any single scene accepted), with one synchronisation for the
+ * bounding boxes and one per sub-batch, instead of one synchronisation and
+ * about ten launches per scene.  On return every out[i] is ready for work on
+ * any stream.  The scenes' arrays share one allocation from the device's
+ * pool, released with the last of them; each scene is released with
+ * si_free_scene, in any order (the others stay valid).
+ *   descs  host array of n descriptions; out  host array of n handles
+ * n == 0 does nothing.  Returns SI_E_INVALID (naming the scene) for an
+ * invalid description, NULL descs/out or n < 0; on any error no scene is
+ * built and every out[i] is NULL.
+ */
+si_status si_build_scenes(const si_scene_desc* descs, int32_t n, void* hip_stream,
+                          si_scene** out);
+
 /* Release a scene (NULL is ignored).  Work using it must have completed. */
 void si_free_scene(si_scene* scene);
 

@@ -6,7 +6,7 @@ step of spin-image generation runs in the library's HIP kernels.  PyTorch is
 used for device memory and streams.  There is no fallback: if the library is
 not built this module raises on first use.
 
-Names follow the C ABI: ``si_build_scene``, ``si_generate``,
+Names follow the C ABI: ``si_build_scene`` (``si_build_scenes``), ``si_generate``,
 ``si_generate_batched``, ``si_features``, ``si_cost_model_*``,
 ``si_chunk_table``, ``si_learned_table``, ``si_support_radius``.
 """
@@ -22,7 +22,7 @@ import torch
 
 __all__ = [
     "SiError", "Params", "Sched", "Scene", "CostModel", "lib",
-    "si_build_scene", "si_generate", "si_generate_batched", "si_features",
+    "si_build_scene", "si_build_scenes", "si_generate", "si_generate_batched", "si_features",
     "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
     "si_cost_model_predict_planner", "si_cost_model_gradient",
     "si_features_batched", "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
@@ -71,6 +71,11 @@ class c_scene_info(ctypes.Structure):
                 ("origin", ctypes.c_float * 3), ("n_cells", ctypes.c_int64)]
 
 
+class c_scene_desc(ctypes.Structure):
+    _fields_ = [("points_xyz", ctypes.c_void_p), ("normals_xyz", ctypes.c_void_p),
+                ("M", ctypes.c_int64), ("max_support_radius", ctypes.c_float)]
+
+
 class c_batch_item(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_void_p), ("oriented_idx", ctypes.c_void_p),
                 ("N", ctypes.c_int64), ("params", c_params),
@@ -90,6 +95,7 @@ def lib():
         P, I32, I64, F, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64
         sig = {
             "si_build_scene": (I32, [P, P, I64, F, P, ctypes.POINTER(P)]),
+            "si_build_scenes": (I32, [ctypes.POINTER(c_scene_desc), I32, P, ctypes.POINTER(P)]),
             "si_free_scene": (None, [P]),
             "si_scene_info_get": (I32, [P, ctypes.POINTER(c_scene_info)]),
             "si_support_radius": (I32, [ctypes.POINTER(c_params), ctypes.POINTER(F)]),
@@ -250,6 +256,25 @@ def si_build_scene(points: torch.Tensor, normals: torch.Tensor, max_support_radi
     _check(lib().si_build_scene(pp, nn, M, float(max_support_radius), _stream(stream),
                                 ctypes.byref(h)))
     return Scene(h, M, points.device.index or 0)
+
+
+def si_build_scenes(scenes, stream=None) -> list:
+    """Build many scenes at once from (points, normals, max_support_radius)
+    triples of device (M, 3) float32 tensors; returns one Scene per triple,
+    each the scene si_build_scene would build from it."""
+    scenes = list(scenes)
+    n = len(scenes)
+    descs = (c_scene_desc * max(1, n))()
+    for i, (points, normals, radius) in enumerate(scenes):
+        M = int(points.shape[0])
+        descs[i].points_xyz = _dev_ptr(points, torch.float32, f"points[{i}]", (M, 3)).value
+        descs[i].normals_xyz = _dev_ptr(normals, torch.float32, f"normals[{i}]", (M, 3)).value
+        descs[i].M = M
+        descs[i].max_support_radius = float(radius)
+    handles = (ctypes.c_void_p * max(1, n))()
+    _check(lib().si_build_scenes(descs, n, _stream(stream), handles))
+    return [Scene(ctypes.c_void_p(handles[i]), int(scenes[i][0].shape[0]),
+                  scenes[i][0].device.index or 0) for i in range(n)]
 
 
 def _stats_dict(st: c_stats, busy) -> dict:

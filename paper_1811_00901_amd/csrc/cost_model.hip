@@ -111,11 +111,9 @@ __global__ void __launch_bounds__(256) k_sat(SceneView sc, int32_t* __restrict__
     if (t < n) sat_step(sc, S, axis, t);
 }
 
-// The same over the items of a batch: off holds 3 (n_items + 1) prefix
-// offsets (entries, y columns, z columns); item i's table starts at entry
-// off[i].
-__device__ __forceinline__ int find_off3(const int64_t* off, int n, int64_t t) {
-    int lo = 0, hi = n - 1;  // largest i with off[i] <= t
+// Largest i < n with off[i] <= t (off ascending, off[0] <= t).
+__device__ __forceinline__ int find_off(const int64_t* off, int n, int64_t t) {
+    int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (off[mid] <= t) lo = mid; else hi = mid - 1;
@@ -123,13 +121,25 @@ __device__ __forceinline__ int find_off3(const int64_t* off, int n, int64_t t) {
     return lo;
 }
 
+// The same for element t = blockIdx.x * blockDim.x + threadIdx.x: the search
+// for the block's first element is the same in every lane (uniform loads),
+// then each thread steps over the few offsets inside the block.
+__device__ __forceinline__ int find_off_block(const int64_t* off, int n, int64_t t) {
+    int i = find_off(off, n, (int64_t)blockIdx.x * blockDim.x);
+    while (i + 1 < n && off[i + 1] <= t) ++i;
+    return i;
+}
+
+// The same over the items of a batch: off holds 3 (n_items + 1) prefix
+// offsets (entries, y columns, z columns); item i's table starts at entry
+// off[i].
 __global__ void __launch_bounds__(256) k_sat_multi(const Item* __restrict__ items, int n_items,
                                                    const int64_t* __restrict__ off,
                                                    int32_t* __restrict__ S, int axis) {
     const int64_t* o = off + (size_t)axis * (n_items + 1);
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= o[n_items]) return;
-    const int i = find_off3(o, n_items, t);
+    const int i = find_off_block(o, n_items, t);
     sat_step(items[i].scene, S + off[i], axis, t - o[i]);
 }
 
@@ -773,15 +783,6 @@ __global__ void __launch_bounds__(256) k_learned_perm(const int32_t* __restrict_
 // a contiguous range of that order: the segment of (key k, item i) starts at
 // base_len[i][k] = iterations of item i's units with keys < k.
 
-__device__ __forceinline__ int find_off(const int64_t* off, int n, int64_t t) {
-    int lo = 0, hi = n - 1;  // largest i with off[i] <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Features of flattened iteration t (the image of item i's iteration
 // perm_cell[t], or t - item_off[i] without a cell order).
 template <bool TABLE>
@@ -795,7 +796,7 @@ __global__ void __launch_bounds__(256) k_features_multi(const Item* __restrict__
                                                         int64_t total_N, float* __restrict__ feats) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= total_N) return;
-    const int i = find_off(item_off, n_items, t);
+    const int i = find_off_block(item_off, n_items, t);
     const Item& it = items[i];
     const int w = perm_cell ? perm_cell[t] : (int)(t - item_off[i]);
     // items with a table have entries in it; the other launch takes the rest
@@ -839,7 +840,7 @@ __global__ void __launch_bounds__(256) k_unit_cost_multi(
     int32_t* __restrict__ uitem, int32_t* __restrict__ hcount, int32_t* __restrict__ hlen) {
     const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (u >= n_units) return;
-    const int i = find_off(unit_off, n_items, u);
+    const int i = find_off_block(unit_off, n_items, u);
     const int64_t a = item_off[i] + (u - unit_off[i]) * kUnit;
     const int64_t b = min(item_off[i + 1], a + kUnit);
     float c = 0.0f;

@@ -4,7 +4,7 @@
 // point is floor((x - origin) / h) per axis, evaluated in double precision so
 // that the conservative culling in the spin kernel can reproduce cell
 // boundaries exactly.
-#include "si_internal.h"
+#include "scene_build.h"
 
 namespace si {
 
@@ -13,12 +13,13 @@ namespace {
 constexpr int kScanTile = 2048;        // elements per scan tile (256 threads x 8)
 constexpr int kBBoxBlocks = 1024;
 
-__global__ void __launch_bounds__(256) k_bbox_partial(const float* __restrict__ xyz, int64_t M,
-                                                      float* __restrict__ part) {
+// Block-wide min/max of the finite coordinates of points first, first +
+// stride, ... < M into out6 (lo xyz, hi xyz).
+__device__ __forceinline__ void bbox_block(const float* __restrict__ xyz, int64_t M,
+                                           int64_t first, int64_t stride, float* __restrict__ out6) {
     float lo[3] = {INFINITY, INFINITY, INFINITY};
     float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = first; i < M; i += stride) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const float v = xyz[3 * i + a];
@@ -45,14 +46,15 @@ __global__ void __launch_bounds__(256) k_bbox_partial(const float* __restrict__ 
         }
         __syncthreads();
     }
-    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+    if (threadIdx.x < 6) out6[threadIdx.x] = s[threadIdx.x][0];
 }
 
-__global__ void __launch_bounds__(256) k_bbox_final(const float* __restrict__ part, int n,
-                                                    float* __restrict__ out6) {
+// Block-wide reduction of n partial boxes (6 floats each) into out6.
+__device__ __forceinline__ void bbox_reduce(const float* __restrict__ part, int64_t n,
+                                            float* __restrict__ out6) {
     __shared__ float s[6][256];
     float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    for (int i = threadIdx.x; i < n; i += 256) {
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             v[a] = fminf(v[a], part[i * 6 + a]);
@@ -75,11 +77,54 @@ __global__ void __launch_bounds__(256) k_bbox_final(const float* __restrict__ pa
     if (threadIdx.x < 6) out6[threadIdx.x] = s[threadIdx.x][0];
 }
 
-struct GridDesc {
-    double origin[3];
-    double h;
-    int32_t dims[3];
-};
+__global__ void __launch_bounds__(256) k_bbox_partial(const float* __restrict__ xyz, int64_t M,
+                                                      float* __restrict__ part) {
+    bbox_block(xyz, M, blockIdx.x * (int64_t)blockDim.x + threadIdx.x,
+               (int64_t)gridDim.x * blockDim.x, part + blockIdx.x * 6);
+}
+
+__global__ void __launch_bounds__(256) k_bbox_final(const float* __restrict__ part, int n,
+                                                    float* __restrict__ out6) {
+    bbox_reduce(part, n, out6);
+}
+
+// Largest i < n with off[i] <= t (off ascending, off[0] <= t).
+__device__ __forceinline__ int find_item(const int64_t* off, int n, int64_t t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Item of element t, for blocks of consecutive elements: the search for the
+// block's first element is the same in every lane (its loads are uniform),
+// and each thread then steps over the few segment ends inside the block.
+__device__ __forceinline__ int find_item_block(const int64_t* off, int n, int64_t t) {
+    int s = find_item(off, n, (int64_t)blockIdx.x * blockDim.x);
+    while (s + 1 < n && off[s + 1] <= t) ++s;
+    return s;
+}
+
+// Partial boxes of many scenes: block b works for scene s with
+// blk_off[s] <= b < blk_off[s+1], striding over that scene's points.
+__global__ void __launch_bounds__(256) k_bbox_partial_multi(const BuildItem* __restrict__ items,
+                                                            const int64_t* __restrict__ blk_off,
+                                                            int n, float* __restrict__ part) {
+    const int s = find_item(blk_off, n, blockIdx.x);
+    const int64_t lb = blockIdx.x - blk_off[s], nb = blk_off[s + 1] - blk_off[s];
+    bbox_block(items[s].xyz, items[s].M, lb * blockDim.x + threadIdx.x, nb * blockDim.x,
+               part + blockIdx.x * 6);
+}
+
+// One block per scene reduces its partial boxes.
+__global__ void __launch_bounds__(256) k_bbox_final_multi(const int64_t* __restrict__ blk_off,
+                                                          const float* __restrict__ part,
+                                                          float* __restrict__ out6) {
+    const int s = blockIdx.x;
+    bbox_reduce(part + blk_off[s] * 6, blk_off[s + 1] - blk_off[s], out6 + 6 * s);
+}
 
 // Sort key of a point: cell * kSubX + the quarter of the cell along x,
 // floor(kSubX t) - kSubX floor(t) for t = (x - origin) / h.
@@ -208,6 +253,56 @@ __global__ void __launch_bounds__(256) k_scatter(const float* __restrict__ xyz,
     inv[i] = s;
 }
 
+// Batched build: point t of the concatenation, scene s = its segment.
+__global__ void __launch_bounds__(256) k_bin_points_multi(const BuildItem* __restrict__ items,
+                                                          const int64_t* __restrict__ pt_off,
+                                                          int n, int64_t total_M,
+                                                          int32_t* __restrict__ key_of,
+                                                          int32_t* __restrict__ rank,
+                                                          int32_t* __restrict__ counts) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= total_M) return;
+    const int s = find_item_block(pt_off, n, t);
+    const BuildItem& it = items[s];
+    const int64_t i = t - pt_off[s];
+    const int k = key_of_point(it.g, it.xyz[3 * i], it.xyz[3 * i + 1], it.xyz[3 * i + 2]);
+    key_of[t] = k;
+    rank[t] = atomicAdd(counts + it.key_base + k, 1);
+}
+
+// sub_start of every scene from the scan of the concatenated counts:
+// entry j of scene s is gscan[key_base + j] - gscan[key_base].
+__global__ void __launch_bounds__(256) k_sub_start_multi(const BuildItem* __restrict__ items,
+                                                         const int64_t* __restrict__ sub_off,
+                                                         int n, int64_t total,
+                                                         const int32_t* __restrict__ gscan) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int s = find_item_block(sub_off, n, t);
+    const int64_t kb = items[s].key_base;
+    items[s].sub_start[t - sub_off[s]] = gscan[kb + (t - sub_off[s])] - gscan[kb];
+}
+
+__global__ void __launch_bounds__(256) k_scatter_multi(const BuildItem* __restrict__ items,
+                                                       const int64_t* __restrict__ pt_off, int n,
+                                                       int64_t total_M,
+                                                       const int32_t* __restrict__ key_of,
+                                                       const int32_t* __restrict__ rank,
+                                                       const int32_t* __restrict__ gscan) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= total_M) return;
+    const int s = find_item_block(pt_off, n, t);
+    const BuildItem& it = items[s];
+    const int64_t i = t - pt_off[s];
+    const int k = key_of[t];
+    const int sp = gscan[it.key_base + k] - gscan[it.key_base] + rank[t];
+    it.pos[sp] = make_float4(it.xyz[3 * i], it.xyz[3 * i + 1], it.xyz[3 * i + 2],
+                             __int_as_float(k / kSubX));
+    it.nr[sp] = make_float4(it.nrm[3 * i], it.nrm[3 * i + 1], it.nrm[3 * i + 2],
+                            __int_as_float((int)i));
+    it.inv[i] = sp;
+}
+
 __global__ void __launch_bounds__(256) k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -237,15 +332,6 @@ __global__ void __launch_bounds__(256) k_order_scatter(const int32_t* __restrict
     perm[starts[key[i]] + rank[i]] = (int32_t)i;
 }
 
-__device__ __forceinline__ int find_item(const int64_t* off, int n, int64_t t) {
-    int lo = 0, hi = n - 1;  // largest i with off[i] <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 __global__ void __launch_bounds__(256) k_order_keys_multi(const Item* __restrict__ items,
                                                           const int64_t* __restrict__ item_off,
                                                           const int64_t* __restrict__ key_base,
@@ -255,7 +341,7 @@ __global__ void __launch_bounds__(256) k_order_keys_multi(const Item* __restrict
                                                           int32_t* __restrict__ counts) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= total_N) return;
-    const int i = find_item(item_off, n_items, t);
+    const int i = find_item_block(item_off, n_items, t);
     const Item& it = items[i];
     const int o = it.oriented[t - item_off[i]];
     const int c = (o >= 0 && o < it.scene.M) ? it.scene.inv[o] : 0;
@@ -272,7 +358,7 @@ __global__ void __launch_bounds__(256) k_order_scatter_multi(const int32_t* __re
                                                              int32_t* __restrict__ perm) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= total_N) return;
-    const int i = find_item(item_off, n_items, t);
+    const int i = find_item_block(item_off, n_items, t);
     perm[starts[key[t]] + rank[t]] = (int32_t)(t - item_off[i]);
 }
 
@@ -327,12 +413,7 @@ hipError_t launch_bbox(const float* xyz, int64_t M, float* out6, hipStream_t s) 
 
 hipError_t launch_bin_points(const float* xyz, int64_t M, const Scene& sc, int32_t* key_of,
                              int32_t* rank, int32_t* counts, hipStream_t s) {
-    GridDesc g;
-    for (int a = 0; a < 3; ++a) {
-        g.origin[a] = (double)sc.origin[a];
-        g.dims[a] = sc.dims[a];
-    }
-    g.h = sc.h;
+    const GridDesc g = grid_of(sc);
     hipLaunchKernelGGL(k_bin_points, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, xyz, M,
                        g, key_of, rank, counts);
     return hipGetLastError();
@@ -368,6 +449,36 @@ hipError_t launch_scatter(const float* xyz, const float* nrm, int64_t M, const i
                           hipStream_t s) {
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, xyz, nrm,
                        M, key_of, rank, sub_start, sc.pos, sc.nrm, sc.inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_bbox_multi(const BuildItem* items, const int64_t* blk_off, int n,
+                             int64_t total_blocks, float* part, float* out6, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bbox_partial_multi, dim3((unsigned)total_blocks), dim3(256), 0, s, items,
+                       blk_off, n, part);
+    hipLaunchKernelGGL(k_bbox_final_multi, dim3((unsigned)n), dim3(256), 0, s, blk_off, part,
+                       out6);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_multi(const BuildItem* items, const int64_t* pt_off,
+                              const int64_t* sub_off, int n, int64_t total_M, int64_t total_keys,
+                              int32_t* key_of, int32_t* rank, int32_t* counts, int32_t* gscan,
+                              int32_t* tmp, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipError_t e = launch_fill(counts, total_keys, 0, s);
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)((total_M + 255) / 256);
+    hipLaunchKernelGGL(k_bin_points_multi, dim3(nb), dim3(256), 0, s, items, pt_off, n, total_M,
+                       key_of, rank, counts);
+    e = launch_scan(counts, gscan, total_keys, tmp, scan_tmp_elems(total_keys), s);
+    if (e != hipSuccess) return e;
+    const int64_t total_sub = total_keys + n;
+    hipLaunchKernelGGL(k_sub_start_multi, dim3((unsigned)((total_sub + 255) / 256)), dim3(256), 0,
+                       s, items, sub_off, n, total_sub, gscan);
+    hipLaunchKernelGGL(k_scatter_multi, dim3(nb), dim3(256), 0, s, items, pt_off, n, total_M,
+                       key_of, rank, gscan);
     return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@
 #include <tuple>
 #include <vector>
 
-#include "si_internal.h"
+#include "scene_build.h"
 
 namespace si {
 
@@ -233,15 +233,101 @@ SceneView view_of(const Scene& s) {
     return v;
 }
 
+// The scenes of one si_build_scenes call share one allocation of their
+// arrays (mem is its base for all of them); it is released with the last of
+// them.  Counts of the scenes still holding each shared allocation:
+static std::mutex g_shared_mu;
+static std::map<void*, int64_t> g_shared_refs;
+
 // The scene's arrays come from the device's stream-ordered pool (which keeps
 // freed memory cached), so building a scene per frame costs no allocation
 // round trips.  Frees are ordered on `stream`.
 static void free_scene_mem(Scene* sc, hipStream_t stream) {
     if (!sc) return;
-    if (sc->mem) (void)hipFreeAsync(sc->mem, stream);
+    if (sc->mem) {
+        bool last = true;
+        {
+            std::lock_guard<std::mutex> lk(g_shared_mu);
+            auto it = g_shared_refs.find(sc->mem);
+            if (it != g_shared_refs.end()) {
+                last = --it->second == 0;
+                if (last) g_shared_refs.erase(it);
+            }
+        }
+        if (last) (void)hipFreeAsync(sc->mem, stream);
+    }
     sc->mem = nullptr;
     sc->pos = sc->nrm = nullptr;
     sc->sub_start = sc->inv = nullptr;
+}
+
+static size_t rup256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// A scene's grid from the bounding box of its finite coordinates (hb: lo
+// xyz, hi xyz) and the largest support radius it will serve: cells of edge
+// R (1 + 2e-5) / kSub, enlarged while the grid would exceed kMaxCells; a
+// radius <= 0 (or no finite point) gives one cell, the brute-force loop.
+static void scene_grid(Scene* sc, const float hb[6], float max_support_radius) {
+    double lo[3], ext[3];
+    bool any = true;
+    for (int a = 0; a < 3; ++a) {
+        if (!(hb[a] <= hb[3 + a])) any = false;
+        lo[a] = any ? (double)hb[a] : 0.0;
+    }
+    for (int a = 0; a < 3; ++a) ext[a] = any ? (double)hb[3 + a] - lo[a] : 0.0;
+    for (int a = 0; a < 3; ++a) sc->origin[a] = any ? hb[a] : 0.0f;
+
+    if (max_support_radius > 0.0f && any) {
+        // margin 2e-5 > the 1e-5 of the culling radius: reach stays <= kSub
+        double h = (double)max_support_radius * (1.0 + 2e-5) / kSub;
+        for (;;) {
+            int64_t cells = 1;
+            for (int a = 0; a < 3; ++a) {
+                const int64_t d = (int64_t)floor(ext[a] / h) + 1;
+                sc->dims[a] = (int32_t)d;
+                cells *= d;
+            }
+            if (cells <= kMaxCells) {
+                sc->n_cells = cells;
+                break;
+            }
+            h *= std::cbrt((double)cells / (double)kMaxCells) * 1.01;
+        }
+        sc->h = h;
+        sc->max_radius = max_support_radius;
+    } else {
+        sc->h = std::max({ext[0], ext[1], ext[2], 0.0}) + 1.0;
+        sc->dims[0] = sc->dims[1] = sc->dims[2] = 1;
+        sc->n_cells = 1;
+        sc->max_radius = 0.0f;
+    }
+}
+
+// Bytes of the scene's four arrays (each 256-byte aligned).
+static size_t scene_bytes(const Scene* sc) {
+    const int64_t M = sc->M, n_keys = sc->n_cells * kSubX;
+    return 2 * rup256(sizeof(float4) * M) + rup256(sizeof(int32_t) * M) +
+           rup256(sizeof(int32_t) * (n_keys + 1));
+}
+
+// Point the scene's arrays into m (scene_bytes(sc) bytes).
+static void scene_place(Scene* sc, char* m) {
+    const size_t b_pos = rup256(sizeof(float4) * sc->M), b_inv = rup256(sizeof(int32_t) * sc->M);
+    sc->pos = reinterpret_cast<float4*>(m);
+    sc->nrm = reinterpret_cast<float4*>(m + b_pos);
+    sc->inv = reinterpret_cast<int32_t*>(m + 2 * b_pos);
+    sc->sub_start = reinterpret_cast<int32_t*>(m + 2 * b_pos + b_inv);
+}
+
+// The scene's four arrays, in one allocation from the device's pool.
+static hipError_t scene_alloc(Scene* sc, hipStream_t s) {
+    hipError_t e = pool_alloc(&sc->mem, scene_bytes(sc), s);
+    if (e != hipSuccess) {
+        sc->mem = nullptr;
+        return e;
+    }
+    scene_place(sc, static_cast<char*>(sc->mem));
+    return hipSuccess;
 }
 
 }  // namespace si
@@ -278,39 +364,7 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { delete sc; return hip_fail(e, "scene bounding box"); }
 
-    double lo[3], ext[3];
-    bool any = true;
-    for (int a = 0; a < 3; ++a) {
-        if (!(hb[a] <= hb[3 + a])) any = false;
-        lo[a] = any ? (double)hb[a] : 0.0;
-    }
-    for (int a = 0; a < 3; ++a) ext[a] = any ? (double)hb[3 + a] - lo[a] : 0.0;
-    for (int a = 0; a < 3; ++a) sc->origin[a] = any ? hb[a] : 0.0f;
-
-    if (max_support_radius > 0.0f && any) {
-        // margin 2e-5 > the 1e-5 of the culling radius: reach stays <= kSub
-        double h = (double)max_support_radius * (1.0 + 2e-5) / kSub;
-        for (;;) {
-            int64_t cells = 1;
-            for (int a = 0; a < 3; ++a) {
-                const int64_t d = (int64_t)floor(ext[a] / h) + 1;
-                sc->dims[a] = (int32_t)d;
-                cells *= d;
-            }
-            if (cells <= kMaxCells) {
-                sc->n_cells = cells;
-                break;
-            }
-            h *= std::cbrt((double)cells / (double)kMaxCells) * 1.01;
-        }
-        sc->h = h;
-        sc->max_radius = max_support_radius;
-    } else {
-        sc->h = std::max({ext[0], ext[1], ext[2], 0.0}) + 1.0;
-        sc->dims[0] = sc->dims[1] = sc->dims[2] = 1;
-        sc->n_cells = 1;
-        sc->max_radius = 0.0f;
-    }
+    scene_grid(sc, hb, max_support_radius);
 
     // ---- bin, scan, scatter ----
     int32_t *key_of = nullptr, *rank = nullptr, *counts = nullptr, *tmp = nullptr;
@@ -318,20 +372,12 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     const int64_t ntmp = scan_tmp_elems(n_keys);
     // two pool allocations: the scene's arrays, and temporaries that return
     // to the pool once the stream has used them
-    auto rup = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t b_pos = rup(sizeof(float4) * M), b_inv = rup(sizeof(int32_t) * M);
-    const size_t b_sub = rup(sizeof(int32_t) * (n_keys + 1));
-    const size_t b_key = rup(sizeof(int32_t) * n_keys);
+    const size_t b_inv = rup256(sizeof(int32_t) * M);
+    const size_t b_key = rup256(sizeof(int32_t) * n_keys);
     char* tmem = nullptr;
-    e = pool_alloc(&sc->mem, 2 * b_pos + b_inv + b_sub, s);
-    if (e == hipSuccess) {
-        char* m = static_cast<char*>(sc->mem);
-        sc->pos = reinterpret_cast<float4*>(m);
-        sc->nrm = reinterpret_cast<float4*>(m + b_pos);
-        sc->inv = reinterpret_cast<int32_t*>(m + 2 * b_pos);
-        sc->sub_start = reinterpret_cast<int32_t*>(m + 2 * b_pos + b_inv);
-        e = pool_alloc((void**)&tmem, 2 * b_inv + b_key + rup(sizeof(int32_t) * ntmp), s);
-    }
+    e = scene_alloc(sc, s);
+    if (e == hipSuccess)
+        e = pool_alloc((void**)&tmem, 2 * b_inv + b_key + rup256(sizeof(int32_t) * ntmp), s);
     if (e == hipSuccess) {
         key_of = reinterpret_cast<int32_t*>(tmem);
         rank = reinterpret_cast<int32_t*>(tmem + b_inv);
@@ -355,6 +401,193 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
         return hip_fail(e, "scene build");
     }
     *out = sc;
+    return SI_OK;
+}
+
+// Bounding-box blocks per scene and sub-batch bounds of a batched build.
+static constexpr int64_t kBBoxBlocksPerScene = 64;
+static constexpr int64_t kBuildKeys = int64_t(1) << 27;
+static constexpr int64_t kBuildPoints = int64_t(1) << 28;
+
+si_status si_build_scenes(const si_scene_desc* descs, int32_t n, void* hip_stream,
+                          si_scene** out) {
+    if (n < 0) return fail(SI_E_INVALID, "n must be >= 0");
+    if (n == 0) return SI_OK;
+    if (!descs || !out) return fail(SI_E_INVALID, "descs or out is NULL");
+    for (int i = 0; i < n; ++i) out[i] = nullptr;
+    for (int i = 0; i < n; ++i) {
+        const si_scene_desc& d = descs[i];
+        const std::string at = "scene " + std::to_string(i) + ": ";
+        if (!d.points_xyz || !d.normals_xyz)
+            return fail(SI_E_INVALID, at + "points or normals is NULL");
+        if (d.M <= 0 || d.M >= INT32_MAX)
+            return fail(SI_E_INVALID, at + "M must be in [1, 2^31 - 1)");
+        if (!isfinite(d.max_support_radius))
+            return fail(SI_E_INVALID, at + "max_support_radius not finite");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    DeviceState* st;
+    si_status rc = device_state(&st);
+    if (rc != SI_OK) return rc;
+    int dev = 0;
+    SI_HIP(hipGetDevice(&dev));
+
+    std::vector<si_scene*> scenes(n, nullptr);
+    auto discard = [&]() {
+        (void)hipStreamSynchronize(s);
+        for (si_scene*& sc : scenes) {
+            if (sc) free_scene_mem(sc, s);
+            delete sc;
+            sc = nullptr;
+        }
+    };
+    for (int i = 0; i < n; ++i) {
+        scenes[i] = new (std::nothrow) si_scene();
+        if (!scenes[i]) {
+            discard();
+            return fail(SI_E_OOM, "host allocation failed");
+        }
+        scenes[i]->M = descs[i].M;
+        scenes[i]->device = dev;
+    }
+
+    // ---- bounding boxes of all scenes (one synchronisation) ----
+    std::vector<BuildItem> items(n);
+    std::vector<int64_t> blk_off(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        memset(&items[i], 0, sizeof(BuildItem));
+        items[i].xyz = descs[i].points_xyz;
+        items[i].nrm = descs[i].normals_xyz;
+        items[i].M = descs[i].M;
+        blk_off[i + 1] = blk_off[i] + std::min(kBBoxBlocksPerScene, (descs[i].M + 255) / 256);
+    }
+    const int64_t n_blk = blk_off[n];
+    std::vector<float> hb(6 * (size_t)n);
+    {
+        const size_t b_it = rup256(sizeof(BuildItem) * n);
+        const size_t b_off = rup256(sizeof(int64_t) * (n + 1));
+        const size_t b_part = rup256(sizeof(float) * 6 * n_blk);
+        char* m = nullptr;
+        hipError_t e = pool_alloc((void**)&m, b_it + b_off + b_part + sizeof(float) * 6 * n, s);
+        if (e == hipSuccess) {
+            BuildItem* d_it = reinterpret_cast<BuildItem*>(m);
+            int64_t* d_off = reinterpret_cast<int64_t*>(m + b_it);
+            float* d_part = reinterpret_cast<float*>(m + b_it + b_off);
+            float* d_box = reinterpret_cast<float*>(m + b_it + b_off + b_part);
+            e = hipMemcpyAsync(d_it, items.data(), sizeof(BuildItem) * n, hipMemcpyHostToDevice,
+                               s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_off, blk_off.data(), sizeof(int64_t) * (n + 1),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = launch_bbox_multi(d_it, d_off, n, n_blk, d_part, d_box, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hb.data(), d_box, sizeof(float) * 6 * n,
+                                   hipMemcpyDeviceToHost, s);
+            (void)hipFreeAsync(m, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        if (e != hipSuccess) {
+            discard();
+            return hip_fail(e, "batched bounding boxes");
+        }
+    }
+
+    // ---- grids and the scenes' arrays (one shared allocation) ----
+    size_t total_bytes = 0;
+    for (int i = 0; i < n; ++i) {
+        scene_grid(scenes[i], &hb[6 * (size_t)i], descs[i].max_support_radius);
+        total_bytes += scene_bytes(scenes[i]);
+    }
+    void* shared = nullptr;
+    {
+        const hipError_t e = pool_alloc(&shared, total_bytes, s);
+        if (e != hipSuccess) {
+            discard();
+            return hip_fail(e, "scene arrays");
+        }
+        std::lock_guard<std::mutex> lk(g_shared_mu);
+        g_shared_refs[shared] = n;
+    }
+    size_t at = 0;
+    for (int i = 0; i < n; ++i) {
+        si_scene* sc = scenes[i];
+        sc->mem = shared;
+        scene_place(sc, static_cast<char*>(shared) + at);
+        at += scene_bytes(sc);
+        items[i].g = grid_of(*sc);
+        items[i].pos = sc->pos;
+        items[i].nr = sc->nrm;
+        items[i].inv = sc->inv;
+        items[i].sub_start = sc->sub_start;
+    }
+
+    // ---- bin, scan and scatter in bounded sub-batches ----
+    // SI_TEST_BUILD_KEYS, a key count, lowers the key bound of a sub-batch: a
+    // test hook for builds that take several sub-batches
+    int64_t key_cap = kBuildKeys;
+    if (const char* v = getenv("SI_TEST_BUILD_KEYS")) {
+        const long long k = strtoll(v, nullptr, 10);
+        if (k > 0) key_cap = k;
+    }
+    for (int b0 = 0; b0 < n;) {
+        int64_t n_keys = 0, n_pts = 0;
+        int b1 = b0;
+        while (b1 < n) {
+            const int64_t k = scenes[b1]->n_cells * kSubX;
+            if (b1 > b0 && (n_keys + k > key_cap || n_pts + descs[b1].M > kBuildPoints)) break;
+            items[b1].key_base = n_keys;
+            n_keys += k;
+            n_pts += descs[b1].M;
+            ++b1;
+        }
+        const int nb = b1 - b0;
+        std::vector<int64_t> pt_off(nb + 1, 0), sub_off(nb + 1, 0);
+        for (int j = 0; j < nb; ++j) {
+            pt_off[j + 1] = pt_off[j] + descs[b0 + j].M;
+            sub_off[j + 1] = sub_off[j] + scenes[b0 + j]->n_cells * kSubX + 1;
+        }
+        const int64_t ntmp = scan_tmp_elems(n_keys);
+        const size_t b_it = rup256(sizeof(BuildItem) * nb);
+        const size_t b_off = rup256(sizeof(int64_t) * (nb + 1));
+        const size_t b_pt = rup256(sizeof(int32_t) * n_pts);
+        const size_t b_cnt = rup256(sizeof(int32_t) * n_keys);
+        const size_t b_scan = rup256(sizeof(int32_t) * (n_keys + 1));
+        char* m = nullptr;
+        hipError_t e = pool_alloc((void**)&m,
+                                  b_it + 2 * b_off + 2 * b_pt + b_cnt + b_scan +
+                                      sizeof(int32_t) * ntmp, s);
+        if (e == hipSuccess) {
+            BuildItem* d_it = reinterpret_cast<BuildItem*>(m);
+            int64_t* d_pt = reinterpret_cast<int64_t*>(m + b_it);
+            int64_t* d_sub = reinterpret_cast<int64_t*>(m + b_it + b_off);
+            char* t = m + b_it + 2 * b_off;
+            int32_t* key_of = reinterpret_cast<int32_t*>(t);
+            int32_t* rank = reinterpret_cast<int32_t*>(t + b_pt);
+            int32_t* counts = reinterpret_cast<int32_t*>(t + 2 * b_pt);
+            int32_t* gscan = reinterpret_cast<int32_t*>(t + 2 * b_pt + b_cnt);
+            int32_t* tmp = reinterpret_cast<int32_t*>(t + 2 * b_pt + b_cnt + b_scan);
+            e = hipMemcpyAsync(d_it, items.data() + b0, sizeof(BuildItem) * nb,
+                               hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_pt, pt_off.data(), sizeof(int64_t) * (nb + 1),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_sub, sub_off.data(), sizeof(int64_t) * (nb + 1),
+                                   hipMemcpyHostToDevice, s);
+            if (e == hipSuccess)
+                e = launch_build_multi(d_it, d_pt, d_sub, nb, n_pts, n_keys, key_of, rank,
+                                       counts, gscan, tmp, s);
+            (void)hipFreeAsync(m, s);
+            // the host tables are staged from pageable memory: wait before they go
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        if (e != hipSuccess) {
+            discard();
+            return hip_fail(e, "batched scene build");
+        }
+        b0 = b1;
+    }
+    for (int i = 0; i < n; ++i) out[i] = scenes[i];
     return SI_OK;
 }
 
