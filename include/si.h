@@ -264,10 +264,17 @@ typedef struct si_batch_item {
 } si_batch_item;
 
 /*
- * Generate the images of many scenes in one persistent launch: one flattened
- * schedule whose chunks never span two scenes.  use_graph = 1 captures the
- * launch in a HIP graph that is cached and replayed while the item list
- * (pointers, sizes, params) and schedule are unchanged.  sched->kind is any
+ * Generate the images of many scenes in one persistent launch per image-size
+ * class: one flattened schedule whose chunks never span two scenes.  Items
+ * with W <= 32 and with W > 32 form two classes, launched one after the other
+ * on the stream, each with its own schedule and its own default group and
+ * workgroup count (a launch sizes its LDS for its largest image, so small
+ * images next to W = 64 ones would run at a lower occupancy); sched applies
+ * to both.  use_graph = 1 captures the launches in one HIP graph that is
+ * cached and replayed while the item list (pointers, sizes, params) and
+ * schedule are unchanged.  In the statistics, n_wg and wg_busy_ns are those
+ * of the larger launch's workgroup slots, busy times summed over the
+ * launches; kernel_ms runs from the first spin launch to the end of the last.  sched->kind is any
  * SI_SCHED_*.  SI_SCHED_LEARNED plans the whole batch on the device before
  * the launch (inside the graph): features and predicted costs of every
  * image, units of 16 iterations that never cross an item, one
@@ -290,7 +297,8 @@ si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
  * `kind`.  Tuned: group (images per shared candidate pass, from 1, 2, 4, 6,
  * 8), num_workgroups (2, 3, 4, 5, 6 or 8 per compute unit), fac_divisor (FAC and
  * LEARNED: 1.5, 2, 3, 4) and min_chunk (dynamic techniques: 0, 4, 16), by two
- * sweeps of coordinate descent from the library's defaults for the workload,
+ * sweeps of coordinate descent from the library's defaults (group and
+ * num_workgroups 0: chosen per launch; a tuned value applies to every launch),
  * at most max_trials timed candidates (each the median of two launches after
  * a warm-up).  Every candidate's images and counts must give the same 64-bit
  * checksum as the first one,

@@ -189,14 +189,10 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
         }
     }
 
-    // the defaults the library would pick for this workload, spelled out
-    int max_w2 = 4;
-    for (int32_t i = 0; i < n_items; ++i)
-        if (items[i].N > 0) max_w2 = std::max(max_w2, items[i].params.W * items[i].params.W);
-    int max_W = 2;
-    while (max_W * max_W < max_w2) ++max_W;
-    base.group = fit_group(st, default_group(max_W), max_w2);
-    base.num_workgroups = auto_workgroups(st, max_w2, base.group);
+    // the library's defaults first: group and workgroups chosen per launch
+    // (a batch runs one launch per image-size class), FAC2
+    base.group = 0;
+    base.num_workgroups = 0;
     base.fac_divisor = (kind == SI_SCHED_FAC || kind == SI_SCHED_LEARNED) ? 2.0f : 0.0f;
 
     unsigned long long* dsum = nullptr;

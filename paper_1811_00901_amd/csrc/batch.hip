@@ -8,6 +8,12 @@
 // iterations is one counting sort over all items (keys offset by each item's
 // cell count).  With use_graph the sort and the spin kernel are captured once
 // into a HIP graph, cached per item list, and replayed.
+//
+// A launch sizes its LDS for its largest image, so W <= 32 images sharing a
+// launch with W = 64 images would run at that launch's lower occupancy (three
+// workgroups per CU instead of five).  Items are therefore launched in two
+// classes, W <= 32 and W > 32, one after the other on the stream (one graph
+// holds both); each class is its own concatenated loop, scheduled as above.
 #include <stddef.h>
 #include <string.h>
 
@@ -128,13 +134,14 @@ void flat_chunks(Flat& f, int min_chunk, float divisor) {
     if (stat) f.wg_first[P] = (int32_t)f.chunks.size();
 }
 
-si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_items,
+// The flattened launch of items sel[0..] (indices into items).
+si_status build_flat(DeviceState* st, const si_batch_item* items, const std::vector<int32_t>& sel,
                      const si_sched* sched, Flat& f) {
     int dev = 0;
     SI_HIP(hipGetDevice(&dev));
     f.item_off.push_back(0);
     f.key_base.push_back(0);
-    for (int32_t k = 0; k < n_items; ++k) {
+    for (const int32_t k : sel) {
         const si_batch_item& b = items[k];
         if (b.N == 0) continue;
         if (!b.scene) return fail(SI_E_INVALID, "batch item " + std::to_string(k) + ": scene is NULL");
@@ -214,6 +221,27 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, int32_t n_item
         f.divisor = sched->fac_divisor;
     } else {
         flat_chunks(f, sched->min_chunk, sched->fac_divisor);
+    }
+    return SI_OK;
+}
+
+// Image-size class of a batch item (see the file comment).
+int size_class(const si_batch_item& b) { return b.params.W > 32 ? 1 : 0; }
+constexpr int kClasses = 2;
+
+// The flattened launches of a batch, one per non-empty class, in class order.
+si_status build_launches(DeviceState* st, const si_batch_item* items, int32_t n_items,
+                         const si_sched* sched, std::vector<Flat>& flats) {
+    std::vector<int32_t> sel[kClasses];
+    for (int32_t k = 0; k < n_items; ++k)
+        if (items[k].N != 0) sel[size_class(items[k])].push_back(k);
+    flats.clear();
+    for (int c = 0; c < kClasses; ++c) {
+        if (sel[c].empty()) continue;
+        Flat f;
+        const si_status rc = build_flat(st, items, sel[c], sched, f);
+        if (rc != SI_OK) return rc;
+        if (!f.items.empty()) flats.push_back(std::move(f));
     }
     return SI_OK;
 }
@@ -298,29 +326,44 @@ hipError_t enqueue(const Flat& f, const FlatMem& m, const LaunchDesc& d, bool st
     return e;
 }
 
-si_status read_stats(DeviceState* st, const Flat& f, const FlatMem& m, float ms, si_stats* stats,
-                     hipStream_t s) {
-    std::vector<unsigned long long> h(4 + (size_t)f.n_wg);
-    SI_HIP(hipMemcpyAsync(h.data(), m.stats, sizeof(unsigned long long) * h.size(),
-                          hipMemcpyDeviceToHost, s));
-    SI_HIP(hipStreamSynchronize(s));
+// Statistics of the launches of one call, summed over them; kernel_ms is the
+// time from the first spin launch to the end of the last.  n_wg and the
+// per-workgroup busy times are those of the largest launch's workgroup
+// slots (busy times summed over the launches).
+si_status read_stats(DeviceState* st, const std::vector<Flat>& flats,
+                     const std::vector<FlatMem>& mems, float ms, si_stats* stats, hipStream_t s) {
     stats->kernel_ms = ms;
-    stats->pairs_tested = h[0];
-    stats->pairs_in_support = h[1];
-    stats->n_invalid = (int32_t)(uint32_t)h[2];
-    stats->n_overflow = (int32_t)(uint32_t)h[3];
-    stats->sched_used = f.kind;
-    stats->n_wg = f.n_wg;
-    stats->n_chunks = (int32_t)f.chunks.size();
-    if (f.learned) {
-        int32_t nc = 0;
-        SI_HIP(hipMemcpy(&nc, m.lm.n_chunks, sizeof(nc), hipMemcpyDeviceToHost));
-        stats->n_chunks = nc;
+    stats->pairs_tested = stats->pairs_in_support = 0;
+    stats->n_invalid = stats->n_overflow = 0;
+    stats->sched_used = flats.empty() ? 0 : flats[0].kind;
+    stats->n_wg = 0;
+    stats->n_chunks = 0;
+    for (const Flat& f : flats) stats->n_wg = std::max(stats->n_wg, f.n_wg);
+    std::vector<uint64_t> busy((size_t)stats->n_wg, 0);
+    for (size_t c = 0; c < flats.size(); ++c) {
+        const Flat& f = flats[c];
+        const FlatMem& m = mems[c];
+        std::vector<unsigned long long> h(4 + (size_t)f.n_wg);
+        SI_HIP(hipMemcpyAsync(h.data(), m.stats, sizeof(unsigned long long) * h.size(),
+                              hipMemcpyDeviceToHost, s));
+        SI_HIP(hipStreamSynchronize(s));
+        stats->pairs_tested += h[0];
+        stats->pairs_in_support += h[1];
+        stats->n_invalid += (int32_t)(uint32_t)h[2];
+        stats->n_overflow += (int32_t)(uint32_t)h[3];
+        if (f.learned) {
+            int32_t nc = 0;
+            SI_HIP(hipMemcpy(&nc, m.lm.n_chunks, sizeof(nc), hipMemcpyDeviceToHost));
+            stats->n_chunks += nc;
+        } else {
+            stats->n_chunks += (int32_t)f.chunks.size();
+        }
+        for (int i = 0; i < f.n_wg; ++i)
+            busy[i] += (uint64_t)((double)h[4 + i] * 1e6 / (double)st->wall_khz);
     }
     if (stats->wg_busy_ns) {
-        const int n = std::min(stats->wg_busy_cap, f.n_wg);
-        for (int i = 0; i < n; ++i)
-            stats->wg_busy_ns[i] = (uint64_t)((double)h[4 + i] * 1e6 / (double)st->wall_khz);
+        const int n = std::min(stats->wg_busy_cap, stats->n_wg);
+        for (int i = 0; i < n; ++i) stats->wg_busy_ns[i] = busy[i];
     }
     if (stats->n_invalid) return fail(SI_E_INVALID, "oriented_idx holds indices outside [0, M)");
     return SI_OK;
@@ -328,9 +371,9 @@ si_status read_stats(DeviceState* st, const Flat& f, const FlatMem& m, float ms,
 
 // ---- graph cache ----
 struct GraphEntry {
-    Flat flat;
-    FlatMem mem;
-    uint32_t* counter = nullptr;
+    std::vector<Flat> flats;  // one launch per image-size class
+    std::vector<FlatMem> mems;
+    std::vector<uint32_t*> counters;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     uint64_t last_use = 0;
@@ -346,8 +389,8 @@ void free_entry(GraphEntry* e) {
     if (e->exec) (void)hipGraphExecDestroy(e->exec);
     if (e->ev0) (void)hipEventDestroy(e->ev0);
     if (e->ev1) (void)hipEventDestroy(e->ev1);
-    (void)hipFree(e->mem.base);
-    (void)hipFree(e->counter);
+    for (FlatMem& m : e->mems) (void)hipFree(m.base);
+    for (uint32_t* c : e->counters) (void)hipFree(c);
     delete e;
 }
 
@@ -389,36 +432,43 @@ si_status make_graph(DeviceState* st, const si_batch_item* items, int32_t n_item
                      const si_sched* sched, bool stats, GraphEntry** out) {
     GraphEntry* e = new (std::nothrow) GraphEntry();
     if (!e) return fail(SI_E_OOM, "host allocation failed");
-    si_status rc = build_flat(st, items, n_items, sched, e->flat);
+    si_status rc = build_launches(st, items, n_items, sched, e->flats);
     if (rc != SI_OK) { delete e; return rc; }
-    if (e->flat.items.empty()) {  // nothing to launch: an entry without a graph
+    if (e->flats.empty()) {  // nothing to launch: an entry without a graph
         *out = e;
         return SI_OK;
     }
+    const size_t nl = e->flats.size();
+    e->mems.resize(nl);
+    e->counters.assign(nl, nullptr);
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipError_t err = hipSuccess;
-    const size_t bytes = layout(e->flat, e->mem, nullptr);
-    char* base = nullptr;
-    err = hipMalloc(&base, bytes);
-    if (err == hipSuccess) err = hipMalloc(&e->counter, 2 * sizeof(uint32_t));
-    if (err == hipSuccess) err = hipMemset(e->counter, 0, 2 * sizeof(uint32_t));
+    for (size_t c = 0; c < nl && err == hipSuccess; ++c) {
+        char* base = nullptr;
+        err = hipMalloc(&base, layout(e->flats[c], e->mems[c], nullptr));
+        if (err == hipSuccess) layout(e->flats[c], e->mems[c], base);
+        if (err == hipSuccess) err = hipMalloc(&e->counters[c], 2 * sizeof(uint32_t));
+        if (err == hipSuccess) err = hipMemset(e->counters[c], 0, 2 * sizeof(uint32_t));
+    }
     if (err == hipSuccess) err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (err != hipSuccess) {
-        (void)hipFree(base);
         free_entry(e);
         return hip_fail(err, "graph setup");
     }
-    layout(e->flat, e->mem, base);
-    rc = upload(e->flat, e->mem, cs);
+    for (size_t c = 0; c < nl && rc == SI_OK; ++c) rc = upload(e->flats[c], e->mems[c], cs);
     if (rc == SI_OK) {
         err = hipStreamSynchronize(cs);
         if (err == hipSuccess) err = hipEventCreate(&e->ev0);
         if (err == hipSuccess) err = hipEventCreate(&e->ev1);
-        LaunchDesc d = desc_of(e->flat, e->mem, e->counter, stats);
         if (err == hipSuccess) err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (err == hipSuccess) {
-            hipError_t qe = enqueue(e->flat, e->mem, d, stats, nullptr, nullptr, nullptr, nullptr, cs);
+            hipError_t qe = hipSuccess;
+            for (size_t c = 0; c < nl && qe == hipSuccess; ++c) {
+                const LaunchDesc d = desc_of(e->flats[c], e->mems[c], e->counters[c], stats);
+                qe = enqueue(e->flats[c], e->mems[c], d, stats, nullptr, nullptr, nullptr, nullptr,
+                             cs);
+            }
             err = hipStreamEndCapture(cs, &graph);
             if (qe != hipSuccess) err = qe;
         }
@@ -455,19 +505,25 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
     user_kernel_events(&ub, &ue);
 
     if (!use_graph) {
-        Flat f;
-        rc = build_flat(st, items, n_items, sched, f);
+        std::vector<Flat> flats;
+        rc = build_launches(st, items, n_items, sched, flats);
         if (rc != SI_OK) return rc;
-        if (f.items.empty()) {
+        if (flats.empty()) {
             if (stats) memset(stats, 0, offsetof(si_stats, wg_busy_cap));
             return SI_OK;
         }
-        FlatMem m;
-        const size_t bytes = layout(f, m, nullptr);
-        char* base = nullptr;
-        SI_HIP(pool_alloc((void**)&base, bytes, s));
-        layout(f, m, base);
-        rc = upload(f, m, s);
+        const size_t nl = flats.size();
+        std::vector<FlatMem> mems(nl);
+        std::vector<char*> bases(nl, nullptr);
+        for (size_t c = 0; c < nl && rc == SI_OK; ++c) {
+            const hipError_t e = pool_alloc((void**)&bases[c], layout(flats[c], mems[c], nullptr), s);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "batched launch tables");
+                break;
+            }
+            layout(flats[c], mems[c], bases[c]);
+            rc = upload(flats[c], mems[c], s);
+        }
         // the staged host tables are about to go out of scope
         if (rc == SI_OK && hipStreamSynchronize(s) != hipSuccess)
             rc = fail(SI_E_DEVICE, "stream synchronisation failed");
@@ -476,20 +532,25 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
             if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
                 rc = fail(SI_E_DEVICE, "event creation failed");
         }
-        if (rc == SI_OK) {
-            LaunchDesc d = desc_of(f, m, take_counter(st), stats != nullptr);
-            hipError_t e = enqueue(f, m, d, stats != nullptr, e0, e1, ub, ue, s);
+        for (size_t c = 0; c < nl && rc == SI_OK; ++c) {
+            // events bracket the spin launches: from the first to the last
+            const bool first = c == 0, last = c + 1 == nl;
+            LaunchDesc d = desc_of(flats[c], mems[c], take_counter(st), stats != nullptr);
+            hipError_t e = enqueue(flats[c], mems[c], d, stats != nullptr, first ? e0 : nullptr,
+                                   last ? e1 : nullptr, first ? ub : nullptr, last ? ue : nullptr,
+                                   s);
             if (e != hipSuccess) rc = hip_fail(e, "batched launch");
         }
         if (rc == SI_OK && stats) {
             float ms = 0.0f;
             (void)hipEventSynchronize(e1);
             (void)hipEventElapsedTime(&ms, e0, e1);
-            rc = read_stats(st, f, m, ms, stats, s);
+            rc = read_stats(st, flats, mems, ms, stats, s);
         }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
-        (void)hipFreeAsync(base, s);
+        for (char* b : bases)
+            if (b) (void)hipFreeAsync(b, s);
         return rc;
     }
 
@@ -518,7 +579,7 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
         g_graphs[key] = e;
     }
     e->last_use = ++g_graph_clock;
-    if (e->flat.items.empty()) {
+    if (e->flats.empty()) {
         if (stats) memset(stats, 0, offsetof(si_stats, wg_busy_cap));
         return SI_OK;
     }
@@ -531,7 +592,7 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
     SI_HIP(hipEventSynchronize(e->ev1));
     float ms = 0.0f;
     SI_HIP(hipEventElapsedTime(&ms, e->ev0, e->ev1));
-    return read_stats(st, e->flat, e->mem, ms, stats, s);
+    return read_stats(st, e->flats, e->mems, ms, stats, s);
 }
 
 // Features of every image of many scenes in one pass of launches (the

@@ -151,7 +151,7 @@ def test_autotune(env, tmp_path):
         batch = make_batch(torch, si, n_scenes=6, seed=4400)
         ref = singles(si, torch, batch, si.Sched("fac"))
         sched, ms = si.si_autotune(items_of(batch), "fac", use_graph=True, max_trials=8)
-        assert 1 <= sched.group <= 8 and ms > 0
+        assert 0 <= sched.group <= 8 and ms > 0      # 0: the library's default per launch
         for b in batch:
             b["img"].zero_()
         si.si_generate_batched(items_of(batch), sched, use_graph=True)
