@@ -243,3 +243,59 @@ def test_batched_features_equal_per_scene(env, monkeypatch):
         torch.cuda.synchronize()
         assert torch.equal(forced, exp)
     monkeypatch.delenv("SI_FEATURES_TABLE")
+
+
+def test_batch256_full_sampled(env):
+    """The full 256-scene batch (8.9M images, M log-uniform in [1k, 200k],
+    W in {16, 32, 64}) in the configuration bench.py times: scenes from
+    si_build_scenes, one graph at the library's defaults.  FAC and LEARNED
+    (untrained network: only the plan differs) give the same counts and the
+    same per-image checksums, the statistics count every in-support pair, and
+    8 sampled images of each of 24 scenes (all three widths) match the FP64
+    oracle."""
+    torch, si, oracle = env
+    print("\n[case] batch256 full", flush=True)
+    specs = sg.batch_specs(256)
+    data, raw = [], []
+    for seed, M, W in specs:
+        xyz, nrm = sg.batch_scene(seed, M)
+        params = si.Params(W, B, S60)
+        data.append((xyz, nrm, params))
+        raw.append((torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(),
+                    si.si_support_radius(params)))
+    scenes = si.si_build_scenes(raw)
+    items = []
+    for (xyz, _, params), sc in zip(data, scenes):
+        M, W = len(xyz), params.W
+        items.append((sc, torch.arange(M, dtype=torch.int32, device="cuda"), params,
+                      torch.full((M, W, W), -1.0, device="cuda"),
+                      torch.full((M,), -1, dtype=torch.int32, device="cuda")))
+
+    def digest():
+        return [(cnt.clone(), img.view(torch.int32).to(torch.int64).sum(dim=(1, 2)))
+                for _, _, _, img, cnt in items]
+
+    st = si.si_generate_batched(items, si.Sched("fac"), use_graph=True, stats=True)
+    torch.cuda.synchronize()
+    ref = digest()
+    assert st["pairs_in_support"] == sum(int(c.to(torch.int64).sum()) for c, _ in ref)
+    assert st["n_invalid"] == 0
+    model = si.si_cost_model_create(3)
+    si.si_generate_batched(items, si.Sched("learned", model=model), use_graph=True)
+    torch.cuda.synchronize()
+    for k, ((c0, h0), (c1, h1)) in enumerate(zip(ref, digest())):
+        assert torch.equal(c0, c1) and torch.equal(h0, h1), f"scene {k}"
+    rng = np.random.default_rng(256)
+    picks = []
+    for W in (16, 32, 64):
+        of_w = [k for k, (_, _, p) in enumerate(data) if p.W == W]
+        picks += list(rng.choice(of_w, size=8, replace=False))
+    for k in sorted(picks):
+        xyz, nrm, params = data[k]
+        M = len(xyz)
+        sample = np.sort(rng.choice(M, size=min(M, 8), replace=False)).astype(np.int32)
+        sel = torch.from_numpy(sample.astype(np.int64)).cuda()
+        img = items[k][3][sel].cpu().numpy()
+        cnt = items[k][4][sel].cpu().numpy().view(np.uint32)
+        ref_o = oracle.generate(xyz, nrm, sample, params.W, B, S60)
+        parity.check(img, cnt, ref_o, 0, f"batch256 scene {k} (W={params.W}, M={M})")

@@ -203,3 +203,27 @@ def test_learned_order_gain_simulated(env, prims):
     lt, lu = learned_makespan(pred_t), learned_makespan(pred_u)
     print(f"makespan FAC2 {fac:.0f} learned {lt:.0f} untrained {lu:.0f} mean {true.sum() / P:.0f}")
     assert lt < fac and lt <= lu
+
+
+def test_learned_clustered2m_identical(env):
+    """The learned schedule on the 2M-point clustered scene (every point
+    oriented) gives FAC's counts and images bit for bit (compared as per-image
+    checksums of the fixed-point words) and counts the same pairs."""
+    torch, si, _ = env
+    print("\n[case] learned clustered2m", flush=True)
+    xyz, nrm = sg.config_scene("clustered2m")
+    params = si.Params(32, 0.02, S60)
+    scene = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(),
+                              si.si_support_radius(params))
+    N = xyz.shape[0]
+    idx = torch.arange(N, dtype=torch.int32, device="cuda")
+    img, cnt, st = si.si_generate(scene, idx, params, si.Sched("fac"), stats=True)
+    ref = (cnt.clone(), img.view(torch.int32).to(torch.int64).sum(dim=(1, 2)))
+    del img
+    model = si.si_cost_model_create(3)
+    img, cnt, st2 = si.si_generate(scene, idx, params, si.Sched("learned", model=model), stats=True)
+    torch.cuda.synchronize()
+    assert st2["sched_used"] == si.SCHED["learned"]
+    assert st2["pairs_in_support"] == st["pairs_in_support"]
+    assert torch.equal(cnt, ref[0])
+    assert torch.equal(img.view(torch.int32).to(torch.int64).sum(dim=(1, 2)), ref[1])
