@@ -102,6 +102,9 @@ def parse():
     ap.add_argument("--no-extent", action="store_true",
                     help="stop after the timed steps (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    # images of the paper-shaped loop in the host replica of the paper's
+    # experiment (the oracle under STATIC, SS, GSS and FAC2; 0 = skip)
+    ap.add_argument("--cpu-sched-images", type=int, default=4096)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy BYTES device-to-device once, so that a "
                          "counter run sees a plain copy of known size beside the spin kernel")
@@ -269,6 +272,38 @@ def batched(torch, si, sg, model):
 # 64K images in 20.5 s with SS on 160 Xeon E5-2640 cores, every image testing
 # all of ~826K points -- end-to-end wall time including MPI.  Context only.
 PAPER_TESTS_PER_S_160_CORES_SS = 64_000 * 826_000 / 20.5
+
+
+def cpu_schedules(oracle, sg, threads, n_images):
+    """The paper's experiment on the host cores, as context: the oracle loop
+    over the first n_images images of the paper-shaped workload (826K points,
+    W = 5, B = 0.1 x mean nearest-neighbour spacing, S = 2 pi, brute force)
+    under STATIC, SS, GSS and a FAC2 chunk table, one thread per core."""
+    from oracle import chunks as och
+    pcfg = sg.CONFIGS["paper826k"]
+    xyz, nrm = sg.config_scene("paper826k")
+    M = xyz.shape[0]
+    B = 0.1 * sg.mean_nn_spacing(xyz)
+    n = min(pcfg.N, n_images)
+    idx = np.arange(n, dtype=np.int32)
+    out = {"workload": f"paper826k loop, its first {n} images (brute force over {M} points, "
+                       f"W={pcfg.W}, S=2 pi, FP64 oracle); best of two interleaved rounds",
+           "threads": threads}
+    # a warm-up call touches every point on every thread
+    oracle.generate(xyz, nrm, idx[:threads], pcfg.W, B, pcfg.support_angle, want_touch=False,
+                    schedule="static")
+    best = {}
+    for _ in range(2):
+        for name in ("static", "ss", "gss", "fac"):
+            sch = och.starts(och.fac_sizes(n, threads)) if name == "fac" else name
+            t = time.perf_counter()
+            oracle.generate(xyz, nrm, idx, pcfg.W, B, pcfg.support_angle, want_touch=False,
+                            schedule=sch)
+            best[name] = min(best.get(name, float("inf")), time.perf_counter() - t)
+    for name in ("static", "ss", "gss", "fac"):
+        out[name] = {"s": best[name], "pair_tests_per_s": n * M / best[name],
+                     "speedup_vs_static": best["static"] / best[name]}
+    return out
 
 
 def paper_shape(torch, si, sg):
@@ -522,6 +557,11 @@ def main():
                "sample": f"{done} seeded-random images of {cfg.name} (brute force over all {M} "
                          f"points each, FP64), {dt:.1f} s",
                "images_per_s": done / dt}
+        if args.cpu_sched_images > 0:
+            cpu["schedules"] = cpu_schedules(oracle, sg, threads, args.cpu_sched_images)
+            log("[bench] cpu schedules: " + ", ".join(
+                f"{k} {v['s']:.2f} s" for k, v in cpu["schedules"].items()
+                if isinstance(v, dict)))
 
     out = {
         "metric": METRIC,

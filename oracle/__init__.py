@@ -56,6 +56,9 @@ def _load():
         f.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32,
                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_double,
                       P, P, P, P, ctypes.c_int32]
+        g = lib.sio_generate_sched
+        g.restype = ctypes.c_int
+        g.argtypes = f.argtypes + [ctypes.c_int32, P, ctypes.c_int64]
         _lib = lib
     return _lib
 
@@ -64,13 +67,22 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
+SCHEDULES = {"static": 0, "ss": 1, "gss": 2}
+
+
 def generate(xyz, nrm, idx, W, bin, support_angle, mode=BILINEAR, eps=1e-6,
-             want_touch=True, nthreads=0):
+             want_touch=True, nthreads=0, schedule=None):
     """FP64 spin images of the oriented points ``idx`` of the scene (xyz, nrm).
 
     Returns a dict with ``img`` (N, W, W) float64 holding only surely-classified
     pairs, ``cnt_sure`` and ``cnt_amb`` (N,) int64, and ``touch`` (N, W, W)
     int32 (number of flagged pairs that might land in each bin) or None.
+
+    ``schedule`` distributes the loop over the host threads as the paper's
+    techniques do (Section 2.2): None (OpenMP dynamic chunks of 4), "static",
+    "ss", "gss", or an array of chunk starts (0 .. N, for example FAC2's from
+    ``chunks.starts``), chunks handed out one per request.  The results do
+    not depend on it.
     """
     lib = _load()
     xyz = np.ascontiguousarray(xyz, dtype=np.float32)
@@ -81,9 +93,15 @@ def generate(xyz, nrm, idx, W, bin, support_angle, mode=BILINEAR, eps=1e-6,
     cs = np.zeros(N, dtype=np.int64)
     ca = np.zeros(N, dtype=np.int64)
     tch = np.zeros((N, W, W), dtype=np.int32) if want_touch else None
-    rc = lib.sio_generate(_ptr(xyz), _ptr(nrm), M, _ptr(idx), N, int(W),
-                          float(bin), float(support_angle), int(mode), float(eps),
-                          _ptr(img), _ptr(cs), _ptr(ca), _ptr(tch), int(nthreads))
+    args = (_ptr(xyz), _ptr(nrm), M, _ptr(idx), N, int(W), float(bin), float(support_angle),
+            int(mode), float(eps), _ptr(img), _ptr(cs), _ptr(ca), _ptr(tch), int(nthreads))
+    if schedule is None:
+        rc = lib.sio_generate(*args)
+    elif isinstance(schedule, str):
+        rc = lib.sio_generate_sched(*args, SCHEDULES[schedule], None, 0)
+    else:
+        st = np.ascontiguousarray(schedule, dtype=np.int64)
+        rc = lib.sio_generate_sched(*args, 3, _ptr(st), st.shape[0] - 1)
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return {"img": img, "cnt_sure": cs, "cnt_amb": ca, "touch": tch}

@@ -91,11 +91,27 @@ static void touch_box(int32_t* t, int W, long r0, long r1, long c0, long c1)
  *   cnt_sure, cnt_amb : N int64 each
  *   touch    : N x W x W int32 (zeroed here) or NULL
  */
-int sio_generate(const float* xyz, const float* nrm, int64_t M,
-                 const int32_t* idx, int64_t N,
-                 int32_t W, float bin, float support_angle, int32_t mode,
-                 double eps, double* img_sure, int64_t* cnt_sure,
-                 int64_t* cnt_amb, int32_t* touch, int32_t nthreads)
+/* Everything one image's loop needs (the widened thresholds of its call). */
+typedef struct {
+    const float* xyz;
+    const float* nrm;
+    int64_t M;
+    const int32_t* idx;
+    int32_t W;
+    int32_t mode;
+    double eps, B, cosS, half, WW, beta_hi, beta_lo, alpha_max;
+    int vacuous;
+    double* img_sure;
+    int64_t* cnt_sure;
+    int64_t* cnt_amb;
+    int32_t* touch;
+} Job;
+
+/* Checks the arguments and fills the job; 0 or -1. */
+static int make_job(Job* jb, const float* xyz, const float* nrm, int64_t M,
+                    const int32_t* idx, int64_t N, int32_t W, float bin,
+                    float support_angle, int32_t mode, double eps, double* img_sure,
+                    int64_t* cnt_sure, int64_t* cnt_amb, int32_t* touch)
 {
     if (M <= 0 || N < 0 || W < 1 || !(bin > 0.0f) || !(support_angle >= 0.0f))
         return -1;
@@ -104,109 +120,209 @@ int sio_generate(const float* xyz, const float* nrm, int64_t M,
     for (int64_t i = 0; i < N; ++i)
         if (idx[i] < 0 || idx[i] >= M)
             return -1;
-
-    const double B = (double)bin;
+    jb->xyz = xyz;
+    jb->nrm = nrm;
+    jb->M = M;
+    jb->idx = idx;
+    jb->W = W;
+    jb->mode = mode;
+    jb->eps = eps;
+    jb->B = (double)bin;
     const double S = (double)support_angle;
-    const int vacuous = S >= M_PI;
-    const double cosS = cos(S);
-    const double half = 0.5 * (double)W;
-    const double WW = (double)W;
+    jb->vacuous = S >= M_PI;
+    jb->cosS = cos(S);
+    jb->half = 0.5 * (double)W;
+    jb->WW = (double)W;
     /* support thresholds in scene units */
-    const double beta_hi = (mode == SIO_CEIL) ? B * (half + 1.0) : B * half;
-    const double beta_lo = B * (1.0 - half);
-    const double alpha_max = B * (WW - 1.0);
+    jb->beta_hi = (mode == SIO_CEIL) ? jb->B * (jb->half + 1.0) : jb->B * jb->half;
+    jb->beta_lo = jb->B * (1.0 - jb->half);
+    jb->alpha_max = jb->B * (jb->WW - 1.0);
+    jb->img_sure = img_sure;
+    jb->cnt_sure = cnt_sure;
+    jb->cnt_amb = cnt_amb;
+    jb->touch = touch;
+    return 0;
+}
 
+/* The inner loop of Algorithm 1 for image i: P = OP[idx[i]] against all M points. */
+static void one_image(const Job* jb, int64_t i)
+{
+    const float* xyz = jb->xyz;
+    const float* nrm = jb->nrm;
+    const int64_t M = jb->M;
+    const int32_t W = jb->W;
+    const double eps = jb->eps, B = jb->B, cosS = jb->cosS, half = jb->half, WW = jb->WW;
+    const double beta_hi = jb->beta_hi, beta_lo = jb->beta_lo, alpha_max = jb->alpha_max;
+    const int vacuous = jb->vacuous;
+    const int32_t mode = jb->mode;
+    double* img = jb->img_sure + (size_t)i * W * W;
+    int32_t* tch = jb->touch ? jb->touch + (size_t)i * W * W : NULL;
+    memset(img, 0, sizeof(double) * (size_t)W * W);
+    if (tch)
+        memset(tch, 0, sizeof(int32_t) * (size_t)W * W);
+    int64_t sure = 0, amb = 0;
+
+    const int64_t pi = jb->idx[i];
+    const double px = xyz[3 * pi], py = xyz[3 * pi + 1], pz = xyz[3 * pi + 2];
+    const double nx = nrm[3 * pi], ny = nrm[3 * pi + 1], nz = nrm[3 * pi + 2];
+
+    for (int64_t j = 0; j < M; ++j) {
+        const double qx = xyz[3 * j], qy = xyz[3 * j + 1], qz = xyz[3 * j + 2];
+        const double mx = nrm[3 * j], my = nrm[3 * j + 1], mz = nrm[3 * j + 2];
+
+        const double c = nx * mx + ny * my + nz * mz;
+        const double dx = qx - px, dy = qy - py, dz = qz - pz;
+        const double beta = nx * dx + ny * dy + nz * dz;
+        const double dd = dx * dx + dy * dy + dz * dz;
+        const double a2 = dd - beta * beta;
+        const double alpha = sqrt(a2 > 0.0 ? a2 : 0.0);
+        const double v = half - beta / B;
+        const double u = alpha / B;
+
+        int ca = vacuous ? C_TRUE : cond(c >= cosS, c - cosS, eps);
+        int c1, c2, c3;
+        if (mode == SIO_CEIL) {
+            const double kk = ceil(v), ll = ceil(u);
+            c1 = cond(kk >= 0.0, beta - beta_hi, eps);      /* k >= 0 */
+            c2 = cond(kk < WW, beta - beta_lo, eps);        /* k < W  */
+            c3 = cond(ll >= 0.0 && ll < WW, alpha - alpha_max, eps);
+        } else {
+            c1 = cond(v >= 0.0, beta - beta_hi, eps);
+            c2 = cond(v < WW - 1.0, beta - beta_lo, eps);
+            c3 = cond(u < WW - 1.0, alpha - alpha_max, eps);
+        }
+        if (ca == C_FALSE || c1 == C_FALSE || c2 == C_FALSE || c3 == C_FALSE)
+            continue;
+        const int unsure = (ca == C_UNSURE) || (c1 == C_UNSURE) ||
+                           (c2 == C_UNSURE) || (c3 == C_UNSURE);
+
+        if (mode == SIO_CEIL) {
+            const long k = (long)ceil(v), l = (long)ceil(u);
+            if (unsure) {
+                ++amb;
+                touch_box(tch, W, k - 1, k + 1, l - 1, l + 1);
+                continue;
+            }
+            ++sure;
+            int row_unsure = 0, col_unsure = 0;
+            /* x == p (the self-pair, duplicate points) is exact in any
+               precision: beta = alpha = 0, never ambiguous */
+            if (eps > 0.0 && (dx != 0.0 || dy != 0.0 || dz != 0.0)) {
+                const double m = nearbyint(v);             /* nearest row edge */
+                row_unsure = fabs(beta - B * (half - m)) < eps;
+                const double q = nearbyint(u);             /* nearest column edge */
+                col_unsure = (q >= 1.0 && fabs(alpha - B * q) < eps) ||
+                             (a2 != 0.0 && fabs(a2) < 1e-6);
+            }
+            if (row_unsure || col_unsure) {
+                touch_box(tch, W, row_unsure ? k - 1 : k, row_unsure ? k + 1 : k,
+                          col_unsure ? l - 1 : l, col_unsure ? l + 1 : l);
+            } else {
+                img[k * W + l] += 1.0;
+            }
+        } else {
+            const double fi = floor(v), fj = floor(u);
+            if (unsure) {
+                ++amb;
+                touch_box(tch, W, (long)fi - 1, (long)fi + 2, (long)fj - 1, (long)fj + 2);
+                continue;
+            }
+            ++sure;
+            const long i0 = (long)fi, j0 = (long)fj;
+            const double a = v - fi, b = u - fj;
+            img[i0 * W + j0] += (1.0 - a) * (1.0 - b);
+            img[(i0 + 1) * W + j0] += a * (1.0 - b);
+            img[i0 * W + j0 + 1] += (1.0 - a) * b;
+            img[(i0 + 1) * W + j0 + 1] += a * b;
+        }
+    }
+    jb->cnt_sure[i] = sure;
+    jb->cnt_amb[i] = amb;
+}
+
+/*
+ * Returns 0 on success, -1 on invalid arguments.
+ *   xyz, nrm : M x 3 float32, row-major
+ *   idx      : N int32 indices into [0, M)
+ *   img_sure : N x W x W doubles (zeroed here)
+ *   cnt_sure, cnt_amb : N int64 each
+ *   touch    : N x W x W int32 (zeroed here) or NULL
+ */
+int sio_generate(const float* xyz, const float* nrm, int64_t M,
+                 const int32_t* idx, int64_t N,
+                 int32_t W, float bin, float support_angle, int32_t mode,
+                 double eps, double* img_sure, int64_t* cnt_sure,
+                 int64_t* cnt_amb, int32_t* touch, int32_t nthreads)
+{
+    Job jb;
+    if (make_job(&jb, xyz, nrm, M, idx, N, W, bin, support_angle, mode, eps, img_sure,
+                 cnt_sure, cnt_amb, touch) != 0)
+        return -1;
     (void)nthreads;
 #ifdef _OPENMP
     if (nthreads > 0)
         omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
 #endif
-    for (int64_t i = 0; i < N; ++i) {
-        double* img = img_sure + (size_t)i * W * W;
-        int32_t* tch = touch ? touch + (size_t)i * W * W : NULL;
-        memset(img, 0, sizeof(double) * (size_t)W * W);
-        if (tch)
-            memset(tch, 0, sizeof(int32_t) * (size_t)W * W);
-        int64_t sure = 0, amb = 0;
+    for (int64_t i = 0; i < N; ++i)
+        one_image(&jb, i);
+    return 0;
+}
 
-        const int64_t pi = idx[i];
-        const double px = xyz[3 * pi], py = xyz[3 * pi + 1], pz = xyz[3 * pi + 2];
-        const double nx = nrm[3 * pi], ny = nrm[3 * pi + 1], nz = nrm[3 * pi + 2];
-
-        for (int64_t j = 0; j < M; ++j) {
-            const double qx = xyz[3 * j], qy = xyz[3 * j + 1], qz = xyz[3 * j + 2];
-            const double mx = nrm[3 * j], my = nrm[3 * j + 1], mz = nrm[3 * j + 2];
-
-            const double c = nx * mx + ny * my + nz * mz;
-            const double dx = qx - px, dy = qy - py, dz = qz - pz;
-            const double beta = nx * dx + ny * dy + nz * dz;
-            const double dd = dx * dx + dy * dy + dz * dz;
-            const double a2 = dd - beta * beta;
-            const double alpha = sqrt(a2 > 0.0 ? a2 : 0.0);
-            const double v = half - beta / B;
-            const double u = alpha / B;
-
-            int ca = vacuous ? C_TRUE : cond(c >= cosS, c - cosS, eps);
-            int c1, c2, c3;
-            if (mode == SIO_CEIL) {
-                const double kk = ceil(v), ll = ceil(u);
-                c1 = cond(kk >= 0.0, beta - beta_hi, eps);      /* k >= 0 */
-                c2 = cond(kk < WW, beta - beta_lo, eps);        /* k < W  */
-                c3 = cond(ll >= 0.0 && ll < WW, alpha - alpha_max, eps);
-            } else {
-                c1 = cond(v >= 0.0, beta - beta_hi, eps);
-                c2 = cond(v < WW - 1.0, beta - beta_lo, eps);
-                c3 = cond(u < WW - 1.0, alpha - alpha_max, eps);
-            }
-            if (ca == C_FALSE || c1 == C_FALSE || c2 == C_FALSE || c3 == C_FALSE)
-                continue;
-            const int unsure = (ca == C_UNSURE) || (c1 == C_UNSURE) ||
-                               (c2 == C_UNSURE) || (c3 == C_UNSURE);
-
-            if (mode == SIO_CEIL) {
-                const long k = (long)ceil(v), l = (long)ceil(u);
-                if (unsure) {
-                    ++amb;
-                    touch_box(tch, W, k - 1, k + 1, l - 1, l + 1);
-                    continue;
-                }
-                ++sure;
-                int row_unsure = 0, col_unsure = 0;
-                /* x == p (the self-pair, duplicate points) is exact in any
-                   precision: beta = alpha = 0, never ambiguous */
-                if (eps > 0.0 && (dx != 0.0 || dy != 0.0 || dz != 0.0)) {
-                    const double m = nearbyint(v);             /* nearest row edge */
-                    row_unsure = fabs(beta - B * (half - m)) < eps;
-                    const double q = nearbyint(u);             /* nearest column edge */
-                    col_unsure = (q >= 1.0 && fabs(alpha - B * q) < eps) ||
-                                 (a2 != 0.0 && fabs(a2) < 1e-6);
-                }
-                if (row_unsure || col_unsure) {
-                    touch_box(tch, W, row_unsure ? k - 1 : k, row_unsure ? k + 1 : k,
-                              col_unsure ? l - 1 : l, col_unsure ? l + 1 : l);
-                } else {
-                    img[k * W + l] += 1.0;
-                }
-            } else {
-                const double fi = floor(v), fj = floor(u);
-                if (unsure) {
-                    ++amb;
-                    touch_box(tch, W, (long)fi - 1, (long)fi + 2, (long)fj - 1, (long)fj + 2);
-                    continue;
-                }
-                ++sure;
-                const long i0 = (long)fi, j0 = (long)fj;
-                const double a = v - fi, b = u - fj;
-                img[i0 * W + j0] += (1.0 - a) * (1.0 - b);
-                img[(i0 + 1) * W + j0] += a * (1.0 - b);
-                img[i0 * W + j0 + 1] += (1.0 - a) * b;
-                img[(i0 + 1) * W + j0 + 1] += a * b;
-            }
-        }
-        cnt_sure[i] = sure;
-        cnt_amb[i] = amb;
+/*
+ * The same loop with its iterations distributed over the host threads by a
+ * loop-scheduling technique of Section 2.2 (the paper's experiment on one
+ * node, threads in place of MPI workers):
+ *   sched 0  STATIC: one contiguous, balanced block per thread;
+ *   sched 1  SS: one iteration per request;
+ *   sched 2  GSS: each request takes ceil(remaining / threads) iterations
+ *            (OpenMP's guided schedule with chunk 1);
+ *   sched 3  a table of chunks: chunk_starts[0..n_chunks] ascending from 0
+ *            to N, chunks requested one at a time (FAC2 from the table).
+ * Results are those of sio_generate; returns -1 on invalid arguments.
+ */
+int sio_generate_sched(const float* xyz, const float* nrm, int64_t M,
+                       const int32_t* idx, int64_t N,
+                       int32_t W, float bin, float support_angle, int32_t mode,
+                       double eps, double* img_sure, int64_t* cnt_sure,
+                       int64_t* cnt_amb, int32_t* touch, int32_t nthreads,
+                       int32_t sched, const int64_t* chunk_starts, int64_t n_chunks)
+{
+    Job jb;
+    if (make_job(&jb, xyz, nrm, M, idx, N, W, bin, support_angle, mode, eps, img_sure,
+                 cnt_sure, cnt_amb, touch) != 0)
+        return -1;
+    if (sched < 0 || sched > 3)
+        return -1;
+    if (sched == 3) {
+        if (!chunk_starts || n_chunks < 0 || chunk_starts[0] != 0 ||
+            chunk_starts[n_chunks] != N)
+            return -1;
+        for (int64_t c = 0; c < n_chunks; ++c)
+            if (chunk_starts[c + 1] < chunk_starts[c])
+                return -1;
     }
+    (void)nthreads;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+    if (sched == 3) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t c = 0; c < n_chunks; ++c)
+            for (int64_t i = chunk_starts[c]; i < chunk_starts[c + 1]; ++i)
+                one_image(&jb, i);
+        return 0;
+    }
+    omp_set_schedule(sched == 0 ? omp_sched_static
+                     : sched == 1 ? omp_sched_dynamic : omp_sched_guided,
+                     sched == 0 ? 0 : 1);
+#pragma omp parallel for schedule(runtime)
+    for (int64_t i = 0; i < N; ++i)
+        one_image(&jb, i);
+#else
+    for (int64_t i = 0; i < N; ++i)
+        one_image(&jb, i);
+#endif
     return 0;
 }
 

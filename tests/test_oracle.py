@@ -269,3 +269,29 @@ def test_oracle_rejects_bad_arguments(oracle_mod):
         oracle_mod.generate(xyz, nrm, [10], 8, 0.1, 1.0)
     with pytest.raises(ValueError):
         oracle_mod.generate(xyz, nrm, [0], 8, 0.0, 1.0)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_scheduled_loop_same_results(oracle_mod, mode):
+    """The oracle loop distributed by STATIC, SS, GSS or a FAC2 chunk table
+    (the host replica of the paper's experiment) gives the default loop's
+    images, counts and flags: iterations are independent (a DOALL loop)."""
+    from oracle import chunks as och
+    xyz, nrm = sg.uniform_box_scene(2500, seed=21, box=1.0)
+    idx = np.arange(0, 2500, 5, dtype=np.int32)
+    ref = oracle_mod.generate(xyz, nrm, idx, 16, 0.02, S60, mode=mode)
+    tables = ["static", "ss", "gss", och.starts(och.fac_sizes(len(idx), 6)),
+              och.starts(och.gss_sizes(len(idx), 3))]
+    for sch in tables:
+        r = oracle_mod.generate(xyz, nrm, idx, 16, 0.02, S60, mode=mode, schedule=sch,
+                                nthreads=3)
+        for k in ("img", "cnt_sure", "cnt_amb", "touch"):
+            assert np.array_equal(r[k], ref[k]), (k, sch if isinstance(sch, str) else "table")
+
+
+def test_scheduled_loop_rejects_bad_tables(oracle_mod):
+    xyz, nrm = sg.uniform_box_scene(20, seed=2)
+    idx = np.arange(10, dtype=np.int32)
+    for bad in ([0, 5, 9], [1, 10], [0, 6, 4, 10]):     # short, not from 0, descending
+        with pytest.raises(ValueError):
+            oracle_mod.generate(xyz, nrm, idx, 8, 0.1, 1.0, schedule=np.array(bad))
