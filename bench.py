@@ -480,8 +480,21 @@ def main():
         runs = [(k, k, "spread") for k in ("static", "ss", "gss", "fac")]
         runs += [(k + "_cell", k, "cell") for k in ("static", "ss", "gss", "fac")]
         runs += [("learned", "learned", "spread")]
+        # two later techniques of the family: TSS, and probabilistic factoring
+        # fed with sigma / mu of the per-image cost (the cost model's predicted
+        # in-support counts + 1; the measured counts without a model)
+        cost = ref_cnt.to(torch.float64) + 1.0
+        cv_source = "measured in-support counts + 1"
+        if model is not None:
+            pred = si.si_cost_model_predict(model, si.si_features(scene, idx, params))
+            cost = pred.to(torch.float64).clamp_min(0.0) + 1.0
+            cv_source = "cost model's predicted in-support counts + 1"
+        cost_cv = float(cost.std() / cost.mean())
+        del cost
+        runs += [("tss", "tss", "spread"), ("fac_prob", "fac_prob", "spread")]
         for name, kind, order in runs:
-            sch = si.Sched(kind, model=model if kind == "learned" else None, order=order)
+            sch = si.Sched(kind, model=model if kind == "learned" else None, order=order,
+                           fac_divisor=cost_cv if kind == "fac_prob" else 0.0)
             times, used, ok = [], None, True
             for r in range(WARM + REPS):
                 images.fill_(-1.0)
@@ -506,6 +519,8 @@ def main():
             log(f"[bench] {name}: kernel {sched_res[name]['kernel_ms']['median']:.2f} ms, "
                 f"call {call['median']:.2f} ms, identical {ok}, "
                 f"imbalance {sched_res[name]['imbalance']:.3f}")
+        sched_res["fac_prob"]["cost_cv"] = cost_cv
+        sched_res["fac_prob"]["cost_cv_source"] = cv_source
         base = sched_res["static"]["call_ms"]["median"]
         base_cell = sched_res["static_cell"]["call_ms"]["median"]
         for k in sched_res:

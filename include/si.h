@@ -56,7 +56,10 @@ enum {
     SI_SCHED_SS = 1,      /* self-scheduling: one image per claim             */
     SI_SCHED_GSS = 2,     /* guided: ceil(remaining / P) per claim            */
     SI_SCHED_FAC = 3,     /* factoring: batches of P chunks ceil(R_b/(x P))   */
-    SI_SCHED_LEARNED = 4  /* cost-model order + cost-weighted factoring       */
+    SI_SCHED_LEARNED = 4, /* cost-model order + cost-weighted factoring       */
+    /* two later techniques of the family (the paper's future work) */
+    SI_SCHED_TSS = 5,     /* trapezoid: sizes fall linearly from N/(2P) to 1  */
+    SI_SCHED_FAC_PROB = 6 /* probabilistic factoring from the cost's sigma/mu */
 };
 
 /* Binning of a pair into the image (see si_params). */
@@ -97,7 +100,17 @@ typedef struct si_params {
  *   kind            SI_SCHED_*
  *   num_workgroups  P; 0 = library default for the device and W
  *   min_chunk       lower bound of every dynamic chunk (0 or 1 = none)
- *   fac_divisor     x of SI_SCHED_FAC / SI_SCHED_LEARNED; 0 = 2 (FAC2)
+ *   fac_divisor     x of SI_SCHED_FAC / SI_SCHED_LEARNED; 0 = 2 (FAC2).
+ *                   For SI_SCHED_FAC_PROB: cv = sigma / mu of the per-image
+ *                   cost (>= 0), which sets each batch's ratio x_j
+ *                   (Hummel, Schonberg and Flynn 1992): with
+ *                   b_j = P cv / (2 sqrt(R_j)), x_0 = 1 + b_0^2 +
+ *                   b_0 sqrt(b_0^2 + 2), x_j = 2 + b_j^2 + b_j sqrt(b_j^2 + 4);
+ *                   cv = 0 gives one batch (STATIC's blocks, claimed
+ *                   dynamically).  SI_SCHED_TSS (Tzen and Ni 1993): chunk i
+ *                   has ceil(F - i delta) iterations, F = ceil(N / (2P)),
+ *                   delta = (F - L) / (C - 1) (real), C = ceil(2N / (F + L)),
+ *                   never below L = max(1, min_chunk).
  *   model           SI_SCHED_LEARNED only; trained cost model
  *   fallback_to_fac SI_SCHED_LEARNED without a model: 1 = run FAC, 0 = error
  *   group           images that share one pass over their common candidate
@@ -394,7 +407,10 @@ si_status si_cost_model_load(const char* path, si_cost_model** out);
  * Writes chunk starts (n_chunks + 1 entries, the last = N) to starts_out
  * (host, capacity cap) and the count to *n_chunks.  STATIC gives P
  * balanced blocks; SS, GSS and FAC follow Section 2.2 (FAC as FAC2 with
- * divisor x).  Returns SI_E_INVALID when cap is too small.
+ * divisor x); SI_SCHED_TSS and SI_SCHED_FAC_PROB as in si_sched (for
+ * FAC_PROB, fac_divisor carries sigma / mu).  SI_SCHED_LEARNED has no
+ * fixed table (si_learned_table).  Returns SI_E_INVALID when cap is too
+ * small or the kind is unknown.
  */
 si_status si_chunk_table(int32_t kind, int64_t N, int32_t P, int32_t min_chunk,
                          float fac_divisor, int64_t* starts_out, int64_t cap,

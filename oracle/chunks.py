@@ -15,6 +15,20 @@ Section 2.2 of the paper describes the techniques in words:
     so the FAC2 rule of Hummel et al. (cited by the paper) is used: batch b
     has P chunks of ceil(R_b / (x P)) with x = 2, the last chunks clamped to
     what remains.
+Two later techniques of the same family, which the paper leaves to future
+work (more complex dynamic loop scheduling), follow their authors' papers:
+  * FAC_PROB -- probabilistic factoring (Hummel, Schonberg and Flynn 1992):
+    batch j of P chunks of ceil(R_j / (x_j P)), where with
+    b_j = P cv / (2 sqrt(R_j)) and cv = sigma / mu of the iteration cost,
+    x_0 = 1 + b_0^2 + b_0 sqrt(b_0^2 + 2) for the first batch and
+    x_j = 2 + b_j^2 + b_j sqrt(b_j^2 + 4) for the later ones;
+  * TSS      -- trapezoid self-scheduling (Tzen and Ni 1993): chunk sizes fall
+    linearly from F = ceil(N / (2P)) towards L = 1 over
+    C = ceil(2N / (F + L)) chunks: chunk i has ceil(F - i delta) iterations
+    (never below L) with the real step delta = (F - L) / (C - 1), the last
+    chunk clamped to what remains.  An integer step would be 0 whenever
+    C - 1 > F - L, which is the case for a GPU's P (N = 2M, P = 1280 gives
+    delta = 0.15), and TSS would degenerate to fixed chunks of N / (2P).
 ``min_chunk`` raises every dynamic chunk to at least that many iterations.
 
 Chunks are half-open [start, end) ranges of the iteration space in order; a
@@ -34,6 +48,7 @@ import math
 import numpy as np
 
 STATIC, SS, GSS, FAC = 0, 1, 2, 3
+TSS, FAC_PROB = 5, 6
 
 
 def static_sizes(N: int, P: int) -> list[int]:
@@ -74,6 +89,48 @@ def fac_sizes(N: int, P: int, divisor: float = 2.0, min_chunk: int = 1) -> list[
     return out
 
 
+def fac_prob_ratio(R: int, P: int, cv: float, first: bool) -> float:
+    """Hummel's x_j of a batch with R iterations remaining."""
+    b = P * cv / (2.0 * math.sqrt(R))
+    if first:
+        return 1.0 + b * b + b * math.sqrt(b * b + 2.0)
+    return 2.0 + b * b + b * math.sqrt(b * b + 4.0)
+
+
+def fac_prob_sizes(N: int, P: int, cv: float, min_chunk: int = 1) -> list[int]:
+    out, R = [], N
+    cv = float(np.float32(cv))
+    first = True
+    while R > 0:
+        x = fac_prob_ratio(R, P, cv, first)
+        first = False
+        c = max(int(math.ceil(R / (x * P))), min_chunk, 1)
+        for _ in range(P):
+            if R == 0:
+                break
+            k = min(c, R)
+            out.append(k)
+            R -= k
+    return out
+
+
+def tss_sizes(N: int, P: int, min_chunk: int = 1) -> list[int]:
+    if N <= 0:
+        return []
+    last = max(1, min_chunk)
+    first = max(-(-N // (2 * P)), last)
+    n = -(-2 * N // (first + last))
+    delta = (first - last) / (n - 1) if n > 1 else 0.0
+    out, R, i = [], N, 0
+    while R > 0:
+        c = max(int(math.ceil(first - i * delta)), last)
+        k = min(c, R)
+        out.append(k)
+        R -= k
+        i += 1
+    return out
+
+
 def sizes(kind: int, N: int, P: int, min_chunk: int = 1, divisor: float = 2.0) -> list[int]:
     if kind == STATIC:
         return static_sizes(N, P)
@@ -83,6 +140,10 @@ def sizes(kind: int, N: int, P: int, min_chunk: int = 1, divisor: float = 2.0) -
         return gss_sizes(N, P, min_chunk)
     if kind == FAC:
         return fac_sizes(N, P, divisor, min_chunk)
+    if kind == TSS:
+        return tss_sizes(N, P, min_chunk)
+    if kind == FAC_PROB:
+        return fac_prob_sizes(N, P, divisor, min_chunk)
     raise ValueError(kind)
 
 

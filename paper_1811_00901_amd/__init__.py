@@ -32,7 +32,7 @@ __all__ = [
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libspinimg.so")
 
-SCHED = {"static": 0, "ss": 1, "gss": 2, "fac": 3, "learned": 4}
+SCHED = {"static": 0, "ss": 1, "gss": 2, "fac": 3, "learned": 4, "tss": 5, "fac_prob": 6}
 PROBE = {"valu": 0, "lds_atomic_seq": 1, "lds_atomic_random": 2, "hbm_copy": 3}
 MODE = {"bilinear": 0, "ceil": 1}
 ORDER = {"spread": 0, "given": 1, "cell": 2}
@@ -197,6 +197,7 @@ class Sched:
     kind: str = "fac"
     num_workgroups: int = 0
     min_chunk: int = 0
+    # FAC / LEARNED: the divisor x (0 = 2); "fac_prob": sigma / mu of the cost
     fac_divisor: float = 0.0
     model: "CostModel | None" = None
     fallback_to_fac: bool = True

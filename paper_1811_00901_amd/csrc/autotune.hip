@@ -161,7 +161,7 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
                                  si_sched* best, double* best_ms, void* hip_stream) {
     if (!best) return fail(SI_E_INVALID, "best is NULL");
     if (n_items <= 0 || !items) return fail(SI_E_INVALID, "empty item list");
-    if (kind < SI_SCHED_STATIC || kind > SI_SCHED_LEARNED) return fail(SI_E_INVALID, "bad kind");
+    if (kind < SI_SCHED_STATIC || kind > SI_SCHED_FAC_PROB) return fail(SI_E_INVALID, "bad kind");
     if (max_trials < 1) max_trials = 1;
     hipStream_t s = (hipStream_t)hip_stream;
     DeviceState* st;

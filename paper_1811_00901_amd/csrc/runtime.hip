@@ -161,6 +161,39 @@ int64_t chunk_sizes(int kind, int64_t N, int P, int min_chunk, float divisor, in
             put(c);
             R -= c;
         }
+    } else if (kind == SI_SCHED_TSS) {
+        // trapezoid self-scheduling: sizes fall linearly from F = ceil(N / 2P)
+        // towards L over C = ceil(2N / (F + L)) chunks, chunk i of
+        // ceil(F - i delta) with the real step delta = (F - L) / (C - 1)
+        const int64_t L = mc;
+        const int64_t F = std::max((N + 2 * (int64_t)P - 1) / (2 * (int64_t)P), L);
+        const int64_t C = (2 * N + F + L - 1) / (F + L);
+        const double delta = C > 1 ? (double)(F - L) / (double)(C - 1) : 0.0;
+        int64_t i = 0;
+        for (int64_t R = N; R > 0; ++i) {
+            const int64_t c = std::max((int64_t)ceil((double)F - (double)i * delta), L);
+            const int64_t k = std::min(c, R);
+            put(k);
+            R -= k;
+        }
+    } else if (kind == SI_SCHED_FAC_PROB) {
+        // probabilistic factoring: batch j of P chunks of ceil(R_j / (x_j P)),
+        // x_j from b_j = P cv / (2 sqrt(R_j)), cv = sigma / mu of the
+        // iteration cost (the first batch's ratio differs from the later ones')
+        const double cv = (double)divisor;
+        bool first = true;
+        for (int64_t R = N; R > 0;) {
+            const double b = (double)P * cv / (2.0 * sqrt((double)R));
+            const double x = first ? 1.0 + b * b + b * sqrt(b * b + 2.0)
+                                   : 2.0 + b * b + b * sqrt(b * b + 4.0);
+            first = false;
+            const int64_t c = std::max((int64_t)ceil((double)R / (x * (double)P)), mc);
+            for (int k = 0; k < P && R > 0; ++k) {
+                const int64_t cc = std::min(c, R);
+                put(cc);
+                R -= cc;
+            }
+        }
     } else {  // FAC / LEARNED tables over equal-cost units
         const double x = divisor > 0.0f ? (double)divisor : 2.0;
         for (int64_t R = N; R > 0;) {
@@ -178,12 +211,14 @@ int64_t chunk_sizes(int kind, int64_t N, int P, int min_chunk, float divisor, in
 
 si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk,
                            float divisor, Chunk** out, int* n_out) {
+    // the parameter: FAC's divisor (0 = 2), FAC_PROB's cost variation (0 kept)
     uint32_t dbits;
-    const float dv = divisor > 0.0f ? divisor : 2.0f;
+    const float dv = kind == SI_SCHED_FAC_PROB ? divisor : divisor > 0.0f ? divisor : 2.0f;
     memcpy(&dbits, &dv, 4);
-    const int kk = kind == SI_SCHED_FAC ? SI_SCHED_FAC : kind;
+    const int kk = kind;
+    const bool param = kk == SI_SCHED_FAC || kk == SI_SCHED_FAC_PROB;
     auto key = std::make_tuple(kk, N, P, kind == SI_SCHED_STATIC ? 0 : std::max(1, min_chunk),
-                               kk == SI_SCHED_FAC ? dbits : 0u);
+                               param ? dbits : 0u);
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = st->tables.find(key);
@@ -629,7 +664,8 @@ si_status si_support_radius(const si_params* params, float* radius) {
 si_status si_chunk_table(int32_t kind, int64_t N, int32_t P, int32_t min_chunk,
                          float fac_divisor, int64_t* starts_out, int64_t cap,
                          int64_t* n_chunks) {
-    if (kind < SI_SCHED_STATIC || kind > SI_SCHED_FAC) return fail(SI_E_INVALID, "bad kind");
+    if (kind < SI_SCHED_STATIC || kind > SI_SCHED_FAC_PROB || kind == SI_SCHED_LEARNED)
+        return fail(SI_E_INVALID, "bad kind");
     if (N < 0 || P < 1) return fail(SI_E_INVALID, "N must be >= 0 and P >= 1");
     if (fac_divisor < 0.0f || !isfinite(fac_divisor)) return fail(SI_E_INVALID, "bad divisor");
     const int64_t n = chunk_sizes(kind, N, P, min_chunk, fac_divisor, nullptr, 0);
@@ -735,13 +771,13 @@ si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_st
 
 si_status check_sched(const si_sched* sc) {
     if (!sc) return fail(SI_E_INVALID, "sched is NULL");
-    if (sc->kind < SI_SCHED_STATIC || sc->kind > SI_SCHED_LEARNED)
+    if (sc->kind < SI_SCHED_STATIC || sc->kind > SI_SCHED_FAC_PROB)
         return fail(SI_E_INVALID, "unknown schedule kind");
     if (sc->num_workgroups < 0) return fail(SI_E_INVALID, "num_workgroups must be >= 0");
     if (sc->min_chunk < 0) return fail(SI_E_INVALID, "min_chunk must be >= 0");
     if (!isfinite(sc->fac_divisor) || sc->fac_divisor < 0.0f)
         return fail(SI_E_INVALID, "fac_divisor must be finite and >= 0");
-    if (sc->fac_divisor > 0.0f && sc->fac_divisor < 1.0f)
+    if (sc->kind != SI_SCHED_FAC_PROB && sc->fac_divisor > 0.0f && sc->fac_divisor < 1.0f)
         return fail(SI_E_INVALID, "fac_divisor must be >= 1");
     if (sc->group < 0 || sc->group > kMaxGroup) return fail(SI_E_INVALID, "group must be in [0, 8]");
     if (sc->order != SI_ORDER_SPREAD && sc->order != SI_ORDER_CELL && sc->order != SI_ORDER_GIVEN)

@@ -64,10 +64,10 @@ def test_param_validation(si, bad):
     assert e.value.status == -1
 
 
-KIND = {"static": och.STATIC, "ss": och.SS, "gss": och.GSS, "fac": och.FAC}
+KIND = {"static": och.STATIC, "ss": och.SS, "gss": och.GSS, "fac": och.FAC, "tss": och.TSS}
 
 
-@pytest.mark.parametrize("kind", ["static", "ss", "gss", "fac"])
+@pytest.mark.parametrize("kind", ["static", "ss", "gss", "fac", "tss"])
 @pytest.mark.parametrize("N,P", [(0, 4), (1, 4), (10, 3), (100, 4), (65536, 1024), (99991, 768),
                                  (2_000_000, 2048)])
 def test_library_chunk_tables_equal_oracle(si, kind, N, P):
@@ -84,6 +84,23 @@ def test_library_chunk_tables_variants(si, mc, div):
         got = si.si_chunk_table(kind, 12345, 64, mc, div)
         exp = och.starts(och.sizes(KIND[kind], 12345, 64, min_chunk=mc, divisor=div or 2.0))
         np.testing.assert_array_equal(got, exp)
+
+
+@pytest.mark.parametrize("cv", [0.0, 0.25, 0.8, 1.7, 40.0])
+@pytest.mark.parametrize("N,P", [(1, 4), (1000, 4), (65536, 1024), (2_000_000, 1280)])
+def test_library_fac_prob_tables_equal_oracle(si, cv, N, P):
+    """Probabilistic factoring: the library's table (cv passed in the
+    divisor slot) equals the oracle's, with and without a minimum chunk."""
+    for mc in (0, 3):
+        got = si.si_chunk_table("fac_prob", N, P, mc, cv)
+        exp = och.starts(och.fac_prob_sizes(N, P, cv, min_chunk=max(1, mc)))
+        np.testing.assert_array_equal(got, exp)
+
+
+def test_library_tss_min_chunk_equals_oracle(si):
+    for mc in (2, 7):
+        got = si.si_chunk_table("tss", 12345, 64, mc)
+        np.testing.assert_array_equal(got, och.starts(och.tss_sizes(12345, 64, min_chunk=mc)))
 
 
 def test_chunk_table_capacity_error(si):

@@ -119,3 +119,62 @@ def test_gss_overloads_first_requester():
     assert int(np.argmax(fin)) == 0
     fin_fac = ch.simulate(costs, ch.sizes(ch.FAC, N, P), P)
     assert fin.max() > fin_fac.max()
+
+
+@pytest.mark.parametrize("N", [1, 10, 1000, 65536, 2_000_000])
+@pytest.mark.parametrize("P", [1, 4, 1280])
+def test_fac_prob_reduces_to_static_and_ss(N, P):
+    """Probabilistic factoring's limits: with no cost variation (cv = 0) the
+    whole loop goes out in one batch of P chunks of ceil(N/P) (STATIC's
+    blocks when P divides N); with unbounded variation every chunk is one
+    iteration (SS)."""
+    z = ch.fac_prob_sizes(N, P, 0.0)
+    c = math.ceil(N / P)
+    assert sum(z) == N and len(z) <= P and all(k == c for k in z[:-1])
+    if N % P == 0:
+        assert z == ch.static_sizes(N, P)
+    if N <= 65536:
+        assert ch.fac_prob_sizes(N, P, 1e30) == [1] * N
+
+
+@pytest.mark.parametrize("N,P", [(1000, 4), (65536, 64), (2_000_000, 1280), (99991, 768)])
+def test_fac_prob_invariants(N, P):
+    """Batches of P equal chunks; chunk sizes never grow; after the first
+    batch no chunk exceeds FAC2's for the same remaining work (x_j >= 2); more
+    variation never enlarges the first chunk."""
+    firsts = []
+    for cv in (0.0, 0.1, 0.5, 1.0, 2.0, 8.0):
+        f = ch.fac_prob_sizes(N, P, cv)
+        assert sum(f) == N
+        batches = [f[i:i + P] for i in range(0, len(f), P)]
+        for b in batches[:-1]:
+            assert len(set(b)) == 1
+        assert all(a >= b for a, b in zip(f, f[1:]))
+        R = N - sum(batches[0])
+        for b in batches[1:]:
+            assert b[0] <= max(1, math.ceil(R / (2 * P)))
+            R -= sum(b)
+        firsts.append(f[0])
+    assert all(a >= b for a, b in zip(firsts, firsts[1:]))
+
+
+@pytest.mark.parametrize("N", [1, 7, 100, 1000, 65536, 100003])
+@pytest.mark.parametrize("P", [1, 3, 64, 1024])
+def test_tss_invariants(N, P):
+    """Trapezoid self-scheduling: the first chunk is ceil(N/(2P)), sizes fall
+    linearly (each step within one of the real step (F - L)/(C - 1)) until
+    the floor of one iteration or the clamped last chunk, within about
+    C = ceil(2N/(F + L)) chunks (the trapezoid's area is N); with P >= N/2
+    every chunk is one iteration (SS)."""
+    t = ch.tss_sizes(N, P)
+    F = max(1, math.ceil(N / (2 * P)))
+    C = math.ceil(2 * N / (F + 1))
+    d = (F - 1) / (C - 1) if C > 1 else 0.0
+    assert sum(t) == N and t[0] == min(F, N) and len(t) <= C + 1
+    body = t[:-1]
+    assert all(abs((a - b) - d) < 1.0 for a, b in zip(body, body[1:]) if b > 1)
+    assert all(k >= 1 for k in t) and all(a >= b for a, b in zip(body, body[1:]))
+    if 2 * P >= N:
+        assert t == [1] * N
+    if N >= 1000 and P == 64:                      # the sizes really fall
+        assert t[-2] < t[0]

@@ -60,7 +60,7 @@ def singles(si, torch, batch, sched):
     return res
 
 
-@pytest.mark.parametrize("kind", ["static", "ss", "gss", "fac"])
+@pytest.mark.parametrize("kind", ["static", "ss", "gss", "fac", "tss", "fac_prob"])
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_batched_equals_single(env, kind, use_graph):
     torch, si, _ = env

@@ -17,7 +17,7 @@ from tests import parity
 pytestmark = pytest.mark.gpu
 
 S60 = float(np.float32(math.pi / 3))
-SCHEDS = ["static", "ss", "gss", "fac"]
+SCHEDS = ["static", "ss", "gss", "fac", "tss", "fac_prob"]
 
 
 @pytest.fixture(scope="module")
@@ -101,7 +101,8 @@ def test_axis_law_gpu(env):
 @pytest.mark.parametrize("mode", ["bilinear", "ceil"])
 def test_prims_small_all_schedules(env, mode):
     """Uneven-density primitives recipe at 20,000 points, 4,000 images, cell
-    list: every image against the oracle, and the four schedules bit-identical."""
+    list: every image against the oracle, and the schedules bit-identical (the
+    paper's four, TSS and probabilistic factoring)."""
     print_case(f"prims 20k {mode}")
     _, _, oracle = env
     xyz, nrm = sg.config_scene("prims100k", M=20000)
@@ -123,6 +124,14 @@ def test_prims_small_all_schedules(env, mode):
     for kw in (dict(order="given"), dict(order="cell"), dict(group=1),
                dict(group=3, order="given"), dict(group=2, order="cell")):
         img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, mode, "fac", **kw)
+        np.testing.assert_array_equal(img, base[0])
+        np.testing.assert_array_equal(cnt, base[1])
+    # probabilistic factoring with cost variation, TSS with a minimum chunk
+    si = env[1]
+    for sched, kw in (("fac_prob", dict(fac_divisor=0.9)), ("fac_prob", dict(fac_divisor=7.5)),
+                      ("tss", dict(min_chunk=5))):
+        img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, mode, sched, num_workgroups=97, **kw)
+        assert st["sched_used"] == si.SCHED[sched]
         np.testing.assert_array_equal(img, base[0])
         np.testing.assert_array_equal(cnt, base[1])
 
