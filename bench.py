@@ -528,6 +528,35 @@ def main():
             if k.endswith("_cell"):
                 sched_res[k]["speedup_vs_static_cell"] = base_cell / sched_res[k]["call_ms"]["median"]
         si.si_generate(scene, idx, params, fac, images, counts)
+
+    # ---- heterogeneous workers, emulated (the paper's Section 5.2 setting) ----
+    hetero = None
+    if not args.no_schedules:
+        hetero = {"setting": "every 2nd workgroup 2x slower (it idles after each chunk for "
+                             "the chunk's own time); same images",
+                  "slowdown": 2.0, "every": 2}
+        try:
+            si.si_set_emulated_workers(2, 2.0)
+            for kind in ("static", "ss", "gss", "fac", "tss", "fac_prob", "learned"):
+                sch = si.Sched(kind, model=model if kind == "learned" else None,
+                               fac_divisor=cost_cv if kind == "fac_prob" else 0.0)
+                ks, ok = [], True
+                for r in range(2 + 5):
+                    _, _, s2 = si.si_generate(scene, idx, params, sch, images, counts, stats=True)
+                    ok = ok and bool(torch.equal(counts, ref_cnt))
+                    if r >= 2:
+                        ks.append(s2["kernel_ms"])
+                busy = s2["wg_busy_ns"].astype(np.float64)
+                hetero[kind] = {"kernel_ms": spread(ks), "counts_identical": ok,
+                                "imbalance": float(busy.max() / max(busy.mean(), 1.0))}
+        finally:
+            si.si_set_emulated_workers(0, 1.0)
+        for kind in ("static", "ss", "gss", "fac", "tss", "fac_prob", "learned"):
+            hetero[kind]["speedup_vs_static"] = (hetero["static"]["kernel_ms"]["median"] /
+                                                 hetero[kind]["kernel_ms"]["median"])
+        log("[bench] heterogeneous: " + ", ".join(
+            f"{k} {hetero[k]['kernel_ms']['median']:.2f} ms"
+            for k in ("static", "ss", "gss", "fac", "tss", "fac_prob", "learned")))
     torch.cuda.synchronize()
     del ref_img, ref_cnt
 
@@ -598,6 +627,7 @@ def main():
         "images_per_s": images_per_s,
         "generation_ms": gen_ms,
         "schedules": sched_res,
+        "heterogeneous_emulated": hetero,
         "cost_model": cm_info,
         "batched": batch,
         "paper_shape": paper,

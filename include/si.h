@@ -439,6 +439,18 @@ si_status si_learned_table(const float* unit_cost, int64_t n, int32_t P, float f
  */
 si_status si_set_kernel_events(void* begin_event, void* end_event);
 
+/*
+ * Host-only, for experiments on heterogeneous workers (Section 5.2 runs the
+ * techniques on a mix of faster and slower processors): from now on, on the
+ * calling thread, every `every`-th persistent workgroup of si_generate and
+ * si_generate_batched behaves as a worker `slowdown` times slower -- after
+ * each chunk it idles for (slowdown - 1) times that chunk's own time.  Work
+ * and images are unchanged; the launches use a separate build of the
+ * kernel.  every = 0 or slowdown = 1 turns it off.  Returns SI_E_INVALID for
+ * every < 0 or a slowdown below 1 or not finite.
+ */
+si_status si_set_emulated_workers(int32_t every, float slowdown);
+
 const char* si_status_string(si_status status);
 const char* si_last_error(void);
 int32_t si_abi_version(void);

@@ -26,7 +26,7 @@ __all__ = [
     "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
     "si_cost_model_predict_planner", "si_cost_model_gradient",
     "si_features_batched", "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
-    "si_set_kernel_events", "si_autotune", "si_peak_probe",
+    "si_set_kernel_events", "si_set_emulated_workers", "si_autotune", "si_peak_probe",
     "SCHED", "MODE", "PROBE",
 ]
 
@@ -118,6 +118,7 @@ def lib():
             "si_chunk_table": (I32, [I32, I64, I32, I32, F, P, I64, ctypes.POINTER(I64)]),
             "si_learned_table": (I32, [P, I64, I32, F, P, P, I64, ctypes.POINTER(I64)]),
             "si_set_kernel_events": (I32, [P, P]),
+            "si_set_emulated_workers": (I32, [I32, F]),
             "si_autotune": (I32, [ctypes.POINTER(c_batch_item), I32, I32, I32, I32, I32,
                                   ctypes.POINTER(c_sched), ctypes.POINTER(ctypes.c_double), P]),
             "si_status_string": (ctypes.c_char_p, [I32]),
@@ -154,6 +155,12 @@ def _dev_ptr(t: torch.Tensor, dtype, name: str, shape=None) -> ctypes.c_void_p:
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def si_set_emulated_workers(every: int, slowdown: float):
+    """Emulate heterogeneous workers on this thread: every ``every``-th
+    workgroup runs ``slowdown`` times slower (0 or 1.0 to stop)."""
+    _check(lib().si_set_emulated_workers(int(every), float(slowdown)))
 
 
 def si_set_kernel_events(begin, end):

@@ -279,6 +279,7 @@ si_status upload(const Flat& f, FlatMem& m, hipStream_t s) {
 LaunchDesc desc_of(const Flat& f, const FlatMem& m, uint32_t* counter, bool stats) {
     LaunchDesc d;
     memset(&d, 0, sizeof(d));
+    apply_emulated_workers(d);
     d.items = m.items;
     d.chunks = m.chunks;
     d.n_chunks = (int32_t)f.chunks.size();
@@ -412,6 +413,11 @@ std::string graph_key(const si_batch_item* items, int32_t n_items, const si_sche
     put(&sc.fallback_to_fac, sizeof(sc.fallback_to_fac));
     const char* lim = getenv("SI_TEST_OVERFLOW_LIMIT");
     k.append(lim ? lim : "-");
+    LaunchDesc emu;  // the calling thread's emulated-worker setting
+    memset(&emu, 0, sizeof(emu));
+    apply_emulated_workers(emu);
+    put(&emu.emu_every, sizeof(emu.emu_every));
+    put(&emu.emu_extra, sizeof(emu.emu_extra));
     for (int32_t i = 0; i < n_items; ++i) {
         const si_batch_item& b = items[i];
         put(&b.scene, sizeof(b.scene));

@@ -551,6 +551,9 @@ __device__ __forceinline__ void run_group_pass(const SceneView& sc, const SpinPa
 
 }  // namespace
 
+// EMU: the build that can emulate slower workers (si_set_emulated_workers);
+// the default build has none of that code.
+template <bool EMU>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) k_spin(LaunchDesc d) {
     extern __shared__ uint4 acc_lds[];
     uint32_t* acc = reinterpret_cast<uint32_t*>(acc_lds);
@@ -560,6 +563,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
     __shared__ int s_n_rows;
     __shared__ uint32_t s_cnt[kMaxGroup];
     __shared__ int s_step;
+    __shared__ unsigned long long s_t_chunk;  // EMU: when the chunk was claimed
     __shared__ WaveQueue s_q[kBlock / 64];
     // the row culling's partial runs live in the queues, which are empty
     // between candidate passes (barriers separate the two uses)
@@ -585,6 +589,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
                 step = local == 0 ? (int)blockIdx.x : n_chunks;
             }
             s_step = step;
+            if (EMU) s_t_chunk = wall_clock64();
         }
         ++local;
         __syncthreads();
@@ -791,6 +796,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
                 cur += ng;
             }
         }
+        // emulated heterogeneous workers: every emu_every-th workgroup idles
+        // after each chunk for emu_extra times the chunk's own time, so it
+        // runs (1 + emu_extra) times slower; its images do not change
+        if (EMU && d.emu_every > 0 && tid == 0 && blockIdx.x % (unsigned)d.emu_every == 0) {
+            const uint64_t t1 = wall_clock64();
+            const uint64_t until = t1 + (uint64_t)((float)(t1 - s_t_chunk) * d.emu_extra);
+            while (wall_clock64() < until) __builtin_amdgcn_s_sleep(4);
+        }
     }
 
     if (tid == 0) {
@@ -826,11 +839,11 @@ int spin_max_wg_per_cu(int max_w2, int group) {
     const size_t dyn = spin_lds_bytes(max_w2, group);
     int n = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &n, reinterpret_cast<const void*>(k_spin), kBlock, dyn);
+        &n, reinterpret_cast<const void*>(k_spin<false>), kBlock, dyn);
     if (e != hipSuccess || n < 1) n = 1;
     hipFuncAttributes fa;
     int dev = 0, cu_lds = 0;
-    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_spin)) == hipSuccess &&
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_spin<false>)) == hipSuccess &&
         hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
             hipSuccess &&
@@ -844,7 +857,10 @@ int spin_max_wg_per_cu(int max_w2, int group) {
 
 hipError_t launch_spin(const LaunchDesc& d, int n_wg, hipStream_t s) {
     const size_t lds = spin_lds_bytes(d.max_w2, d.group);
-    hipLaunchKernelGGL(k_spin, dim3(n_wg), dim3(kBlock), lds, s, d);
+    if (d.emu_every > 0)
+        hipLaunchKernelGGL(k_spin<true>, dim3(n_wg), dim3(kBlock), lds, s, d);
+    else
+        hipLaunchKernelGGL(k_spin<false>, dim3(n_wg), dim3(kBlock), lds, s, d);
     return hipGetLastError();
 }
 

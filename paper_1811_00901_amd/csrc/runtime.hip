@@ -52,6 +52,14 @@ void user_kernel_events(hipEvent_t* begin, hipEvent_t* end) {
     *end = g_ev_end;
 }
 
+static thread_local int32_t g_emu_every = 0;
+static thread_local float g_emu_slowdown = 1.0f;
+
+void apply_emulated_workers(LaunchDesc& d) {
+    d.emu_every = g_emu_every;
+    d.emu_extra = g_emu_slowdown - 1.0f;
+}
+
 // --------------------------------------------------------- device state --
 namespace {
 
@@ -870,6 +878,7 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
 
     LaunchDesc d;
     memset(&d, 0, sizeof(d));
+    apply_emulated_workers(d);
     d.single.scene = view_of(*scene);
     d.single.p = p;
     d.single.oriented = oriented_idx;
@@ -940,6 +949,14 @@ const char* si_status_string(si_status status) {
 }
 
 const char* si_last_error(void) { return g_last_error.c_str(); }
+
+si_status si_set_emulated_workers(int32_t every, float slowdown) {
+    if (every < 0) return fail(SI_E_INVALID, "every must be >= 0");
+    if (!isfinite(slowdown) || slowdown < 1.0f) return fail(SI_E_INVALID, "slowdown must be >= 1");
+    g_emu_every = slowdown > 1.0f ? every : 0;
+    g_emu_slowdown = slowdown;
+    return SI_OK;
+}
 
 si_status si_set_kernel_events(void* begin_event, void* end_event) {
     if ((begin_event == nullptr) != (end_event == nullptr))

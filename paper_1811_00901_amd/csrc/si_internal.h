@@ -118,6 +118,10 @@ struct LaunchDesc {
     uint32_t* stat_invalid;
     uint32_t* stat_overflow;
     unsigned long long* wg_ns;         // per workgroup busy time (may be null)
+    // emulated heterogeneous workers (si_set_emulated_workers): every
+    // emu_every-th workgroup (0 = none) runs 1 + emu_extra times slower
+    int32_t emu_every;
+    float emu_extra;
 };
 
 constexpr int kMaxGroup = 8;
@@ -183,6 +187,8 @@ si_status device_state(DeviceState** out);
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
 // events registered by si_set_kernel_events on this thread (or null)
 void user_kernel_events(hipEvent_t* begin, hipEvent_t* end);
+// this thread's si_set_emulated_workers setting, written into a launch
+void apply_emulated_workers(LaunchDesc& d);
 uint32_t* take_counter(DeviceState* st);
 si_status make_params(const si_params* prm, SpinParams* out, double* radius);
 si_status check_sched(const si_sched* sc);

@@ -109,3 +109,13 @@ def test_chunk_table_capacity_error(si):
     buf = np.zeros(3, dtype=np.int64)
     rc = lib.si_chunk_table(0, 10, 4, 0, 0.0, buf.ctypes.data, 3, ctypes.byref(n))
     assert rc == -1 and n.value == 4
+
+
+def test_emulated_workers_validation(si):
+    """The heterogeneous-worker emulation setting is host state: bad values
+    are rejected, and it can be set and cleared without a GPU."""
+    for every, slow in ((-1, 2.0), (2, 0.5), (2, float("nan")), (2, float("inf"))):
+        with pytest.raises(si.SiError):
+            si.si_set_emulated_workers(every, slow)
+    si.si_set_emulated_workers(2, 3.0)
+    si.si_set_emulated_workers(0, 1.0)

@@ -379,3 +379,38 @@ def test_spread_order_covers_every_image(env):
             assert torch.equal(img, ref) and torch.equal(cnt, rcnt), (N, kind)
             assert st["pairs_in_support"] == int(rcnt.to(torch.int64).sum()), (N, kind)
     scene.free()
+
+
+def test_emulated_heterogeneous_workers(env):
+    """Every second workgroup emulated 3x slower (si_set_emulated_workers):
+    images and counts are unchanged for STATIC and FAC; under STATIC the slow
+    workgroups are busy about three times as long as the others, and FAC,
+    which hands the slow ones less work, finishes first."""
+    print_case("emulated heterogeneous workers")
+    torch, si, _ = env
+    xyz, nrm = sg.config_scene("prims100k", M=60000)
+    params = si.Params(32, 0.02, S60)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(params))
+    idx = torch.arange(60000, dtype=torch.int32, device="cuda")
+    ref_img, ref_cnt, _ = si.si_generate(scene, idx, params, si.Sched("fac"))
+    ref_img, ref_cnt = ref_img.clone(), ref_cnt.clone()
+    res = {}
+    try:
+        si.si_set_emulated_workers(2, 3.0)
+        for kind in ("static", "fac"):
+            img, cnt, st = si.si_generate(scene, idx, params, si.Sched(kind, num_workgroups=256),
+                                          stats=True)
+            torch.cuda.synchronize()
+            assert torch.equal(img, ref_img) and torch.equal(cnt, ref_cnt), kind
+            res[kind] = st
+    finally:
+        si.si_set_emulated_workers(0, 1.0)
+    busy = res["static"]["wg_busy_ns"].astype(np.float64)
+    ratio = busy[0::2].mean() / busy[1::2].mean()
+    assert 2.4 < ratio < 3.6, ratio
+    assert res["fac"]["kernel_ms"] < res["static"]["kernel_ms"]
+    # the setting is off again: the default build runs
+    img, cnt, st = si.si_generate(scene, idx, params, si.Sched("static", num_workgroups=256),
+                                  stats=True)
+    b = st["wg_busy_ns"].astype(np.float64)
+    assert b[0::2].mean() / b[1::2].mean() < 1.5
