@@ -57,7 +57,7 @@ OPS_PER_SUPPORT_PAIR = 26
 ATOMICS_PER_SUPPORT_PAIR = 4
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz non-packed FP32/INT VALU
 # lane-operations per second (the 157.3 TFLOP/s figure counts an FMA as two
-# flops and needs packed dual FP32, which this build does not emit).
+# flops and needs packed dual FP32, which the library's kernels do not use).
 PEAK_VALU_OPS = 256 * 64 * 2.4e9
 
 
@@ -339,8 +339,9 @@ def paper_shape(torch, si, sg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the per-image loop would shard over GPUs as described in DESIGN.md)",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the per-image loop would shard over GPUs by ranges of images, each GPU "
+              "holding a copy of the scene)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -47,7 +47,7 @@ typedef enum si_status {
     SI_E_INVALID = -1,     /* an argument is out of its documented domain */
     SI_E_OOM = -2,         /* device or host allocation failed */
     SI_E_DEVICE = -3,      /* a HIP runtime call failed */
-    SI_E_UNSUPPORTED = -4  /* valid request this build does not implement */
+    SI_E_UNSUPPORTED = -4  /* valid request the library does not implement */
 } si_status;
 
 /* Loop-scheduling techniques (Section 2.2) plus the learned schedule. */
