@@ -606,8 +606,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
         const int w2 = W * W;
         // images per group: keep the LDS footprint of the launch (group x
         // max_w2); items of a smaller W take more images, at most
-        // max(group, 4) (more would not fit the scalar registers)
-        const int G_item = min(max(d.group, 4),
+        // max(group, 4) (the 8-image pass spills scalar registers, which
+        // pays only for W <= 16 images, whose groups have few candidates
+        // and whose per-group work dominates: those take up to 8)
+        const int G_item = min(w2 <= 256 ? kMaxGroup : max(d.group, 4),
                                min(kMaxGroup, max(1, (d.group * (d.max_w2 + 4)) / (w2 + 4))));
         // cells a group may span per axis beyond the first, and rows available
         const int span_lim = max(0, min(1, 7 - 2 * p.reach));
