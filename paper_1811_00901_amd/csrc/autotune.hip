@@ -193,7 +193,7 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
     // (a batch runs one launch per image-size class), FAC2
     base.group = 0;
     base.num_workgroups = 0;
-    base.fac_divisor = (kind == SI_SCHED_FAC || kind == SI_SCHED_LEARNED) ? 2.0f : 0.0f;
+    base.fac_divisor = 0.0f;  // the library's default ratio for the launch
 
     unsigned long long* dsum = nullptr;
     SI_HIP(hipMalloc(&dsum, 16));

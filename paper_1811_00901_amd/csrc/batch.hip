@@ -220,7 +220,15 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, const std::vec
         for (int k = 0; k < 3; ++k) f.sat_pass[k] = f.sat_off[(k + 1) * n1 - 1];
         f.divisor = sched->fac_divisor;
     } else {
-        flat_chunks(f, sched->min_chunk, sched->fac_divisor);
+        // FAC's default ratio: x = 2 (FAC2) assumes iterations of similar
+        // cost, as in one spread-ordered scene; a concatenation of several
+        // scenes (other widths, densities and sizes) varies much more, and
+        // factoring's batch ratio grows with the cost variation, so a launch
+        // over several items takes x = 4 unless the caller sets one
+        const float dv = sched->fac_divisor > 0.0f ? sched->fac_divisor
+                         : (f.kind == SI_SCHED_FAC && f.items.size() > 1) ? 4.0f
+                                                                           : 0.0f;
+        flat_chunks(f, sched->min_chunk, dv);
     }
     return SI_OK;
 }
