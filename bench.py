@@ -291,14 +291,14 @@ def cpu_schedules(oracle, sg, threads, n_images):
            "threads": threads}
     # a warm-up call touches every point on every thread
     oracle.generate(xyz, nrm, idx[:threads], pcfg.W, B, pcfg.support_angle, want_touch=False,
-                    schedule="static")
+                    schedule="static", nthreads=threads)
     best = {}
     for _ in range(2):
         for name in ("static", "ss", "gss", "fac"):
             sch = och.starts(och.fac_sizes(n, threads)) if name == "fac" else name
             t = time.perf_counter()
             oracle.generate(xyz, nrm, idx, pcfg.W, B, pcfg.support_angle, want_touch=False,
-                            schedule=sch)
+                            schedule=sch, nthreads=threads)
             best[name] = min(best.get(name, float("inf")), time.perf_counter() - t)
     for name in ("static", "ss", "gss", "fac"):
         out[name] = {"s": best[name], "pair_tests_per_s": n * M / best[name],
@@ -602,6 +602,16 @@ def main():
                "sample": f"{done} seeded-random images of {cfg.name} (brute force over all {M} "
                          f"points each, FP64), {dt:.1f} s",
                "images_per_s": done / dt}
+        # one thread on the 2,000-point sphere workload (all 2,000 images, brute force)
+        c1 = sg.CONFIGS["sphere2k"]
+        sxyz, snrm = sg.config_scene("sphere2k")
+        t = time.perf_counter()
+        r1 = oracle.generate(sxyz, snrm, np.arange(c1.N, dtype=np.int32), c1.W, c1.bin,
+                             c1.support_angle, want_touch=False, nthreads=1)
+        el = time.perf_counter() - t
+        cpu["single_thread_sphere2k"] = {
+            "pairs_per_s": float((r1["cnt_sure"].sum() + r1["cnt_amb"].sum()) / el),
+            "pair_tests_per_s": c1.N * sxyz.shape[0] / el, "s": el, "threads": 1}
         if args.cpu_sched_images > 0:
             cpu["schedules"] = cpu_schedules(oracle, sg, threads, args.cpu_sched_images)
             log("[bench] cpu schedules: " + ", ".join(
