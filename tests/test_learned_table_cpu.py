@@ -55,3 +55,33 @@ def test_partition_and_descending_keys(si):
     keys = np.floor(np.log2(np.maximum(np.rint(costs), 1)) * 32)[perm]
     assert np.all(np.diff(keys) <= 0)
     assert st[0] == 0 and st[-1] == 5000 and np.all(np.diff(st) > 0)
+
+
+from hypothesis import given, settings                      # noqa: E402
+from hypothesis import strategies as st_                    # noqa: E402
+
+
+@settings(max_examples=150, deadline=None)
+@given(n=st_.integers(min_value=1, max_value=3000),
+       P=st_.integers(min_value=1, max_value=2048),
+       x=st_.floats(min_value=1.0, max_value=6.0, allow_nan=False, width=32),
+       seed=st_.integers(min_value=0, max_value=2**31 - 1),
+       spread=st_.floats(min_value=0.0, max_value=12.0, allow_nan=False))
+def test_learned_table_properties(si, n, P, x, seed, spread):
+    """For random unit costs: the order is a permutation, sorted by the cost
+    key (32 buckets per octave) from the largest down and stable inside a
+    key; the chunk starts partition it into non-empty chunks."""
+    costs = np.exp(np.random.default_rng(seed).uniform(0.0, spread, size=n))
+    perm, st = si.si_learned_table(costs, P, x)
+    perm = np.asarray(perm)
+    assert sorted(perm.tolist()) == list(range(n))
+    # the key in double precision; the library takes log2 in single
+    # precision, so costs within 1e-3 of a bucket edge may fall either way
+    v = (np.log2(np.maximum(np.rint(costs.astype(np.float32)), 1)) * 32)[perm]
+    keys = np.floor(v)
+    edge = np.abs(v - np.rint(v)) < 1e-3
+    clear = ~(edge[:-1] | edge[1:])
+    assert np.all(np.diff(keys)[clear] <= 0)
+    same = (np.diff(keys) == 0) & clear
+    assert np.all(np.diff(perm)[same] > 0)                  # stable inside a key
+    assert st[0] == 0 and st[-1] == n and np.all(np.diff(st) > 0)
