@@ -301,8 +301,12 @@ typedef struct si_batch_item {
  * item.  Items with N == 0 are skipped.  Without a graph the call stages its
  * tables and synchronises the stream once before launching; the first call
  * with a new item list in graph mode also synchronises (capture).  The graph
- * cache holds up to 8 item lists per process; entries hold device pointers of
- * the scenes and buffers they were built for, so a replay needs them alive.
+ * cache holds up to 8 item lists per process.  An entry is keyed on the
+ * scenes' and cost model's identities (serial numbers that are never reused,
+ * not their addresses) and on the index and output pointers; it holds those
+ * buffers' device pointers, so a replay needs them alive.  si_free_scene and
+ * si_free_cost_model drop every entry built for the freed object, so a scene
+ * or model created later at the same address gets a graph of its own.
  */
 si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
                               const si_sched* sched, int32_t use_graph,

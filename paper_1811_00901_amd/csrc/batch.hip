@@ -386,6 +386,7 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     uint64_t last_use = 0;
+    std::vector<uint64_t> serials;  // scenes and cost model the graph reads
 };
 
 std::mutex g_graph_mu;
@@ -403,6 +404,28 @@ void free_entry(GraphEntry* e) {
     delete e;
 }
 
+}  // namespace
+
+void drop_graphs_of(uint64_t serial) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    bool synced = false;
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+        const std::vector<uint64_t>& v = it->second->serials;
+        if (std::find(v.begin(), v.end(), serial) == v.end()) {
+            ++it;
+            continue;
+        }
+        if (!synced) {  // a replay may still be queued
+            (void)hipDeviceSynchronize();
+            synced = true;
+        }
+        free_entry(it->second);
+        it = g_graphs.erase(it);
+    }
+}
+
+namespace {
+
 std::string graph_key(const si_batch_item* items, int32_t n_items, const si_sched* sched,
                       bool stats, int dev) {
     std::string k;
@@ -417,7 +440,10 @@ std::string graph_key(const si_batch_item* items, int32_t n_items, const si_sche
     put(&sc.fac_divisor, sizeof(sc.fac_divisor));
     put(&sc.group, sizeof(sc.group));
     put(&sc.order, sizeof(sc.order));
-    put(&sc.model, sizeof(sc.model));
+    // objects by serial, not by address: a freed scene's or model's handle
+    // and device memory can be handed out again to a new one
+    const uint64_t mser = model_serial(sc.model);
+    put(&mser, sizeof(mser));
     put(&sc.fallback_to_fac, sizeof(sc.fallback_to_fac));
     const char* lim = getenv("SI_TEST_OVERFLOW_LIMIT");
     k.append(lim ? lim : "-");
@@ -428,11 +454,8 @@ std::string graph_key(const si_batch_item* items, int32_t n_items, const si_sche
     put(&emu.emu_extra, sizeof(emu.emu_extra));
     for (int32_t i = 0; i < n_items; ++i) {
         const si_batch_item& b = items[i];
-        put(&b.scene, sizeof(b.scene));
-        if (b.scene) {
-            put(&b.scene->pos, sizeof(b.scene->pos));
-            put(&b.scene->n_cells, sizeof(b.scene->n_cells));
-        }
+        const uint64_t ser = b.scene ? b.scene->serial : 0;
+        put(&ser, sizeof(ser));
         put(&b.oriented_idx, sizeof(b.oriented_idx));
         put(&b.N, sizeof(b.N));
         put(&b.params, sizeof(b.params));
@@ -581,8 +604,16 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
     if (!e) {
         rc = make_graph(st, items, n_items, sched, stats != nullptr, &e);
         if (rc != SI_OK) return rc;
+        for (int32_t i = 0; i < n_items; ++i)
+            if (items[i].scene) e->serials.push_back(items[i].scene->serial);
+        if (sched->model) e->serials.push_back(model_serial(sched->model));
         std::lock_guard<std::mutex> lk(g_graph_mu);
-        if (g_graphs.size() >= kMaxGraphs) {  // evict the least recently used entry
+        auto again = g_graphs.find(key);
+        if (again != g_graphs.end()) {  // another thread captured the same list meanwhile
+            (void)hipDeviceSynchronize();
+            free_entry(e);
+            e = again->second;
+        } else if (g_graphs.size() >= kMaxGraphs) {  // evict the least recently used entry
             auto victim = g_graphs.begin();
             for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
                 if (it->second->last_use < victim->second->last_use) victim = it;
@@ -590,7 +621,7 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
             free_entry(victim->second);
             g_graphs.erase(victim);
         }
-        g_graphs[key] = e;
+        if (again == g_graphs.end()) g_graphs[key] = e;
     }
     e->last_use = ++g_graph_clock;
     if (e->flats.empty()) {

@@ -27,6 +27,7 @@
 #include "si_internal.h"
 
 struct si_cost_model {
+    uint64_t serial = si::next_serial();
     int device = 0;
     uint64_t seed = 0;
     int64_t step = 0;        // Adam steps taken
@@ -1269,6 +1270,8 @@ hipError_t learned_multi_enqueue(const si_cost_model* model, const LearnedMulti&
     return hipGetLastError();
 }
 
+uint64_t model_serial(const si_cost_model* m) { return m ? m->serial : 0; }
+
 }  // namespace si
 
 using namespace si;
@@ -1316,6 +1319,7 @@ si_status si_cost_model_create(uint64_t seed, si_cost_model** out) {
 
 void si_free_cost_model(si_cost_model* m) {
     if (!m) return;
+    si::drop_graphs_of(m->serial);
     (void)hipFree(m->params);
     (void)hipFree(m->m);
     (void)hipFree(m->v);

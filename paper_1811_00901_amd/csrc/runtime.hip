@@ -640,6 +640,7 @@ void si_free_scene(si_scene* scene) {
     // synchronisation also covers the build's own kernels, which may still be
     // queued on a stream that does not synchronise with the null stream
     (void)hipDeviceSynchronize();
+    drop_graphs_of(scene->serial);  // graphs hold its grid and arrays by value
     free_scene_mem(scene, nullptr);
     delete scene;
 }

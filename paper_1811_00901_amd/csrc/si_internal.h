@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <map>
 #include <string>
 #include <tuple>
@@ -25,6 +26,20 @@ si_status hip_fail(hipError_t e, const char* what);
     } while (0)
 
 // ----------------------------------------------------------------- scene --
+// Process-wide serial numbers of scenes and cost models, never reused: a
+// freed object's address (host handle, pool memory) can come back for the
+// next one, its serial cannot, so caches keyed on serials never match a
+// later object.
+inline uint64_t next_serial() {
+    static std::atomic<uint64_t> counter{0};
+    return ++counter;
+}
+// Drop every cached batched-launch graph that was built for the scene or
+// cost model of this serial (called when the object is freed).
+void drop_graphs_of(uint64_t serial);
+// The serial of a cost model (0 for NULL).
+uint64_t model_serial(const si_cost_model* m);
+
 // Grid cells per support radius: cell edge h = R_max (1 + 2e-5) / kSub (odd,
 // so that the 3 x 3 x 3 coarse cells of the cost features are centred).
 constexpr int kSub = 3;
@@ -38,6 +53,7 @@ constexpr int kSpreadUnit = 8;
 constexpr int64_t kMaxCells = int64_t(1) << 25;
 
 struct Scene {
+    uint64_t serial = next_serial();
     int64_t M = 0;
     float4* pos = nullptr;       // sorted by cell: (x, y, z, bits(cell id))
     float4* nrm = nullptr;       // sorted by cell: (nx, ny, nz, bits(original index))

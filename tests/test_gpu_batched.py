@@ -299,3 +299,68 @@ def test_batch256_full_sampled(env):
         cnt = items[k][4][sel].cpu().numpy().view(np.uint32)
         ref_o = oracle.generate(xyz, nrm, sample, params.W, B, S60)
         parity.check(img, cnt, ref_o, 0, f"batch256 scene {k} (W={params.W}, M={M})")
+
+
+def test_graph_not_replayed_for_a_rebuilt_scene(env):
+    """A graph captured for a scene must not be replayed for a later scene
+    that reuses its handle or memory.  Scene A is generated through the graph
+    cache and freed; scene B (A's points translated by whole cells, so the
+    grid has the same dims and key count but another origin, and the pool
+    hands back the same memory) is generated into the same buffers with the
+    same item list.  B's images must equal si_generate's on B; a replay of
+    A's graph would cull B's rows with A's origin.  Then the same for a cost
+    model freed and re-created under the learned schedule."""
+    torch, si, _ = env
+    print("\n[case] graph cache after free + rebuild", flush=True)
+    W = 32
+    params = si.Params(W, B, S60)
+    radius = si.si_support_radius(params)
+    xyz, nrm = sg.batch_scene(4400, 3000)
+    N = 3000
+    idx = torch.arange(N, dtype=torch.int32, device="cuda")
+    img = torch.zeros((N, W, W), dtype=torch.float32, device="cuda")
+    cnt = torch.zeros((N,), dtype=torch.int32, device="cuda")
+    sa = si.si_build_scene(torch.from_numpy(xyz).cuda(), torch.from_numpy(nrm).cuda(), radius)
+    ia = sa.info
+    si.si_generate_batched([(sa, idx, params, img, cnt)], si.Sched("fac"), use_graph=True)
+    torch.cuda.synchronize()
+    img_a = img.clone()
+    sa.free()
+    shift = np.float32(5 * ia["cell_size"])
+    xyz_b = (xyz + np.array([shift, 0, 0], dtype=np.float32)).astype(np.float32)
+    # a different geometry too, so that stale candidate lists would show:
+    # mirror the normals of every other point
+    nrm_b = nrm.copy()
+    nrm_b[::2] *= -1
+    sb = si.si_build_scene(torch.from_numpy(xyz_b).cuda(), torch.from_numpy(nrm_b).cuda(), radius)
+    ib = sb.info
+    # both grids are the same shape: a stale replay would stay inside B's arrays
+    assert ib["dims"] == ia["dims"] and ib["n_cells"] == ia["n_cells"]
+    assert ib["origin"] != ia["origin"]
+    si.si_generate_batched([(sb, idx, params, img, cnt)], si.Sched("fac"), use_graph=True)
+    torch.cuda.synchronize()
+    ref_img, ref_cnt, _ = si.si_generate(sb, idx, params, si.Sched("fac"))
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref_img)
+    assert torch.equal(cnt, ref_cnt)
+    assert not torch.equal(img, img_a)
+
+    # learned schedule: a freed model's graph is dropped with it
+    feats = si.si_features(sb, idx, params)
+    m1 = si.si_cost_model_create(1)
+    si.si_cost_model_train(m1, feats, ref_cnt, epochs=2, batch=512, loss_curve=False)
+    si.si_generate_batched([(sb, idx, params, img, cnt)], si.Sched("learned", model=m1),
+                           use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref_img)
+    m1.free()
+    m2 = si.si_cost_model_create(2)
+    si.si_cost_model_train(m2, feats, ref_cnt, epochs=1, batch=512, loss_curve=False)
+    img.zero_()
+    si.si_generate_batched([(sb, idx, params, img, cnt)], si.Sched("learned", model=m2),
+                           use_graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref_img)
+    assert torch.equal(cnt, ref_cnt)
+    m2.free()
+    sb.free()
