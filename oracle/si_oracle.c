@@ -144,100 +144,132 @@ static int make_job(Job* jb, const float* xyz, const float* nrm, int64_t M,
     return 0;
 }
 
-/* The inner loop of Algorithm 1 for image i: P = OP[idx[i]] against all M points. */
-static void one_image(const Job* jb, int64_t i)
+/* One image's running state: P = (p, n), its image, touch counts and counts. */
+typedef struct {
+    double px, py, pz, nx, ny, nz;
+    double* img;
+    int32_t* tch;
+    int64_t sure, amb;
+} ImageAcc;
+
+static void image_begin(const Job* jb, int64_t i, ImageAcc* a)
+{
+    const int32_t W = jb->W;
+    a->img = jb->img_sure + (size_t)i * W * W;
+    a->tch = jb->touch ? jb->touch + (size_t)i * W * W : NULL;
+    memset(a->img, 0, sizeof(double) * (size_t)W * W);
+    if (a->tch)
+        memset(a->tch, 0, sizeof(int32_t) * (size_t)W * W);
+    a->sure = 0;
+    a->amb = 0;
+    const int64_t pi = jb->idx[i];
+    a->px = jb->xyz[3 * pi];
+    a->py = jb->xyz[3 * pi + 1];
+    a->pz = jb->xyz[3 * pi + 2];
+    a->nx = jb->nrm[3 * pi];
+    a->ny = jb->nrm[3 * pi + 1];
+    a->nz = jb->nrm[3 * pi + 2];
+}
+
+static void image_end(const Job* jb, int64_t i, const ImageAcc* a)
+{
+    jb->cnt_sure[i] = a->sure;
+    jb->cnt_amb[i] = a->amb;
+}
+
+/* The body of Algorithm 1's inner loop: the pair (P, X_j). */
+static inline void pair_update(const Job* jb, ImageAcc* a, int64_t j)
 {
     const float* xyz = jb->xyz;
     const float* nrm = jb->nrm;
-    const int64_t M = jb->M;
     const int32_t W = jb->W;
     const double eps = jb->eps, B = jb->B, cosS = jb->cosS, half = jb->half, WW = jb->WW;
     const double beta_hi = jb->beta_hi, beta_lo = jb->beta_lo, alpha_max = jb->alpha_max;
     const int vacuous = jb->vacuous;
     const int32_t mode = jb->mode;
-    double* img = jb->img_sure + (size_t)i * W * W;
-    int32_t* tch = jb->touch ? jb->touch + (size_t)i * W * W : NULL;
-    memset(img, 0, sizeof(double) * (size_t)W * W);
-    if (tch)
-        memset(tch, 0, sizeof(int32_t) * (size_t)W * W);
-    int64_t sure = 0, amb = 0;
+    double* img = a->img;
+    int32_t* tch = a->tch;
+    const double px = a->px, py = a->py, pz = a->pz;
+    const double nx = a->nx, ny = a->ny, nz = a->nz;
 
-    const int64_t pi = jb->idx[i];
-    const double px = xyz[3 * pi], py = xyz[3 * pi + 1], pz = xyz[3 * pi + 2];
-    const double nx = nrm[3 * pi], ny = nrm[3 * pi + 1], nz = nrm[3 * pi + 2];
+    const double qx = xyz[3 * j], qy = xyz[3 * j + 1], qz = xyz[3 * j + 2];
+    const double mx = nrm[3 * j], my = nrm[3 * j + 1], mz = nrm[3 * j + 2];
 
-    for (int64_t j = 0; j < M; ++j) {
-        const double qx = xyz[3 * j], qy = xyz[3 * j + 1], qz = xyz[3 * j + 2];
-        const double mx = nrm[3 * j], my = nrm[3 * j + 1], mz = nrm[3 * j + 2];
+    const double c = nx * mx + ny * my + nz * mz;
+    const double dx = qx - px, dy = qy - py, dz = qz - pz;
+    const double beta = nx * dx + ny * dy + nz * dz;
+    const double dd = dx * dx + dy * dy + dz * dz;
+    const double a2 = dd - beta * beta;
+    const double alpha = sqrt(a2 > 0.0 ? a2 : 0.0);
+    const double v = half - beta / B;
+    const double u = alpha / B;
 
-        const double c = nx * mx + ny * my + nz * mz;
-        const double dx = qx - px, dy = qy - py, dz = qz - pz;
-        const double beta = nx * dx + ny * dy + nz * dz;
-        const double dd = dx * dx + dy * dy + dz * dz;
-        const double a2 = dd - beta * beta;
-        const double alpha = sqrt(a2 > 0.0 ? a2 : 0.0);
-        const double v = half - beta / B;
-        const double u = alpha / B;
-
-        int ca = vacuous ? C_TRUE : cond(c >= cosS, c - cosS, eps);
-        int c1, c2, c3;
-        if (mode == SIO_CEIL) {
-            const double kk = ceil(v), ll = ceil(u);
-            c1 = cond(kk >= 0.0, beta - beta_hi, eps);      /* k >= 0 */
-            c2 = cond(kk < WW, beta - beta_lo, eps);        /* k < W  */
-            c3 = cond(ll >= 0.0 && ll < WW, alpha - alpha_max, eps);
-        } else {
-            c1 = cond(v >= 0.0, beta - beta_hi, eps);
-            c2 = cond(v < WW - 1.0, beta - beta_lo, eps);
-            c3 = cond(u < WW - 1.0, alpha - alpha_max, eps);
-        }
-        if (ca == C_FALSE || c1 == C_FALSE || c2 == C_FALSE || c3 == C_FALSE)
-            continue;
-        const int unsure = (ca == C_UNSURE) || (c1 == C_UNSURE) ||
-                           (c2 == C_UNSURE) || (c3 == C_UNSURE);
-
-        if (mode == SIO_CEIL) {
-            const long k = (long)ceil(v), l = (long)ceil(u);
-            if (unsure) {
-                ++amb;
-                touch_box(tch, W, k - 1, k + 1, l - 1, l + 1);
-                continue;
-            }
-            ++sure;
-            int row_unsure = 0, col_unsure = 0;
-            /* x == p (the self-pair, duplicate points) is exact in any
-               precision: beta = alpha = 0, never ambiguous */
-            if (eps > 0.0 && (dx != 0.0 || dy != 0.0 || dz != 0.0)) {
-                const double m = nearbyint(v);             /* nearest row edge */
-                row_unsure = fabs(beta - B * (half - m)) < eps;
-                const double q = nearbyint(u);             /* nearest column edge */
-                col_unsure = (q >= 1.0 && fabs(alpha - B * q) < eps) ||
-                             (a2 != 0.0 && fabs(a2) < 1e-6);
-            }
-            if (row_unsure || col_unsure) {
-                touch_box(tch, W, row_unsure ? k - 1 : k, row_unsure ? k + 1 : k,
-                          col_unsure ? l - 1 : l, col_unsure ? l + 1 : l);
-            } else {
-                img[k * W + l] += 1.0;
-            }
-        } else {
-            const double fi = floor(v), fj = floor(u);
-            if (unsure) {
-                ++amb;
-                touch_box(tch, W, (long)fi - 1, (long)fi + 2, (long)fj - 1, (long)fj + 2);
-                continue;
-            }
-            ++sure;
-            const long i0 = (long)fi, j0 = (long)fj;
-            const double a = v - fi, b = u - fj;
-            img[i0 * W + j0] += (1.0 - a) * (1.0 - b);
-            img[(i0 + 1) * W + j0] += a * (1.0 - b);
-            img[i0 * W + j0 + 1] += (1.0 - a) * b;
-            img[(i0 + 1) * W + j0 + 1] += a * b;
-        }
+    int ca = vacuous ? C_TRUE : cond(c >= cosS, c - cosS, eps);
+    int c1, c2, c3;
+    if (mode == SIO_CEIL) {
+        const double kk = ceil(v), ll = ceil(u);
+        c1 = cond(kk >= 0.0, beta - beta_hi, eps);      /* k >= 0 */
+        c2 = cond(kk < WW, beta - beta_lo, eps);        /* k < W  */
+        c3 = cond(ll >= 0.0 && ll < WW, alpha - alpha_max, eps);
+    } else {
+        c1 = cond(v >= 0.0, beta - beta_hi, eps);
+        c2 = cond(v < WW - 1.0, beta - beta_lo, eps);
+        c3 = cond(u < WW - 1.0, alpha - alpha_max, eps);
     }
-    jb->cnt_sure[i] = sure;
-    jb->cnt_amb[i] = amb;
+    if (ca == C_FALSE || c1 == C_FALSE || c2 == C_FALSE || c3 == C_FALSE)
+        return;
+    const int unsure = (ca == C_UNSURE) || (c1 == C_UNSURE) ||
+                       (c2 == C_UNSURE) || (c3 == C_UNSURE);
+
+    if (mode == SIO_CEIL) {
+        const long k = (long)ceil(v), l = (long)ceil(u);
+        if (unsure) {
+            ++a->amb;
+            touch_box(tch, W, k - 1, k + 1, l - 1, l + 1);
+            return;
+        }
+        ++a->sure;
+        int row_unsure = 0, col_unsure = 0;
+        /* x == p (the self-pair, duplicate points) is exact in any
+           precision: beta = alpha = 0, never ambiguous */
+        if (eps > 0.0 && (dx != 0.0 || dy != 0.0 || dz != 0.0)) {
+            const double m = nearbyint(v);             /* nearest row edge */
+            row_unsure = fabs(beta - B * (half - m)) < eps;
+            const double q = nearbyint(u);             /* nearest column edge */
+            col_unsure = (q >= 1.0 && fabs(alpha - B * q) < eps) ||
+                         (a2 != 0.0 && fabs(a2) < 1e-6);
+        }
+        if (row_unsure || col_unsure) {
+            touch_box(tch, W, row_unsure ? k - 1 : k, row_unsure ? k + 1 : k,
+                      col_unsure ? l - 1 : l, col_unsure ? l + 1 : l);
+        } else {
+            img[k * W + l] += 1.0;
+        }
+    } else {
+        const double fi = floor(v), fj = floor(u);
+        if (unsure) {
+            ++a->amb;
+            touch_box(tch, W, (long)fi - 1, (long)fi + 2, (long)fj - 1, (long)fj + 2);
+            return;
+        }
+        ++a->sure;
+        const long i0 = (long)fi, j0 = (long)fj;
+        const double wa = v - fi, wb = u - fj;
+        img[i0 * W + j0] += (1.0 - wa) * (1.0 - wb);
+        img[(i0 + 1) * W + j0] += wa * (1.0 - wb);
+        img[i0 * W + j0 + 1] += (1.0 - wa) * wb;
+        img[(i0 + 1) * W + j0 + 1] += wa * wb;
+    }
+}
+
+/* The inner loop of Algorithm 1 for image i: P = OP[idx[i]] against all M points. */
+static void one_image(const Job* jb, int64_t i)
+{
+    ImageAcc a;
+    image_begin(jb, i, &a);
+    for (int64_t j = 0; j < jb->M; ++j)
+        pair_update(jb, &a, j);
+    image_end(jb, i, &a);
 }
 
 /*
@@ -323,6 +355,143 @@ int sio_generate_sched(const float* xyz, const float* nrm, int64_t M,
     for (int64_t i = 0; i < N; ++i)
         one_image(&jb, i);
 #endif
+    return 0;
+}
+
+/*
+ * Grid-accelerated form of sio_generate, for scenes where brute force is too
+ * slow (millions of images): the same pair arithmetic (pair_update) applied
+ * to the points of the 7 x 7 x 7 block of grid cells around p's cell only.
+ * No pair outside that block can change the result:
+ *   - every pair that is surely in support, or flagged, has |x - p| below
+ *     R_c = sqrt(max(|beta_hi|, |beta_lo|)^2 + alpha_max^2) + 4 eps, because
+ *     beta must lie within eps of [beta_lo, beta_hi] and alpha within eps
+ *     below alpha_max (otherwise one extent condition is surely false);
+ *   - the cells are cubes of edge h >= (R_c (1 + 1e-6) + 1e-9) / 3 over the
+ *     bounding box of the finite points, so a point within R_c of p lies in
+ *     a cell at most three steps from p's along every axis;
+ *   - points with a non-finite coordinate are never in support and never
+ *     flagged (every comparison with NaN or an infinite distance is false),
+ *     and an image whose P is not finite is empty: both are left out.
+ * Counts, ambiguous counts and touch counts are therefore identical to
+ * sio_generate; image bins are the same sums taken in another order (cells
+ * in z, y, x order, points in index order within a cell), so they agree to
+ * FP64 rounding.  The grid is coarsened while it would exceed 2^26 cells.
+ * Returns -1 on invalid arguments, -2 when memory runs out.
+ */
+int sio_generate_grid(const float* xyz, const float* nrm, int64_t M,
+                      const int32_t* idx, int64_t N,
+                      int32_t W, float bin, float support_angle, int32_t mode,
+                      double eps, double* img_sure, int64_t* cnt_sure,
+                      int64_t* cnt_amb, int32_t* touch, int32_t nthreads)
+{
+    Job jb;
+    if (make_job(&jb, xyz, nrm, M, idx, N, W, bin, support_angle, mode, eps, img_sure,
+                 cnt_sure, cnt_amb, touch) != 0)
+        return -1;
+    const double bmax = fmax(fabs(jb.beta_hi), fabs(jb.beta_lo));
+    const double Rc = sqrt(bmax * bmax + jb.alpha_max * jb.alpha_max) + 4.0 * (eps > 0 ? eps : 0);
+    const int64_t reach = 3;
+    double h = (Rc * (1.0 + 1e-6) + 1e-9) / (double)reach;
+
+    /* bounding box of the finite points */
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t j = 0; j < M; ++j) {
+        const double x = xyz[3 * j], y = xyz[3 * j + 1], z = xyz[3 * j + 2];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z))
+            continue;
+        const double q[3] = {x, y, z};
+        for (int a = 0; a < 3; ++a) {
+            if (q[a] < lo[a]) lo[a] = q[a];
+            if (q[a] > hi[a]) hi[a] = q[a];
+        }
+    }
+    int any = lo[0] <= hi[0];
+    int64_t dims[3] = {1, 1, 1};
+    if (any) {
+        for (;;) {
+            double cells = 1.0;
+            for (int a = 0; a < 3; ++a) {
+                dims[a] = (int64_t)floor((hi[a] - lo[a]) / h) + 1;
+                cells *= (double)dims[a];
+            }
+            if (cells <= (double)(1 << 26))
+                break;
+            h *= cbrt(cells / (double)(1 << 26)) * 1.01;
+        }
+    }
+    const int64_t ncell = dims[0] * dims[1] * dims[2];
+    int64_t* cell_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)M);
+    int64_t* start = (int64_t*)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t* pts = (int64_t*)malloc(sizeof(int64_t) * (size_t)M);
+    if (!cell_of || !start || !pts) {
+        free(cell_of);
+        free(start);
+        free(pts);
+        return -2;
+    }
+    for (int64_t j = 0; j < M; ++j) {
+        const double q[3] = {xyz[3 * j], xyz[3 * j + 1], xyz[3 * j + 2]};
+        if (!any || !isfinite(q[0]) || !isfinite(q[1]) || !isfinite(q[2])) {
+            cell_of[j] = -1;
+            continue;
+        }
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = (int64_t)floor((q[a] - lo[a]) / h);
+            if (c[a] < 0) c[a] = 0;
+            if (c[a] > dims[a] - 1) c[a] = dims[a] - 1;
+        }
+        cell_of[j] = (c[2] * dims[1] + c[1]) * dims[0] + c[0];
+        start[cell_of[j] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncell; ++c)
+        start[c + 1] += start[c];
+    {
+        int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)ncell);
+        if (!fill) {
+            free(cell_of);
+            free(start);
+            free(pts);
+            return -2;
+        }
+        memcpy(fill, start, sizeof(int64_t) * (size_t)ncell);
+        for (int64_t j = 0; j < M; ++j)
+            if (cell_of[j] >= 0)
+                pts[fill[cell_of[j]]++] = j;
+        free(fill);
+    }
+    (void)nthreads;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t i = 0; i < N; ++i) {
+        ImageAcc acc;
+        image_begin(&jb, i, &acc);
+        const int64_t pc = cell_of[idx[i]];
+        if (pc >= 0) {
+            const int64_t cx = pc % dims[0], cy = (pc / dims[0]) % dims[1],
+                          cz = pc / (dims[0] * dims[1]);
+            for (int64_t z = cz - reach; z <= cz + reach; ++z) {
+                if (z < 0 || z >= dims[2]) continue;
+                for (int64_t y = cy - reach; y <= cy + reach; ++y) {
+                    if (y < 0 || y >= dims[1]) continue;
+                    for (int64_t x = cx - reach; x <= cx + reach; ++x) {
+                        if (x < 0 || x >= dims[0]) continue;
+                        const int64_t c = (z * dims[1] + y) * dims[0] + x;
+                        for (int64_t k = start[c]; k < start[c + 1]; ++k)
+                            pair_update(&jb, &acc, pts[k]);
+                    }
+                }
+            }
+        }
+        image_end(&jb, i, &acc);
+    }
+    free(cell_of);
+    free(start);
+    free(pts);
     return 0;
 }
 

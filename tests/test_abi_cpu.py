@@ -119,3 +119,15 @@ def test_emulated_workers_validation(si):
             si.si_set_emulated_workers(every, slow)
     si.si_set_emulated_workers(2, 3.0)
     si.si_set_emulated_workers(0, 1.0)
+
+
+def test_library_later_techniques_equal_hand_tables(si):
+    """The library's TSS and probabilistic-factoring tables equal the
+    hand-worked rows of tests/golden/chunk_tables.txt."""
+    from tests.test_chunks_oracle import DIVISOR, golden_tables
+    names = {"TSS": "tss", "FAC_PROB1": "fac_prob"}
+    rows = [r for r in golden_tables() if r[0] in names]
+    assert len(rows) >= 3
+    for kind, n, p, expect in rows:
+        got = si.si_chunk_table(names[kind], n, p, 0, DIVISOR.get(kind, 0.0))
+        np.testing.assert_array_equal(np.diff(got), expect, err_msg=f"{kind} {n} {p}")

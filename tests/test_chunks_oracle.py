@@ -15,7 +15,10 @@ import pytest
 from oracle import chunks as ch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KINDS = {"STATIC": ch.STATIC, "SS": ch.SS, "GSS": ch.GSS, "FAC2": ch.FAC}
+KINDS = {"STATIC": ch.STATIC, "SS": ch.SS, "GSS": ch.GSS, "FAC2": ch.FAC, "TSS": ch.TSS,
+         "FAC_PROB1": ch.FAC_PROB}
+# the divisor argument of each row's kind (FAC_PROB1: cv = sigma/mu = 1)
+DIVISOR = {"FAC_PROB1": 1.0}
 
 
 def golden_tables():
@@ -34,7 +37,7 @@ def golden_tables():
 @pytest.mark.parametrize("row", golden_tables(), ids=lambda r: f"{r[0]}-{r[1]}-{r[2]}")
 def test_hand_worked_tables(row):
     kind, n, p, expect = row
-    assert ch.sizes(KINDS[kind], n, p) == expect
+    assert ch.sizes(KINDS[kind], n, p, divisor=DIVISOR.get(kind, 2.0)) == expect
 
 
 @pytest.mark.parametrize("N", [1, 7, 100, 1000, 65536, 100003])

@@ -149,44 +149,97 @@ def test_cell_list_equals_brute_force(env):
     assert b[2]["pairs_tested"] < a[2]["pairs_tested"] / 5
 
 
-def test_prims100k_full_sampled(env):
-    """The full uneven-density workload (100k points, 65,536 images) in the
-    launch configuration of the benchmark; 1,200 sampled images against the
-    oracle; schedules bit-identical on all images."""
-    print_case("prims100k full")
+@pytest.mark.parametrize("mode", ["bilinear", "ceil"])
+def test_prims100k_full_vs_oracle(env, mode):
+    """The full uneven-density workload (100k points, the first 65,536
+    oriented) in the launch configuration of the benchmark: every image
+    against the FP64 oracle (brute force over all 100k points per image),
+    and every technique bit-identical on all images."""
+    print_case(f"prims100k full {mode}")
     _, _, oracle = env
+    m = 0 if mode == "bilinear" else 1
     xyz, nrm = sg.config_scene("prims100k")
     idx = np.arange(65536)
-    rng = np.random.default_rng(0)
-    sample = np.sort(rng.choice(65536, 1200, replace=False))
-    ref = oracle.generate(xyz, nrm, idx[sample], 32, 0.02, S60, mode=0)
+    ref = oracle.generate(xyz, nrm, idx, 32, 0.02, S60, mode=m)
     base = None
-    for sched in SCHEDS:
-        img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", sched)
+    for sched in (SCHEDS if mode == "bilinear" else ["fac", "gss", "static"]):
+        img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, mode, sched)
         if base is None:
-            info = parity.check(img[sample], cnt[sample], ref, 0, f"prims100k-{sched}")
-            print(info, st)
+            info = parity.check(img, cnt, ref, m, f"prims100k-{mode}-{sched}")
+            print(info, {k: v for k, v in st.items() if k != "wg_busy_ns"})
+            assert st["pairs_in_support"] == int(cnt.astype(np.int64).sum())
             base = (img, cnt)
         else:
             assert np.array_equal(img, base[0]), sched
             assert np.array_equal(cnt, base[1]), sched
 
 
-def test_clustered2m_sampled(env):
-    """The 2M-point clustered workload, every point oriented, FAC: 300 sampled
-    images against the oracle (brute force over all 2M points per image)."""
-    print_case("clustered2m sampled")
-    _, _, oracle = env
+@pytest.fixture(scope="module")
+def clustered2m():
     xyz, nrm = sg.config_scene("clustered2m")
+    return xyz, nrm
+
+
+def test_clustered2m_vs_oracle(env, clustered2m):
+    """The 2M-point clustered workload, every point oriented, in the
+    benchmark's launch configuration (FAC, library defaults):
+      * 10,000 sampled images against the FP64 oracle (brute force over all
+        2M points per image) in bilinear mode;
+      * the overflow statistic equals the number of images with 65,536 or
+        more in-support pairs;
+      * the learned schedule (a model trained on the logged counts) gives
+        the same image tensor bit for bit, all 2M images, so the oracle
+        sample covers it too;
+      * ceil mode: 2,000 sampled images against the oracle."""
+    print_case("clustered2m vs oracle")
+    torch, si, oracle = env
+    xyz, nrm = clustered2m
     N = xyz.shape[0]
-    idx = np.arange(N)
     rng = np.random.default_rng(1)
-    sample = np.sort(rng.choice(N, 300, replace=False))
-    img, cnt, st = run(env, xyz, nrm, idx, 32, 0.02, S60, "bilinear", "fac")
-    ref = oracle.generate(xyz, nrm, idx[sample], 32, 0.02, S60, mode=0)
-    info = parity.check(img[sample], cnt[sample], ref, 0, "clustered2m")
+    params = si.Params(32, 0.02, S60)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(params))
+    idx = torch.arange(N, dtype=torch.int32, device="cuda")
+    img, cnt, st = si.si_generate(scene, idx, params, si.Sched("fac"), stats=True)
+    torch.cuda.synchronize()
+    c_all = cnt.cpu().numpy().view(np.uint32)
+    assert st["pairs_in_support"] == int(c_all.astype(np.int64).sum())
+    assert st["n_overflow"] == int((c_all >= 65536).sum())
+    assert st["n_invalid"] == 0
+    sample = np.sort(rng.choice(N, 10_000, replace=False))
+    sel = torch.from_numpy(sample).cuda()
+    ref = oracle.generate(xyz, nrm, sample, 32, 0.02, S60, mode=0)
+    info = parity.check(img[sel].cpu().numpy(), c_all[sample], ref, 0, "clustered2m bilinear")
     print(info, {k: v for k, v in st.items() if k != "wg_busy_ns"})
-    assert st["n_overflow"] == 0 or st["n_overflow"] > 0
+    del ref
+    # learned schedule: the whole image tensor, bit for bit
+    feats = si.si_features(scene, idx, params)
+    model = si.si_cost_model_create(3)
+    tr = torch.from_numpy(rng.choice(N, 200_000, replace=False)).cuda()
+    si.si_cost_model_train(model, feats[tr].contiguous(), cnt[tr].contiguous(), epochs=2,
+                           lr=2e-3, batch=2048, loss_curve=False)
+    img2 = torch.full_like(img, -1.0)
+    cnt2 = torch.full_like(cnt, -1)
+    _, _, st2 = si.si_generate(scene, idx, params, si.Sched("learned", model=model), img2, cnt2,
+                               stats=True)
+    torch.cuda.synchronize()
+    assert st2["sched_used"] == si.SCHED["learned"]
+    assert st2["pairs_in_support"] == st["pairs_in_support"]
+    assert torch.equal(cnt2, cnt)
+    assert torch.equal(img2, img)
+    del img2, cnt2, img
+    # ceil mode
+    pc = si.Params(32, 0.02, S60, "ceil")
+    scene_c = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(pc))
+    img, cnt, st = si.si_generate(scene_c, idx, pc, si.Sched("fac"), stats=True)
+    torch.cuda.synchronize()
+    sample = np.sort(rng.choice(N, 2_000, replace=False))
+    sel = torch.from_numpy(sample).cuda()
+    ref = oracle.generate(xyz, nrm, sample, 32, 0.02, S60, mode=1)
+    info = parity.check(img[sel].cpu().numpy(), cnt[sel].cpu().numpy().view(np.uint32), ref, 1,
+                        "clustered2m ceil")
+    print(info)
+    scene.free()
+    scene_c.free()
 
 
 def test_edge_cases(env):
@@ -383,11 +436,12 @@ def test_spread_order_covers_every_image(env):
 
 def test_emulated_heterogeneous_workers(env):
     """Every second workgroup emulated 3x slower (si_set_emulated_workers):
-    images and counts are unchanged for STATIC and FAC; under STATIC the slow
+    images and counts are unchanged for STATIC and FAC (and 1,500 images of
+    the emulated build match the oracle); under STATIC the slow
     workgroups are busy about three times as long as the others, and FAC,
     which hands the slow ones less work, finishes first."""
     print_case("emulated heterogeneous workers")
-    torch, si, _ = env
+    torch, si, oracle = env
     xyz, nrm = sg.config_scene("prims100k", M=60000)
     params = si.Params(32, 0.02, S60)
     scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(params))
@@ -403,6 +457,12 @@ def test_emulated_heterogeneous_workers(env):
             torch.cuda.synchronize()
             assert torch.equal(img, ref_img) and torch.equal(cnt, ref_cnt), kind
             res[kind] = st
+            if kind == "static":   # the emulated build's own output, against the oracle
+                sample = np.sort(np.random.default_rng(6).choice(60000, 1500, replace=False))
+                ref = oracle.generate(xyz, nrm, sample, 32, 0.02, S60, mode=0)
+                sel = torch.from_numpy(sample).cuda()
+                parity.check(img[sel].cpu().numpy(), cnt[sel].cpu().numpy().view(np.uint32), ref,
+                             0, "emulated static")
     finally:
         si.si_set_emulated_workers(0, 1.0)
     busy = res["static"]["wg_busy_ns"].astype(np.float64)

@@ -99,3 +99,48 @@ def test_features_hand_pattern():
     exp = [math.log1p(1), math.log1p(5), math.log1p(4), math.log1p(5),
            1 / 15, -1 / 15, -8 / 15, -8 / 15, 8 / 15, 20 / 15, math.log1p(15), Rs / (S * h)]
     np.testing.assert_allclose(f[0], exp, rtol=1e-12, atol=1e-12)
+
+
+def golden_adam():
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    rows = []
+    with open(os.path.join(here, "golden", "adam_steps.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            head, tail = line.split(":")
+            name, theta0, lr = head.split()
+            gs, thetas = tail.split("|")
+            rows.append((name, float(theta0), float(lr), [float(t) for t in gs.split()],
+                         [float(t) for t in thetas.split()]))
+    return rows
+
+
+@pytest.mark.parametrize("row", golden_adam(), ids=lambda r: r[0])
+def test_adam_hand_worked_steps(row):
+    """adam_step against hand-derived steps: bias correction (constant
+    gradient moves by lr g/(|g|+eps) at every step), both moment decays
+    (a gradient whose size changes), and where eps enters (a gradient of
+    the size of eps)."""
+    _, theta0, lr, gs, expect = row
+    theta = np.array([theta0])
+    m = np.zeros(1)
+    v = np.zeros(1)
+    for t, (g, e) in enumerate(zip(gs, expect), start=1):
+        theta, m, v = mlp.adam_step(theta, np.array([g]), m, v, t, lr)
+        assert abs(theta[0] - e) <= 1e-12 * max(1.0, abs(e)), (t, theta[0], e)
+
+
+def test_adam_vector_steps_are_elementwise():
+    """A vector of the golden cases stepped at once equals the scalar runs."""
+    rows = [r for r in golden_adam() if len(r[3]) >= 2]
+    theta = np.array([r[1] for r in rows])
+    lr = np.array([r[2] for r in rows])
+    m = np.zeros(len(rows))
+    v = np.zeros(len(rows))
+    for t in (1, 2):
+        g = np.array([r[3][t - 1] for r in rows])
+        theta, m, v = mlp.adam_step(theta, g, m, v, t, lr)
+        np.testing.assert_allclose(theta, [r[4][t - 1] for r in rows], rtol=1e-12, atol=1e-14)

@@ -295,3 +295,64 @@ def test_scheduled_loop_rejects_bad_tables(oracle_mod):
     for bad in ([0, 5, 9], [1, 10], [0, 6, 4, 10]):     # short, not from 0, descending
         with pytest.raises(ValueError):
             oracle_mod.generate(xyz, nrm, idx, 8, 0.1, 1.0, schedule=np.array(bad))
+
+
+def _same_as_brute(oracle_mod, xyz, nrm, idx, W, B, S, mode, eps=1e-6):
+    a = oracle_mod.generate(xyz, nrm, idx, W, B, S, mode=mode, eps=eps)
+    b = oracle_mod.generate(xyz, nrm, idx, W, B, S, mode=mode, eps=eps, grid=True)
+    np.testing.assert_array_equal(a["cnt_sure"], b["cnt_sure"])
+    np.testing.assert_array_equal(a["cnt_amb"], b["cnt_amb"])
+    np.testing.assert_array_equal(a["touch"], b["touch"])
+    mass = np.maximum(a["img"].sum(axis=(1, 2)), 1.0)
+    assert np.all(np.abs(a["img"] - b["img"]) <= 1e-12 * mass[:, None, None])
+    if mode == 1:                      # ceil bins are integer sums: exact
+        np.testing.assert_array_equal(a["img"], b["img"])
+    return a
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_grid_oracle_equals_brute_force_sphere(oracle_mod, mode):
+    """The grid-accelerated oracle is the brute-force definition restricted
+    to cells that hold every pair that can count or be flagged: identical
+    counts, flags and touch counts, image bins equal to FP64 rounding.
+    2,000-point sphere, every image."""
+    xyz, nrm = sg.config_scene("sphere2k")
+    _same_as_brute(oracle_mod, xyz, nrm, np.arange(2000), 16, 0.05, S60, mode)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("eps", [1e-6, 3e-3])
+def test_grid_oracle_equals_brute_force_prims(oracle_mod, mode, eps):
+    """The 100k-point primitives scene, 6,000 images spread over it; with the
+    flag band widened to 3e-3 thousands of pairs are flagged, and the grid's
+    margin (which grows with the band) still catches every one."""
+    xyz, nrm = sg.config_scene("prims100k")
+    idx = np.random.default_rng(11).choice(100_000, 6000, replace=False)
+    a = _same_as_brute(oracle_mod, xyz, nrm, idx, 32, 0.02, S60, mode, eps=eps)
+    if eps > 1e-4:
+        assert a["cnt_amb"].sum() > 1000
+
+
+def test_grid_oracle_equals_brute_force_clustered(oracle_mod):
+    """The 2M-point clustered scene, 600 sampled images (brute force visits
+    all 2M points for each)."""
+    xyz, nrm = sg.config_scene("clustered2m")
+    idx = np.random.default_rng(12).choice(len(xyz), 600, replace=False)
+    _same_as_brute(oracle_mod, xyz, nrm, idx, 32, 0.02, S60, 0)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_grid_oracle_odd_cases(oracle_mod, mode):
+    """Non-finite points (never in support, never flagged), an oriented
+    point that is not finite (an empty image), duplicates, odd W, S >= pi and
+    S = 0, a scene whose extent is below one cell, and a W = 64 image."""
+    xyz, nrm = sg.uniform_box_scene(3000, seed=9, box=2.0)
+    xyz[5] = np.nan
+    xyz[9, 1] = np.inf
+    xyz[11] = xyz[12]
+    idx = np.array([0, 5, 9, 11, 12, 12, 40, 2999] + list(range(100, 400, 7)))
+    for W, B, S in [(5, 0.07, S60), (16, 0.03, 7.0), (16, 0.03, 0.0), (64, 0.01, S60)]:
+        a = _same_as_brute(oracle_mod, xyz, nrm, idx, W, B, S, mode)
+        assert a["cnt_sure"][1] == 0 and a["cnt_amb"][1] == 0 and not a["img"][1].any()
+    tiny, tn = sg.uniform_box_scene(200, seed=10, box=0.01)
+    _same_as_brute(oracle_mod, tiny, tn, np.arange(200), 8, 0.05, S60, mode)
