@@ -262,7 +262,11 @@ si_status si_support_radius(const si_params* params, float* radius);
  *   stats         host or NULL; when set the stream is synchronised
  * The images and counts do not depend on the schedule or on thread timing.
  * Returns SI_E_INVALID for bad params/schedule, a support radius above the
- * scene's max_support_radius, or (when stats is set) invalid indices.
+ * scene's max_support_radius, or (when stats is set) invalid indices.  An
+ * index outside [0, M) is found on the device: its image is zero, its count
+ * 0xFFFFFFFF, and the device's invalid-index flag is set, which
+ * si_device_errors reports (the call itself returns before the launch has
+ * run, so without stats it cannot).
  * N == 0 is a no-op returning SI_OK.
  */
 si_status si_generate(const si_scene* scene, const int32_t* oriented_idx, int64_t N,
@@ -458,6 +462,17 @@ si_status si_set_kernel_events(void* begin_event, void* end_event);
  * every < 0 or a slowdown below 1 or not finite.
  */
 si_status si_set_emulated_workers(int32_t every, float slowdown);
+
+/*
+ * The device-side error flag of the generation launches (Section 2.1's
+ * loop takes P = OP[i]; an index outside the scene has no image).  Waits for
+ * the work queued on hip_stream, then returns SI_E_INVALID if any generation
+ * launch (si_generate, si_generate_batched) on the
+ * current device met an oriented index outside [0, M) since the previous
+ * si_device_errors call, else SI_OK.  The flag is one per device, shared by
+ * all streams, and this call clears it.  Synchronises the stream.
+ */
+si_status si_device_errors(void* hip_stream);
 
 const char* si_status_string(si_status status);
 const char* si_last_error(void);

@@ -23,6 +23,7 @@ import torch
 __all__ = [
     "SiError", "Params", "Sched", "Scene", "CostModel", "lib",
     "si_build_scene", "si_build_scenes", "si_generate", "si_generate_batched", "si_features",
+    "si_device_errors",
     "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
     "si_cost_model_predict_planner", "si_cost_model_gradient",
     "si_features_batched", "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
@@ -101,6 +102,7 @@ def lib():
             "si_support_radius": (I32, [ctypes.POINTER(c_params), ctypes.POINTER(F)]),
             "si_generate": (I32, [P, P, I64, ctypes.POINTER(c_params), ctypes.POINTER(c_sched),
                                   P, P, ctypes.POINTER(c_stats), P]),
+            "si_device_errors": (I32, [P]),
             "si_generate_batched": (I32, [ctypes.POINTER(c_batch_item), I32, ctypes.POINTER(c_sched),
                                           I32, ctypes.POINTER(c_stats), P]),
             "si_features": (I32, [P, P, I64, ctypes.POINTER(c_params), P, P]),
@@ -332,6 +334,13 @@ def si_generate(scene: Scene, oriented_idx: torch.Tensor, params: Params, sched:
                            op, cp, ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc)
     return images_out, counts_out, (_stats_dict(st, busy) if st is not None else None)
+
+
+def si_device_errors(stream=None):
+    """Raise SiError(SI_E_INVALID) if a generation launch on the current
+    device met an oriented index outside [0, M) since the last check
+    (synchronises the stream; clears the device's flag)."""
+    _check(lib().si_device_errors(_stream(stream)))
 
 
 def _batch_array(items):

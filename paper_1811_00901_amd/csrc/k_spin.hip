@@ -30,6 +30,9 @@
 // with 64-bit LDS accumulators.
 #include "si_internal.h"
 
+#include <map>
+#include <mutex>
+
 namespace si {
 
 namespace {
@@ -812,6 +815,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
         if (d.stat_tested && my_tested) atomicAdd(d.stat_tested, my_tested);
         if (d.stat_support && my_support) atomicAdd(d.stat_support, my_support);
         if (d.stat_invalid && my_invalid) atomicAdd(d.stat_invalid, my_invalid);
+        if (d.err_flag && my_invalid) atomicOr(d.err_flag, 1u);
         if (d.stat_overflow && my_overflow) atomicAdd(d.stat_overflow, my_overflow);
         if (d.wg_ns) d.wg_ns[blockIdx.x] = (unsigned long long)(wall_clock64() - t_begin);
         if (d.dynamic) {
@@ -857,13 +861,65 @@ int spin_max_wg_per_cu(int max_w2, int group) {
     return n;
 }
 
+}  // namespace si
+
+// The sticky invalid-index flag, one copy per device: word 0 is set by any
+// generation launch that meets an oriented index outside [0, M); word 1
+// receives it when it is read and cleared.
+static __device__ uint32_t invalid_seen[2];
+
+namespace si {
+
+namespace {
+
+std::mutex g_flag_mu;
+std::map<int, uint32_t*> g_flag;  // device -> address of invalid_seen
+
+hipError_t invalid_flag(uint32_t** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_flag_mu);
+    auto it = g_flag.find(dev);
+    if (it == g_flag.end()) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(invalid_seen));
+        if (e != hipSuccess) return e;
+        it = g_flag.emplace(dev, static_cast<uint32_t*>(p)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
+__global__ void k_take_flag(uint32_t* f) {
+    if (threadIdx.x == 0) f[1] = atomicExch(f, 0u);
+}
+
+}  // namespace
+
 hipError_t launch_spin(const LaunchDesc& d, int n_wg, hipStream_t s) {
-    const size_t lds = spin_lds_bytes(d.max_w2, d.group);
-    if (d.emu_every > 0)
-        hipLaunchKernelGGL(k_spin<true>, dim3(n_wg), dim3(kBlock), lds, s, d);
+    LaunchDesc dd = d;
+    if (!dd.err_flag) {
+        const hipError_t e = invalid_flag(&dd.err_flag);
+        if (e != hipSuccess) return e;
+    }
+    const size_t lds = spin_lds_bytes(dd.max_w2, dd.group);
+    if (dd.emu_every > 0)
+        hipLaunchKernelGGL(k_spin<true>, dim3(n_wg), dim3(kBlock), lds, s, dd);
     else
-        hipLaunchKernelGGL(k_spin<false>, dim3(n_wg), dim3(kBlock), lds, s, d);
+        hipLaunchKernelGGL(k_spin<false>, dim3(n_wg), dim3(kBlock), lds, s, dd);
     return hipGetLastError();
+}
+
+hipError_t take_invalid_flag(hipStream_t s, uint32_t* seen) {
+    uint32_t* f = nullptr;
+    hipError_t e = invalid_flag(&f);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_take_flag, dim3(1), dim3(64), 0, s, f);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(seen, f + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
 }
 
 }  // namespace si

@@ -61,6 +61,8 @@ void apply_emulated_workers(LaunchDesc& d) {
 }
 
 // --------------------------------------------------------- device state --
+}  // namespace si
+
 namespace {
 
 constexpr int kCounterSlots = 64;
@@ -68,9 +70,17 @@ constexpr int kCounterStride = 32;  // u32 words between slots (128 bytes)
 
 }  // namespace
 
+// Work-counter slots of the generation launches, one copy per device (zero
+// when the code object is loaded; each launch leaves its slot at zero).
+static __device__ __align__(256) uint32_t work_counters[kCounterSlots * kCounterStride];
+
+namespace si {
+
 static std::mutex g_mu;
 static std::map<int, DeviceState> g_dev;
 
+// Set-up of a device: attributes and the address of its counter slots; no
+// allocation, no synchronisation and no stream work.
 si_status device_state(DeviceState** out) {
     int dev = 0;
     SI_HIP(hipGetDevice(&dev));
@@ -91,9 +101,9 @@ si_status device_state(DeviceState** out) {
             uint64_t keep = UINT64_MAX;  // stream-ordered temporaries stay cached
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
         }
-        SI_HIP(hipMalloc(&st.counters, sizeof(uint32_t) * kCounterSlots * kCounterStride));
-        SI_HIP(hipMemset(st.counters, 0, sizeof(uint32_t) * kCounterSlots * kCounterStride));
-        SI_HIP(hipDeviceSynchronize());
+        void* slots = nullptr;
+        SI_HIP(hipGetSymbolAddress(&slots, HIP_SYMBOL(work_counters)));
+        st.counters = static_cast<uint32_t*>(slots);
         st.ready = true;
     }
     *out = &st;
@@ -968,5 +978,14 @@ si_status si_set_kernel_events(void* begin_event, void* end_event) {
 }
 
 int32_t si_abi_version(void) { return SI_ABI_VERSION; }
+
+si_status si_device_errors(void* hip_stream) {
+    uint32_t seen = 0;
+    SI_HIP(take_invalid_flag((hipStream_t)hip_stream, &seen));
+    if (seen)
+        return fail(SI_E_INVALID,
+                    "a generation launch on this device met oriented_idx entries outside [0, M)");
+    return SI_OK;
+}
 
 }  // extern "C"

@@ -134,6 +134,9 @@ struct LaunchDesc {
     uint32_t* stat_invalid;
     uint32_t* stat_overflow;
     unsigned long long* wg_ns;         // per workgroup busy time (may be null)
+    // the device's sticky invalid-index flag (launch_spin fills it in): set
+    // to 1 by any launch that meets an oriented index outside [0, M)
+    uint32_t* err_flag;
     // emulated heterogeneous workers (si_set_emulated_workers): every
     // emu_every-th workgroup (0 = none) runs 1 + emu_extra times slower
     int32_t emu_every;
@@ -146,6 +149,9 @@ constexpr int kBlock = 256;
 // Dynamic LDS bytes a launch needs.
 size_t spin_lds_bytes(int max_w2, int group);
 hipError_t launch_spin(const LaunchDesc& d, int n_wg, hipStream_t s);
+// Read and clear the current device's sticky invalid-index flag after the
+// work queued on s (synchronises s); *seen = 1 if it was set.
+hipError_t take_invalid_flag(hipStream_t s, uint32_t* seen);
 int spin_max_wg_per_cu(int max_w2, int group);
 
 // Scene-building kernels.
@@ -187,7 +193,7 @@ struct DeviceState {
     int n_cu = 0;
     int wall_khz = 100000;
     int max_lds = 65536;           // bytes of LDS one workgroup may allocate
-    uint32_t* counters = nullptr;  // work-counter slots, zero between launches
+    uint32_t* counters = nullptr;  // work-counter slots (a static device array), zero between launches
     uint32_t next_slot = 0;
     // chunk-table cache: (kind, N, P, min_chunk, divisor bits) -> device table
     std::map<std::tuple<int, int64_t, int, int, uint32_t>, std::pair<Chunk*, int>> tables;

@@ -281,15 +281,27 @@ def test_nan_point_and_invalid_index(env):
     assert c[2] == 0 and np.all(img[2].cpu().numpy() == 0)
     ref = oracle.generate(xyz, nrm, idx, 16, 0.03, S60)
     parity.check(img.cpu().numpy(), c, ref, 0, "nan")
+    si.si_device_errors()  # valid indices so far: the device flag is clear
     bad = to_dev(torch, np.array([0, 300, -1, 3], np.int32))
     with pytest.raises(si.SiError) as e:
         si.si_generate(scene, bad, params, stats=True)
     assert e.value.status == -1
+    # the launch with statistics also set the device's flag
+    with pytest.raises(si.SiError) as e:
+        si.si_device_errors()
+    assert e.value.status == -1
+    si.si_device_errors()  # the check cleared it
+    # without statistics the call returns before the launch ran; the
+    # device's flag reports the bad indices afterwards
     img, cnt, _ = si.si_generate(scene, bad, params)
-    torch.cuda.synchronize()
+    with pytest.raises(si.SiError) as e:
+        si.si_device_errors()
+    assert e.value.status == -1
     c = cnt.cpu().numpy().view(np.uint32)
     assert c[1] == 0xFFFFFFFF and c[2] == 0xFFFFFFFF and c[0] != 0xFFFFFFFF
     assert np.all(img[1].cpu().numpy() == 0)
+    si.si_generate(scene, to_dev(torch, idx), params)
+    si.si_device_errors()
 
 
 def test_invalid_arguments(env):
