@@ -464,10 +464,39 @@ si_status si_set_kernel_events(void* begin_event, void* end_event);
 si_status si_set_emulated_workers(int32_t every, float slowdown);
 
 /*
+ * si_generate without allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and results as si_generate (images and
+ * counts identical to its for the same scene, indices, params and
+ * schedule), without statistics.  What si_generate allocates per call (the
+ * claim counter, the chunk table, the temporaries of the cell-sorted loop
+ * order) lives in one static device array of SI_NOALLOC_SCRATCH_BYTES that
+ * each device holds from the library's load until the process ends; the
+ * call allocates no device or pinned memory.
+ *   sched->kind  any fixed schedule; SI_SCHED_LEARNED returns
+ *                SI_E_UNSUPPORTED (its plan needs memory of its own)
+ * Scratch needed: 256 + 12 n_chunks bytes (each region rounded up to 256),
+ * plus 4 (3N + 2M + ceil(M / 2048) + 2) bytes when the loop is cell-ordered
+ * (sched->order SPREAD or CELL on a scene with more than one cell); a call
+ * needing more returns SI_E_INVALID and names the size.  With 64 MiB, a
+ * 2,000,000-point scene with all points oriented fits under every schedule,
+ * SS with one image per chunk included (64.0e6 bytes).
+ * Every call on a device reuses that device's array and leaves its contents
+ * behind: calls that overlap on one device (other streams, other threads)
+ * race and must not be issued.  The chunk table is computed on the host and
+ * copied from pageable memory with hipMemcpyAsync on hip_stream.  Invalid
+ * indices are reported by si_device_errors.
+ */
+#define SI_NOALLOC_SCRATCH_BYTES (64u << 20)
+si_status si_generate_noalloc(const si_scene* scene, const int32_t* oriented_idx, int64_t N,
+                              const si_params* params, const si_sched* sched,
+                              float* images_out, uint32_t* counts_out, void* hip_stream);
+
+/*
  * The device-side error flag of the generation launches (Section 2.1's
  * loop takes P = OP[i]; an index outside the scene has no image).  Waits for
  * the work queued on hip_stream, then returns SI_E_INVALID if any generation
- * launch (si_generate, si_generate_batched) on the
+ * launch (si_generate, si_generate_batched, si_generate_noalloc) on the
  * current device met an oriented index outside [0, M) since the previous
  * si_device_errors call, else SI_OK.  The flag is one per device, shared by
  * all streams, and this call clears it.  Synchronises the stream.

@@ -23,7 +23,7 @@ import torch
 __all__ = [
     "SiError", "Params", "Sched", "Scene", "CostModel", "lib",
     "si_build_scene", "si_build_scenes", "si_generate", "si_generate_batched", "si_features",
-    "si_device_errors",
+    "si_generate_noalloc", "si_device_errors",
     "si_cost_model_create", "si_cost_model_train", "si_cost_model_predict",
     "si_cost_model_predict_planner", "si_cost_model_gradient",
     "si_features_batched", "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
@@ -102,6 +102,8 @@ def lib():
             "si_support_radius": (I32, [ctypes.POINTER(c_params), ctypes.POINTER(F)]),
             "si_generate": (I32, [P, P, I64, ctypes.POINTER(c_params), ctypes.POINTER(c_sched),
                                   P, P, ctypes.POINTER(c_stats), P]),
+            "si_generate_noalloc": (I32, [P, P, I64, ctypes.POINTER(c_params),
+                                          ctypes.POINTER(c_sched), P, P, P]),
             "si_device_errors": (I32, [P]),
             "si_generate_batched": (I32, [ctypes.POINTER(c_batch_item), I32, ctypes.POINTER(c_sched),
                                           I32, ctypes.POINTER(c_stats), P]),
@@ -334,6 +336,25 @@ def si_generate(scene: Scene, oriented_idx: torch.Tensor, params: Params, sched:
                            op, cp, ctypes.byref(st) if st is not None else None, _stream(stream))
     _check(rc)
     return images_out, counts_out, (_stats_dict(st, busy) if st is not None else None)
+
+
+def si_generate_noalloc(scene: Scene, oriented_idx: torch.Tensor, params: Params,
+                        sched: Sched | None, images_out: torch.Tensor, counts_out: torch.Tensor,
+                        stream=None):
+    """si_generate into caller-given outputs without any allocation by the
+    library (its scratch is a static device array shared by every call on
+    the device: overlapping calls race).  No statistics; fixed schedules."""
+    sched = sched or Sched()
+    N = int(oriented_idx.shape[0])
+    W = int(params.W)
+    ip = _dev_ptr(oriented_idx, torch.int32, "oriented_idx", (N,)) if N else ctypes.c_void_p(0)
+    op = _dev_ptr(images_out, torch.float32, "images_out", (N, W, W)) if N else ctypes.c_void_p(0)
+    if counts_out.dtype not in (torch.int32, torch.uint32):
+        raise TypeError("counts_out must be int32 or uint32 storage")
+    cp = ctypes.c_void_p(counts_out.data_ptr()) if N else ctypes.c_void_p(0)
+    _check(lib().si_generate_noalloc(scene.handle, ip, N, ctypes.byref(params.c()),
+                                     ctypes.byref(sched.c()), op, cp, _stream(stream)))
+    return images_out, counts_out
 
 
 def si_device_errors(stream=None):
