@@ -59,7 +59,12 @@ enum {
     SI_SCHED_LEARNED = 4, /* cost-model order + cost-weighted factoring       */
     /* two later techniques of the family (the paper's future work) */
     SI_SCHED_TSS = 5,     /* trapezoid: sizes fall linearly from N/(2P) to 1  */
-    SI_SCHED_FAC_PROB = 6 /* probabilistic factoring from the cost's sigma/mu */
+    SI_SCHED_FAC_PROB = 6,/* probabilistic factoring from the cost's sigma/mu */
+    /* three whose chunk depends on the requesting workgroup, sized when it
+       claims (si_generate only; see si_sched) */
+    SI_SCHED_WF = 7,      /* weighted factoring: FAC2 batches x worker weight */
+    SI_SCHED_AWF = 8,     /* adaptive weighted factoring: weights measured    */
+    SI_SCHED_AF = 9       /* adaptive factoring: from measured mu, sigma      */
 };
 
 /* Binning of a pair into the image (see si_params). */
@@ -115,6 +120,31 @@ typedef struct si_params {
  *                   has ceil(F - i delta) iterations, F = ceil(N / (2P)),
  *                   delta = (F - L) / (C - 1) (real), C = ceil(2N / (F + L)),
  *                   never below L = max(1, min_chunk).
+ *                   SI_SCHED_WF, SI_SCHED_AWF, SI_SCHED_AF size each chunk
+ *                   when a workgroup claims it (a claim counter gives its
+ *                   batch, an atomic addition of the size its start):
+ *                   WF (Hummel, Schmidt, Uma and Wein 1996): claim r is in
+ *                   batch b = r / P, whose FAC2 chunk c_b (divisor x, as
+ *                   for FAC) is scaled by the workgroup's weight w
+ *                   (si_set_worker_weights; else the emulated speeds of
+ *                   si_set_emulated_workers; else 1), weights scaled to sum
+ *                   P: ceil(w c_b) iterations.  AWF (Banicescu, Velusamy and
+ *                   Devaprasad 2003, adapting after every chunk): WF with
+ *                   w_i = P r_i / sum_j r_j, r_i = sum_k k n_ik / sum_k k t_ik
+ *                   over workgroup i's completed chunks (the sum over the
+ *                   measured workgroups, scaled by P over their number; 1
+ *                   before a first chunk).  AF (Banicescu and Liu 2000):
+ *                   (D + 2TR - sqrt(D^2 + 4DTR)) / (2 mu_i) iterations for R
+ *                   left, D = sum sigma_j^2 / mu_j, T = 1 / sum 1 / mu_j, mu
+ *                   and sigma the mean and deviation of each workgroup's
+ *                   time per image (sampled per group of images; sums over
+ *                   the measured workgroups scaled to P); a first claim gets
+ *                   FAC2's first chunk.  Chunk sizes of these three depend
+ *                   on timing; images never do.  For these three,
+ *                   min_chunk 0 means 8 (one unit of the spread order:
+ *                   smaller chunks cannot share candidate passes between
+ *                   images).  They run in si_generate only
+ *                   (SI_E_UNSUPPORTED elsewhere).
  *   model           SI_SCHED_LEARNED only; trained cost model
  *   fallback_to_fac SI_SCHED_LEARNED without a model: 1 = run FAC, 0 = error
  *   group           images that share one pass over their common candidate
@@ -462,6 +492,52 @@ si_status si_set_kernel_events(void* begin_event, void* end_event);
  * every < 0 or a slowdown below 1 or not finite.
  */
 si_status si_set_emulated_workers(int32_t every, float slowdown);
+
+/*
+ * Host-only, from now on, on the calling thread: how the emulated slower
+ * workgroups of si_set_emulated_workers spend their extra time and which
+ * they are.
+ *   busy       0: sleeping, which leaves the compute unit to other
+ *              workgroups (the default); 1: every thread spinning on
+ *              arithmetic, which keeps the compute unit occupied, as a
+ *              slower processor would be.  The extra time is spent after
+ *              each group of images that shares a candidate pass.
+ *   placement  SI_EMU_EVERY (0): workgroups k with k mod every = 0 (the
+ *              default); SI_EMU_FIRST (1): the P / every workgroups whose
+ *              first chunk comes first in claim order; SI_EMU_LAST (2):
+ *              those whose first chunk comes last -- the order in which the
+ *              paper's slower processors first requested work (Section 5.2).
+ *              With FIRST or LAST, SI_SCHED_WF takes equal weights unless
+ *              si_set_worker_weights gives them.
+ * Returns SI_E_INVALID for other values.
+ */
+enum { SI_EMU_EVERY = 0, SI_EMU_FIRST = 1, SI_EMU_LAST = 2 };
+si_status si_set_emulated_mode(int32_t busy, int32_t placement);
+
+/*
+ * Host-only: relative speeds of the persistent workgroups for SI_SCHED_WF,
+ * from now on, on the calling thread: workgroup k takes weight
+ * weights[k mod n] (host array of n positive finite values; scaled so the
+ * launch's weights sum to its workgroup count).  n = 0 clears it (weights
+ * then come from si_set_emulated_workers, 1 / slowdown for the slow ones, or
+ * are all 1).  Returns SI_E_INVALID for n < 0, NULL with n > 0, or a weight
+ * that is not positive and finite.
+ */
+si_status si_set_worker_weights(const float* weights, int32_t n);
+
+/*
+ * Host-only, the chunk rules of SI_SCHED_WF / AWF / AF as the kernel
+ * evaluates them (the same code):
+ *   si_rule_wf_chunk   ceil(w base), in [max(1, min_chunk), remaining]
+ *   si_rule_awf_weight P rate / (rate_sum P / n_meas); 1 when unmeasured
+ *   si_rule_af_chunk   (D + 2TR - sqrt(D^2 + 4DTR)) / (2 mu) rounded up, in
+ *                      [max(1, min_chunk), R], with D and T from the sums
+ *                      var_over_mu_sum, inv_mu_sum over n_meas of P workers
+ */
+int64_t si_rule_wf_chunk(double w, int64_t base, int64_t remaining, int32_t min_chunk);
+double si_rule_awf_weight(double rate, double rate_sum, int32_t n_meas, int32_t P);
+int64_t si_rule_af_chunk(double var_over_mu_sum, double inv_mu_sum, int32_t n_meas, int32_t P,
+                         int64_t remaining, double mu, int32_t min_chunk);
 
 /*
  * si_generate without allocation, for callers that cannot allocate device

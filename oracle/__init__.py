@@ -11,8 +11,10 @@ Contents:
                          conservative cell neighbourhood (for millions of images);
   * ``numpy_ref``     -- an independent vectorised NumPy implementation of the
                          same definition for tiny scenes;
-  * ``chunks``        -- STATIC / SS / GSS / FAC chunk sizes (Section 2.2) and a
-                         discrete-event simulation of P self-scheduling workers;
+  * ``chunks``        -- STATIC / SS / GSS / FAC chunk sizes (Section 2.2), the
+                         later TSS / FAC_PROB / WF / AWF / AF rules, and
+                         discrete-event simulations of P self-scheduling workers
+                         (of different speeds for the worker-dependent rules);
   * ``mlp``           -- FP64 reference of the per-image cost model (features,
                          forward, backward, Adam).
 """

@@ -28,12 +28,16 @@ __all__ = [
     "si_cost_model_predict_planner", "si_cost_model_gradient",
     "si_features_batched", "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
     "si_set_kernel_events", "si_set_emulated_workers", "si_autotune", "si_peak_probe",
+    "si_set_emulated_mode", "si_set_worker_weights", "si_rule_wf_chunk", "si_rule_awf_weight",
+    "si_rule_af_chunk",
     "SCHED", "MODE", "PROBE",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libspinimg.so")
 
-SCHED = {"static": 0, "ss": 1, "gss": 2, "fac": 3, "learned": 4, "tss": 5, "fac_prob": 6}
+SCHED = {"static": 0, "ss": 1, "gss": 2, "fac": 3, "learned": 4, "tss": 5, "fac_prob": 6,
+         "wf": 7, "awf": 8, "af": 9}
+EMU_PLACE = {"every": 0, "first": 1, "last": 2}
 PROBE = {"valu": 0, "lds_atomic_seq": 1, "lds_atomic_random": 2, "hbm_copy": 3}
 MODE = {"bilinear": 0, "ceil": 1}
 ORDER = {"spread": 0, "given": 1, "cell": 2}
@@ -123,6 +127,12 @@ def lib():
             "si_learned_table": (I32, [P, I64, I32, F, P, P, I64, ctypes.POINTER(I64)]),
             "si_set_kernel_events": (I32, [P, P]),
             "si_set_emulated_workers": (I32, [I32, F]),
+            "si_set_emulated_mode": (I32, [I32, I32]),
+            "si_set_worker_weights": (I32, [P, I32]),
+            "si_rule_wf_chunk": (I64, [ctypes.c_double, I64, I64, I32]),
+            "si_rule_awf_weight": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, I32, I32]),
+            "si_rule_af_chunk": (I64, [ctypes.c_double, ctypes.c_double, I32, I32, I64,
+                                       ctypes.c_double, I32]),
             "si_autotune": (I32, [ctypes.POINTER(c_batch_item), I32, I32, I32, I32, I32,
                                   ctypes.POINTER(c_sched), ctypes.POINTER(ctypes.c_double), P]),
             "si_status_string": (ctypes.c_char_p, [I32]),
@@ -167,6 +177,36 @@ def si_set_emulated_workers(every: int, slowdown: float):
     _check(lib().si_set_emulated_workers(int(every), float(slowdown)))
 
 
+def si_set_emulated_mode(busy: bool = False, placement: str = "every"):
+    """How emulated slow workgroups spend their extra time (busy: spinning,
+    keeping the compute unit; else sleeping) and which they are ("every"
+    k-th by index, the "first" or the "last" to claim a chunk)."""
+    _check(lib().si_set_emulated_mode(1 if busy else 0, EMU_PLACE[placement]))
+
+
+def si_set_worker_weights(weights):
+    """Relative workgroup speeds for the "wf" schedule (None or [] clears)."""
+    if weights is None or len(weights) == 0:
+        _check(lib().si_set_worker_weights(None, 0))
+        return
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    _check(lib().si_set_worker_weights(w.ctypes.data_as(ctypes.c_void_p), int(w.size)))
+
+
+def si_rule_wf_chunk(w: float, base: int, remaining: int, min_chunk: int = 0) -> int:
+    return int(lib().si_rule_wf_chunk(float(w), int(base), int(remaining), int(min_chunk)))
+
+
+def si_rule_awf_weight(rate: float, rate_sum: float, n_meas: int, P: int) -> float:
+    return float(lib().si_rule_awf_weight(float(rate), float(rate_sum), int(n_meas), int(P)))
+
+
+def si_rule_af_chunk(var_over_mu_sum: float, inv_mu_sum: float, n_meas: int, P: int,
+                     remaining: int, mu: float, min_chunk: int = 0) -> int:
+    return int(lib().si_rule_af_chunk(float(var_over_mu_sum), float(inv_mu_sum), int(n_meas),
+                                      int(P), int(remaining), float(mu), int(min_chunk)))
+
+
 def si_set_kernel_events(begin, end):
     """Record torch.cuda.Event objects around every following spin-kernel
     launch on this thread (None, None to stop)."""
@@ -208,7 +248,7 @@ class Sched:
     kind: str = "fac"
     num_workgroups: int = 0
     min_chunk: int = 0
-    # FAC / LEARNED: the divisor x (0 = 2); "fac_prob": sigma / mu of the cost
+    # FAC / LEARNED / WF / AWF: the divisor x (0 = 2); "fac_prob": sigma / mu of the cost
     fac_divisor: float = 0.0
     model: "CostModel | None" = None
     fallback_to_fac: bool = True

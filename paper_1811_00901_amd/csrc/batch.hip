@@ -533,6 +533,8 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
                                          si_stats* stats, void* hip_stream) {
     if (n_items < 0 || (n_items > 0 && !items)) return fail(SI_E_INVALID, "bad item list");
     si_status rc = check_sched(sched);
+    if (rc == SI_OK && sched->kind >= SI_SCHED_WF)
+        return fail(SI_E_UNSUPPORTED, "SI_SCHED_WF, AWF and AF run in si_generate only");
     if (rc != SI_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
     DeviceState* st;

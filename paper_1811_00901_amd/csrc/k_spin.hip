@@ -29,6 +29,7 @@
 // whose in-support count reaches 65536 could wrap a 32-bit bin; it is redone
 // with 64-bit LDS accumulators.
 #include "si_internal.h"
+#include "adaptive.h"
 
 #include <map>
 #include <mutex>
@@ -566,7 +567,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
     __shared__ int s_n_rows;
     __shared__ uint32_t s_cnt[kMaxGroup];
     __shared__ int s_step;
-    __shared__ unsigned long long s_t_chunk;  // EMU: when the chunk was claimed
+    __shared__ int s_cs, s_ce;                   // EMU, worker-sized claims: the chunk
+    __shared__ unsigned long long s_until;       // EMU: end of an emulated slowdown
+    __shared__ int s_slow;                       // EMU: this workgroup is an emulated slow one
+    // EMU build, used by thread 0 only: when the current chunk and group
+    // began, the workgroup's measurements for AWF (sums over its chunks k of
+    // k n_k and k t_k, its rate) and AF (Welford sums of per-image times, and
+    // what it last added to the launch-wide sums), and its claims
+    __shared__ struct {
+        unsigned long long t_chunk, t_group;
+        double aw_a, aw_b, aw_rate;
+        double af_n, af_mean, af_m2, af_c1, af_c2;
+        int aw_k, af_meas;
+        uint32_t claims;
+        int first_claim;
+    } s_m;
     __shared__ WaveQueue s_q[kBlock / 64];
     // the row culling's partial runs live in the queues, which are empty
     // between candidate passes (barriers separate the two uses)
@@ -579,11 +594,61 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
     unsigned long long my_tested = 0, my_support = 0;
     uint32_t my_invalid = 0, my_overflow = 0;
     int local = 0;  // static: chunks this workgroup has taken
+    if (EMU && tid == 0) {
+        memset(&s_m, 0, sizeof(s_m));
+        s_slow = d.emu_every > 0 && d.emu_place == SI_EMU_EVERY &&
+                 blockIdx.x % (unsigned)d.emu_every == 0;
+    }
 
     for (;;) {
         if (tid == 0) {
             int step;
-            if (d.dynamic) {
+            if (EMU && d.rule) {
+                // claim sized by this workgroup (WF / AWF / AF): take a claim
+                // index (its batch, for WF and AWF), size the chunk, then
+                // advance the loop's next iteration by that size; a start at
+                // or past the end means the loop is done (no retries: every
+                // workgroup makes progress with two atomic additions)
+                uint32_t* next_it = d.counter + 2;
+                const int64_t N = d.single.N;
+                const int P = (int)gridDim.x;
+                const int64_t mc = d.min_chunk;
+                const uint32_t r = atomicAdd(d.counter, 1u);
+                const int64_t b = (int64_t)(r / (uint32_t)P);
+                const int64_t base = b < d.n_bases ? d.bases[b] : mc;
+                const int64_t nxt = (int64_t)__hip_atomic_load(next_it, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                const int64_t R = N - nxt;
+                int64_t k = 0;
+                if (R > 0) {
+                    if (d.rule == SI_SCHED_WF) {
+                        k = wf_chunk((double)d.weights[blockIdx.x], base, R, mc);
+                    } else {
+                        const double s0 = __hip_atomic_load(&d.adapt[0], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                        const double s1 = __hip_atomic_load(&d.adapt[1], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                        const int nm = (int)__hip_atomic_load(&d.adapt[2], __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                        if (d.rule == SI_SCHED_AWF) {
+                            k = wf_chunk(awf_weight(s_m.aw_rate, s0, nm, P), base, R, mc);
+                        } else if (s_m.af_meas && nm > 0 && s0 > 0.0) {
+                            double D, T;
+                            af_terms(s1, s0, nm, P, &D, &T);
+                            k = af_chunk(D, T, R, s_m.af_mean, mc);
+                        } else {
+                            k = clamp_chunk((double)d.bases[0], R, mc);
+                        }
+                    }
+                }
+                // R was read before the addition: the chunk is clamped to the end
+                const int64_t cs = k > 0 ? (int64_t)atomicAdd(next_it, (uint32_t)k) : N;
+                const int64_t ce = cs < N ? (cs + k < N ? cs + k : N) : N;
+                s_cs = (int)(cs < N ? cs : N);
+                s_ce = (int)ce;
+                step = cs < N ? 0 : n_chunks;
+                if (cs < N && s_m.claims++ == 0) s_m.first_claim = (int)r;
+            } else if (d.dynamic) {
                 step = (int)atomicAdd(d.counter, 1u);
             } else if (d.wg_first) {
                 step = d.wg_first[blockIdx.x] + local;
@@ -592,13 +657,32 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
                 step = local == 0 ? (int)blockIdx.x : n_chunks;
             }
             s_step = step;
-            if (EMU) s_t_chunk = wall_clock64();
+            if (EMU) {
+                s_m.t_chunk = s_m.t_group = wall_clock64();
+                if (local == 0 && d.emu_every > 0 && d.emu_place != SI_EMU_EVERY) {
+                    // slow by the place of this workgroup's first claim among
+                    // all claims (STATIC: its index); a workgroup that finds
+                    // the loop done claims nothing
+                    const int first = d.rule ? (int)(s_m.claims ? s_m.first_claim : 0x7fffffff)
+                                             : step;
+                    const int n_slow = (int)gridDim.x / d.emu_every;
+                    s_slow = d.emu_place == SI_EMU_FIRST ? first < n_slow
+                                                         : first >= (int)gridDim.x - n_slow;
+                }
+            }
         }
         ++local;
         __syncthreads();
         const int step = rfl(s_step);
         if (step >= n_chunks) break;
-        const Chunk ch = d.chunks[step];
+        Chunk ch;
+        if (EMU && d.rule) {
+            ch.item = 0;
+            ch.start = s_cs;
+            ch.end = s_ce;
+        } else {
+            ch = d.chunks[step];
+        }
         const int item_id = rfl(ch.item);
         const int c_start = rfl(ch.start);
         const int c_end = rfl(ch.end);
@@ -798,16 +882,68 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
                     }
                 }
                 __syncthreads();
+                if (EMU) {
+                    // emulated heterogeneous workers: every emu_every-th
+                    // workgroup, after each group, spends emu_extra times the
+                    // group's own time more, so it runs (1 + emu_extra) times
+                    // slower -- idling (its compute unit free for others) or
+                    // with every thread spinning on arithmetic (its compute
+                    // unit kept busy); its images do not change
+                    if (rfl(s_slow)) {
+                        if (tid == 0) {
+                            const uint64_t t1 = wall_clock64();
+                            s_until = t1 + (uint64_t)((float)(t1 - s_m.t_group) * d.emu_extra);
+                        }
+                        if (d.emu_busy) {
+                            __syncthreads();
+                            const uint64_t until = s_until;
+                            float v = (float)tid;
+                            while (wall_clock64() < until) {
+#pragma unroll
+                                for (int i = 0; i < 32; ++i) v = fmaf(v, 0.999f, 0.5f);
+                            }
+                            __asm__ volatile("" ::"v"(v));
+                        } else if (tid == 0) {
+                            const uint64_t until = s_until;
+                            while (wall_clock64() < until) __builtin_amdgcn_s_sleep(4);
+                        }
+                    }
+                    // AF: the group's time per image is one sample of this
+                    // workgroup's iteration time (Welford's update)
+                    if (tid == 0) {
+                        const uint64_t t1 = wall_clock64();
+                        const double x = ((double)(t1 - s_m.t_group) + 0.5) / (double)ng;
+                        s_m.t_group = t1;
+                        s_m.af_n += 1.0;
+                        const double dlt = x - s_m.af_mean;
+                        s_m.af_mean += dlt / s_m.af_n;
+                        s_m.af_m2 += dlt * (x - s_m.af_mean);
+                    }
+                }
                 cur += ng;
             }
         }
-        // emulated heterogeneous workers: every emu_every-th workgroup idles
-        // after each chunk for emu_extra times the chunk's own time, so it
-        // runs (1 + emu_extra) times slower; its images do not change
-        if (EMU && d.emu_every > 0 && tid == 0 && blockIdx.x % (unsigned)d.emu_every == 0) {
-            const uint64_t t1 = wall_clock64();
-            const uint64_t until = t1 + (uint64_t)((float)(t1 - s_t_chunk) * d.emu_extra);
-            while (wall_clock64() < until) __builtin_amdgcn_s_sleep(4);
+        if (EMU && d.rule && tid == 0) {
+            // publish this workgroup's measurements for the next claims
+            if (d.rule == SI_SCHED_AWF) {
+                const double dt = (double)(wall_clock64() - s_m.t_chunk) + 0.5;
+                const int k = ++s_m.aw_k;
+                s_m.aw_a += (double)k * (double)(c_end - c_start);
+                s_m.aw_b += (double)k * dt;
+                const double rate = s_m.aw_a / s_m.aw_b;
+                atomicAdd(&d.adapt[0], rate - s_m.aw_rate);
+                if (k == 1) atomicAdd(&d.adapt[2], 1.0);
+                s_m.aw_rate = rate;
+            } else if (d.rule == SI_SCHED_AF && s_m.af_n >= 2.0) {
+                const double c1 = 1.0 / s_m.af_mean;
+                const double c2 = s_m.af_m2 / (s_m.af_n - 1.0) / s_m.af_mean;
+                atomicAdd(&d.adapt[0], c1 - s_m.af_c1);
+                atomicAdd(&d.adapt[1], c2 - s_m.af_c2);
+                if (!s_m.af_meas) atomicAdd(&d.adapt[2], 1.0);
+                s_m.af_meas = 1;
+                s_m.af_c1 = c1;
+                s_m.af_c2 = c2;
+            }
         }
     }
 
@@ -817,6 +953,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
         if (d.stat_invalid && my_invalid) atomicAdd(d.stat_invalid, my_invalid);
         if (d.err_flag && my_invalid) atomicOr(d.err_flag, 1u);
         if (d.stat_overflow && my_overflow) atomicAdd(d.stat_overflow, my_overflow);
+        if (EMU && d.stat_chunks && s_m.claims) atomicAdd(d.stat_chunks, s_m.claims);
         if (d.wg_ns) d.wg_ns[blockIdx.x] = (unsigned long long)(wall_clock64() - t_begin);
         if (d.dynamic) {
             // the last workgroup to finish leaves the counter at zero for the next launch
@@ -825,6 +962,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))
             if (done == gridDim.x - 1) {
                 atomicExch(d.counter, 0u);
                 atomicExch(d.counter + 1, 0u);
+                if (EMU && d.rule) atomicExch(d.counter + 2, 0u);
             }
         }
     }
@@ -904,7 +1042,7 @@ hipError_t launch_spin(const LaunchDesc& d, int n_wg, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     const size_t lds = spin_lds_bytes(dd.max_w2, dd.group);
-    if (dd.emu_every > 0)
+    if (dd.emu_every > 0 || dd.rule != 0)
         hipLaunchKernelGGL(k_spin<true>, dim3(n_wg), dim3(kBlock), lds, s, dd);
     else
         hipLaunchKernelGGL(k_spin<false>, dim3(n_wg), dim3(kBlock), lds, s, dd);

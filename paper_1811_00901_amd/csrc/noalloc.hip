@@ -71,6 +71,8 @@ extern "C" si_status si_generate_noalloc(const si_scene* scene, const int32_t* o
     if (!scene) return fail(SI_E_INVALID, "scene is NULL");
     si_status rc = check_sched(sched);
     if (rc != SI_OK) return rc;
+    if (sched->kind >= SI_SCHED_WF)
+        return fail(SI_E_UNSUPPORTED, "SI_SCHED_WF, AWF and AF run in si_generate only");
     if (sched->kind == SI_SCHED_LEARNED)
         return fail(SI_E_UNSUPPORTED,
                     "si_generate_noalloc runs the fixed schedules only; the learned plan "

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "scene_build.h"
+#include "adaptive.h"
 
 namespace si {
 
@@ -54,11 +55,18 @@ void user_kernel_events(hipEvent_t* begin, hipEvent_t* end) {
 
 static thread_local int32_t g_emu_every = 0;
 static thread_local float g_emu_slowdown = 1.0f;
+static thread_local int32_t g_emu_busy = 0;
+static thread_local int32_t g_emu_place = SI_EMU_EVERY;
+static thread_local std::vector<float> g_weights;
 
 void apply_emulated_workers(LaunchDesc& d) {
     d.emu_every = g_emu_every;
     d.emu_extra = g_emu_slowdown - 1.0f;
+    d.emu_busy = g_emu_busy;
+    d.emu_place = g_emu_place;
 }
+
+const std::vector<float>& worker_weights() { return g_weights; }
 
 // --------------------------------------------------------- device state --
 }  // namespace si
@@ -732,20 +740,22 @@ si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_st
     unsigned long long* dev_stats = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (stats) {
-        const size_t words = 4 + (size_t)n_wg;
+        const size_t words = 5 + (size_t)n_wg;
         SI_HIP(hipMalloc(&dev_stats, sizeof(unsigned long long) * words));
         SI_HIP(launch_fill(reinterpret_cast<int32_t*>(dev_stats), (int64_t)(2 * words), 0, s));
         d.stat_tested = dev_stats;
         d.stat_support = dev_stats + 1;
         d.stat_invalid = reinterpret_cast<uint32_t*>(dev_stats + 2);
         d.stat_overflow = reinterpret_cast<uint32_t*>(dev_stats + 3);
-        d.wg_ns = dev_stats + 4;
+        d.stat_chunks = reinterpret_cast<uint32_t*>(dev_stats + 4);
+        d.wg_ns = dev_stats + 5;
         SI_HIP(hipEventCreate(&ev0));
         SI_HIP(hipEventCreate(&ev1));
         SI_HIP(hipEventRecord(ev0, s));
     } else {
         d.stat_tested = d.stat_support = nullptr;
         d.stat_invalid = d.stat_overflow = nullptr;
+        d.stat_chunks = nullptr;
         d.wg_ns = nullptr;
     }
     if (g_ev_begin) SI_HIP(hipEventRecord(g_ev_begin, s));
@@ -757,7 +767,7 @@ si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_st
     }
     if (!stats) return SI_OK;
     SI_HIP(hipEventRecord(ev1, s));
-    std::vector<unsigned long long> h(4 + (size_t)n_wg);
+    std::vector<unsigned long long> h(5 + (size_t)n_wg);
     SI_HIP(hipMemcpyAsync(h.data(), dev_stats, sizeof(unsigned long long) * h.size(),
                           hipMemcpyDeviceToHost, s));
     SI_HIP(hipStreamSynchronize(s));
@@ -779,10 +789,11 @@ si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_st
         SI_HIP(hipMemcpy(&nc, d.n_chunks_dev, sizeof(nc), hipMemcpyDeviceToHost));
         stats->n_chunks = nc;
     }
+    if (d.rule) stats->n_chunks = (int32_t)(uint32_t)h[4];
     if (stats->wg_busy_ns) {
         const int n = std::min(stats->wg_busy_cap, n_wg);
         for (int i = 0; i < n; ++i)
-            stats->wg_busy_ns[i] = (uint64_t)((double)h[4 + i] * 1e6 / (double)st->wall_khz);
+            stats->wg_busy_ns[i] = (uint64_t)((double)h[5 + i] * 1e6 / (double)st->wall_khz);
     }
     if (stats->n_invalid) return fail(SI_E_INVALID, "oriented_idx holds indices outside [0, M)");
     return SI_OK;
@@ -790,7 +801,7 @@ si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_st
 
 si_status check_sched(const si_sched* sc) {
     if (!sc) return fail(SI_E_INVALID, "sched is NULL");
-    if (sc->kind < SI_SCHED_STATIC || sc->kind > SI_SCHED_FAC_PROB)
+    if (sc->kind < SI_SCHED_STATIC || sc->kind > SI_SCHED_AF)
         return fail(SI_E_INVALID, "unknown schedule kind");
     if (sc->num_workgroups < 0) return fail(SI_E_INVALID, "num_workgroups must be >= 0");
     if (sc->min_chunk < 0) return fail(SI_E_INVALID, "min_chunk must be >= 0");
@@ -842,6 +853,58 @@ int auto_workgroups(DeviceState* st, int max_w2, int group) {
         st->wg_per_cu[key] = per_cu;
     }
     return std::max(1, st->n_cu * per_cu);
+}
+
+}  // namespace si
+
+namespace si {
+
+// Launch state of SI_SCHED_WF / AWF / AF: FAC2's chunk of each batch (by
+// value in the launch), and one stream-ordered block holding the AWF / AF
+// sums (4 doubles, zero) and the WF weights (n_wg floats).
+si_status rule_setup(int kind, int64_t N, int n_wg, const si_sched* sched, LaunchDesc& d,
+                     char** mem_out, hipStream_t s) {
+    // default floor: a spread unit (8 images); smaller chunks cannot share
+    // candidate passes between images, whatever the rule asks
+    const int64_t mc = sched->min_chunk > 0 ? sched->min_chunk : kSpreadUnit;
+    const double x = sched->fac_divisor > 0.0f ? (double)sched->fac_divisor : 2.0;
+    d.rule = kind;
+    d.min_chunk = (int32_t)mc;
+    d.n_bases = 0;
+    for (int64_t R = N; R > 0 && d.n_bases < kMaxBases;) {
+        const int64_t c = std::max((int64_t)ceil((double)R / (x * (double)n_wg)), mc);
+        d.bases[d.n_bases++] = (int32_t)std::min<int64_t>(c, INT32_MAX);
+        R -= std::min(R, c * (int64_t)n_wg);
+    }
+    // weights: the caller's, else the emulated speeds, else 1; sum n_wg
+    static thread_local std::vector<float> w;
+    w.assign(n_wg, 1.0f);
+    const std::vector<float>& given = worker_weights();
+    if (!given.empty()) {
+        for (int k = 0; k < n_wg; ++k) w[k] = given[k % given.size()];
+    } else if (d.emu_every > 0 && d.emu_place == SI_EMU_EVERY) {
+        for (int k = 0; k < n_wg; ++k)
+            if (k % d.emu_every == 0) w[k] = 1.0f / (1.0f + d.emu_extra);
+    }
+    double sum = 0.0;
+    for (float v : w) sum += v;
+    for (float& v : w) v = (float)((double)v * (double)n_wg / sum);
+    const size_t bytes = 4 * sizeof(double) + sizeof(float) * (size_t)n_wg;
+    char* mem = nullptr;
+    SI_HIP(pool_alloc((void**)&mem, bytes, s));
+    hipError_t e = launch_fill(reinterpret_cast<int32_t*>(mem), 8, 0, s);
+    // pageable source: the copy returns once the runtime holds the bytes
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(mem + 4 * sizeof(double), w.data(), sizeof(float) * (size_t)n_wg,
+                           hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(mem, s);
+        return hip_fail(e, "worker-sized claims");
+    }
+    d.adapt = reinterpret_cast<double*>(mem);
+    d.weights = reinterpret_cast<const float*>(mem + 4 * sizeof(double));
+    *mem_out = mem;
+    return SI_OK;
 }
 
 }  // namespace si
@@ -924,9 +987,21 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
         }
     }
     int32_t* order_mem = nullptr;
-    if (kind != SI_SCHED_LEARNED) {
-        rc = get_table(st, kind, N, n_wg, sched->min_chunk, sched->fac_divisor, &chunks, &n_chunks);
+    char* rule_mem = nullptr;
+    if (kind >= SI_SCHED_WF) {
+        // claims sized by the workgroups: FAC2's batch chunks by value, the
+        // WF weights and the AWF / AF sums in one stream-ordered block
+        rc = rule_setup(kind, N, n_wg, sched, d, &rule_mem, s);
         if (rc != SI_OK) return rc;
+        chunks = nullptr;
+        n_chunks = 1;
+    }
+    if (kind != SI_SCHED_LEARNED) {
+        if (kind < SI_SCHED_WF) {
+            rc = get_table(st, kind, N, n_wg, sched->min_chunk, sched->fac_divisor, &chunks,
+                           &n_chunks);
+            if (rc != SI_OK) return rc;
+        }
         if (sched->order != SI_ORDER_GIVEN && scene->n_cells > 1) {
             rc = cell_order(*scene, oriented_idx, N, s, &order_mem, &d.single.perm);
             if (rc != SI_OK) return rc;
@@ -943,6 +1018,7 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     rc = run_launch(st, d, n_wg, w2, stats, s, kind);
     if (order_mem) (void)hipFreeAsync(order_mem, s);
     if (learned_mem) (void)hipFreeAsync(learned_mem, s);
+    if (rule_mem) (void)hipFreeAsync(rule_mem, s);
     return rc;
 }
 
@@ -967,6 +1043,40 @@ si_status si_set_emulated_workers(int32_t every, float slowdown) {
     g_emu_every = slowdown > 1.0f ? every : 0;
     g_emu_slowdown = slowdown;
     return SI_OK;
+}
+
+si_status si_set_emulated_mode(int32_t busy, int32_t placement) {
+    if (busy != 0 && busy != 1) return fail(SI_E_INVALID, "busy must be 0 or 1");
+    if (placement < SI_EMU_EVERY || placement > SI_EMU_LAST)
+        return fail(SI_E_INVALID, "placement must be SI_EMU_EVERY, SI_EMU_FIRST or SI_EMU_LAST");
+    g_emu_busy = busy;
+    g_emu_place = placement;
+    return SI_OK;
+}
+
+si_status si_set_worker_weights(const float* weights, int32_t n) {
+    if (n < 0) return fail(SI_E_INVALID, "n must be >= 0");
+    if (n > 0 && !weights) return fail(SI_E_INVALID, "weights is NULL");
+    for (int32_t i = 0; i < n; ++i)
+        if (!isfinite(weights[i]) || !(weights[i] > 0.0f))
+            return fail(SI_E_INVALID, "weights must be positive and finite");
+    g_weights.assign(weights, weights + n);
+    return SI_OK;
+}
+
+int64_t si_rule_wf_chunk(double w, int64_t base, int64_t remaining, int32_t min_chunk) {
+    return wf_chunk(w, base, remaining, std::max(1, min_chunk));
+}
+
+double si_rule_awf_weight(double rate, double rate_sum, int32_t n_meas, int32_t P) {
+    return awf_weight(rate, rate_sum, n_meas, P);
+}
+
+int64_t si_rule_af_chunk(double var_over_mu_sum, double inv_mu_sum, int32_t n_meas, int32_t P,
+                         int64_t remaining, double mu, int32_t min_chunk) {
+    double D, T;
+    af_terms(var_over_mu_sum, inv_mu_sum, n_meas, P, &D, &T);
+    return af_chunk(D, T, remaining, mu, std::max(1, min_chunk));
 }
 
 si_status si_set_kernel_events(void* begin_event, void* end_event) {

@@ -9,6 +9,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "../../include/si.h"
 
@@ -116,6 +117,8 @@ struct Item {
     int32_t spread_mult;  // coprime to spread_full
 };
 
+constexpr int kMaxBases = 64;  // FAC2 batches carried by a launch
+
 struct LaunchDesc {
     Item single;              // the item of a single-scene launch (items == nullptr)
     const Item* items;        // device array for batched launches, else nullptr
@@ -138,9 +141,23 @@ struct LaunchDesc {
     // to 1 by any launch that meets an oriented index outside [0, M)
     uint32_t* err_flag;
     // emulated heterogeneous workers (si_set_emulated_workers): every
-    // emu_every-th workgroup (0 = none) runs 1 + emu_extra times slower
+    // emu_every-th workgroup (0 = none) runs 1 + emu_extra times slower,
+    // idling (emu_busy 0) or keeping its compute unit busy (emu_busy 1)
     int32_t emu_every;
     float emu_extra;
+    int32_t emu_busy;
+    int32_t emu_place;           // SI_EMU_EVERY / FIRST / LAST (which workgroups are slow)
+    // claims sized by the claiming workgroup (rule = SI_SCHED_WF, AWF or AF;
+    // 0 = the chunk table): counter[0] counts claims, counter[2] is the
+    // loop's next iteration, each advanced by one atomic addition per claim
+    int32_t rule;
+    int32_t min_chunk;
+    int32_t n_bases;             // FAC2's chunk of each batch (WF, AWF; AF's first chunk)
+    int32_t bases[kMaxBases];
+    const float* weights;        // WF: one weight per workgroup, summing to the count
+    double* adapt;               // AWF: [0] sum of rates, [2] measured workgroups;
+                                 // AF: [0] sum of 1/mu, [1] sum of sigma^2/mu, [2] measured
+    uint32_t* stat_chunks;       // claims made (may be null)
 };
 
 constexpr int kMaxGroup = 8;
@@ -211,6 +228,8 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s);
 void user_kernel_events(hipEvent_t* begin, hipEvent_t* end);
 // this thread's si_set_emulated_workers setting, written into a launch
 void apply_emulated_workers(LaunchDesc& d);
+// this thread's si_set_worker_weights setting (empty = none)
+const std::vector<float>& worker_weights();
 uint32_t* take_counter(DeviceState* st);
 si_status make_params(const si_params* prm, SpinParams* out, double* radius);
 si_status check_sched(const si_sched* sc);
