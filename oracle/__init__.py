@@ -15,6 +15,8 @@ Contents:
                          later TSS / FAC_PROB / WF / AWF / AF rules, and
                          discrete-event simulations of P self-scheduling workers
                          (of different speeds for the worker-dependent rules);
+  * ``matching``      -- mesh resolution (mean nearest-neighbour distance) and
+                         the correlation of spin images, next to the path;
   * ``mlp``           -- FP64 reference of the per-image cost model (features,
                          forward, backward, Adam).
 """
