@@ -584,6 +584,53 @@ const char* si_last_error(void);
 int32_t si_abi_version(void);
 
 /*
+ * Mesh resolution of a scene: the mean, over the chosen points, of the
+ * distance from a point to its nearest other point of the scene (the paper
+ * sets the bin size B as a factor of the mesh resolution, Section 2.1 and
+ * the notation table; a bin of B = factor x this value).  Exact nearest
+ * neighbours: each query searches the scene's grid in shells of cells until
+ * no unsearched point can be nearer (a scene built with radius <= 0 is one
+ * cell: brute force over M points per query).
+ *   idx      device, n int32 indices of the query points (the order given
+ *            to si_build_scene), or NULL for all M points (n ignored)
+ *   nn_out   device, n float32 distances, or NULL
+ *   mean_out host: the mean distance (FP64 sum)
+ * A point at the same place as another has distance 0.  Synchronises the
+ * stream.  Returns SI_E_INVALID for M < 2, n out of [1, 2^31 - 1), an
+ * index outside [0, M) (its distance is NaN), or a NULL mean_out.
+ */
+si_status si_mesh_resolution(const si_scene* scene, const int32_t* idx, int64_t n,
+                             float* nn_out, double* mean_out, void* hip_stream);
+
+/*
+ * Spin-image matching: the normalised linear correlation coefficient of
+ * every pair of images from two sets (the comparison by which spin images
+ * are matched in object recognition, Johnson and Hebert, cited by the paper)
+ *     R(P, Q) = (N sum p q - sum p sum q)
+ *               / sqrt((N sum p^2 - (sum p)^2) (N sum q^2 - (sum q)^2))
+ * over all N = n_bins bins; an image with no variance has R = 0.
+ *   A        device, n_a x n_bins float32 (e.g. si_generate's images_out)
+ *   B        device, n_b x n_bins float32
+ *   R_out    device, n_a x n_b float32 row-major, or NULL
+ *   best_out device, n_a int32: for each image of A, the image of B of
+ *            largest R (lowest index on ties), or NULL
+ *   best_R_out device, n_a float32: that R, or NULL
+ * At least one output must be given.  sum p q runs on the matrix cores in
+ * fp16 with fp32 accumulation: each image is scaled by its largest |bin|
+ * (R is unchanged by that) and rounded to fp16, and all sums are taken from
+ * the rounded values.  Rounding moves R by at most about
+ * 2u (1 + |R|) (k_P + k_Q), u = 2^-11, k = sqrt(1 + mean^2 / variance) of
+ * the image's bins.  Bins must be finite.  Asynchronous on hip_stream; the
+ * temporaries (fp16 copies, 2 n_bins bytes per image) come from the
+ * device's stream-ordered pool.  n_a or n_b = 0 does nothing.  Returns
+ * SI_E_INVALID for negative sizes, sizes of 2^31 - 1 or more, n_bins out of
+ * [2, 65536], NULL inputs or no output.
+ */
+si_status si_correlate(const float* A, int64_t n_a, const float* B, int64_t n_b,
+                       int32_t n_bins, float* R_out, int32_t* best_out, float* best_R_out,
+                       void* hip_stream);
+
+/*
  * Measured throughput ceilings of the device, for reading the spin kernel's
  * roofline (the VALU lane-operations of its pair tests and binning, its LDS
  * atomics, its HBM image stores).  One warm-up and one timed launch, HIP

@@ -28,6 +28,7 @@ __all__ = [
     "si_cost_model_predict_planner", "si_cost_model_gradient",
     "si_features_batched", "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
     "si_set_kernel_events", "si_set_emulated_workers", "si_autotune", "si_peak_probe",
+    "si_mesh_resolution", "si_bin_size", "si_correlate",
     "si_set_emulated_mode", "si_set_worker_weights", "si_rule_wf_chunk", "si_rule_awf_weight",
     "si_rule_af_chunk",
     "SCHED", "MODE", "PROBE",
@@ -139,6 +140,8 @@ def lib():
             "si_last_error": (ctypes.c_char_p, []),
             "si_abi_version": (I32, []),
             "si_peak_probe": (I32, [I32, ctypes.POINTER(ctypes.c_double), P]),
+            "si_mesh_resolution": (I32, [P, P, I64, P, ctypes.POINTER(ctypes.c_double), P]),
+            "si_correlate": (I32, [P, I64, P, I64, I32, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -558,6 +561,47 @@ def si_cost_model_predict_planner(model: CostModel, feats: torch.Tensor, stream=
             model.handle, _dev_ptr(feats, torch.float32, "feats", (n, 12)), n,
             _dev_ptr(out, torch.float32, "pred"), _stream(stream)))
     return out
+
+
+def si_mesh_resolution(scene: Scene, idx: torch.Tensor | None = None, nn_out: bool = False,
+                       stream=None):
+    """Mean distance from the chosen points (device int32 indices, None = all)
+    to their nearest other point; with nn_out=True also the per-point
+    distances (device float32).  Synchronises the stream."""
+    n = scene.M if idx is None else int(idx.shape[0])
+    ip = _dev_ptr(idx, torch.int32, "idx", (n,)) if idx is not None else None
+    dev = torch.device("cuda", scene.device)
+    nn = torch.empty((n,), dtype=torch.float32, device=dev) if nn_out else None
+    mean = ctypes.c_double()
+    _check(lib().si_mesh_resolution(scene.handle, ip, n,
+                                    ctypes.c_void_p(nn.data_ptr()) if nn is not None else None,
+                                    ctypes.byref(mean), _stream(stream)))
+    return (float(mean.value), nn) if nn_out else float(mean.value)
+
+
+def si_bin_size(scene: Scene, factor: float, idx: torch.Tensor | None = None) -> float:
+    """Bin size as the paper states it: a factor of the mesh resolution."""
+    return float(factor) * si_mesh_resolution(scene, idx)
+
+
+def si_correlate(A: torch.Tensor, B: torch.Tensor, R: bool = True, best: bool = True,
+                 stream=None):
+    """Correlation of spin images: A (n_a, ...) and B (n_b, ...) device
+    float32 with the same bins per image.  Returns (R (n_a, n_b) or None,
+    best index (n_a,) int32 or None, best R (n_a,) or None)."""
+    n_a, n_b = int(A.shape[0]), int(B.shape[0])
+    nb = int(A[0].numel()) if n_a else int(B[0].numel()) if n_b else 0
+    ap = _dev_ptr(A, torch.float32, "A")
+    bp = _dev_ptr(B, torch.float32, "B")
+    if n_b and int(B[0].numel()) != nb:
+        raise ValueError("A and B must have the same number of bins per image")
+    dev = A.device
+    Rt = torch.empty((n_a, n_b), dtype=torch.float32, device=dev) if R else None
+    bi = torch.empty((n_a,), dtype=torch.int32, device=dev) if best else None
+    br = torch.empty((n_a,), dtype=torch.float32, device=dev) if best else None
+    p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    _check(lib().si_correlate(ap, n_a, bp, n_b, nb, p(Rt), p(bi), p(br), _stream(stream)))
+    return Rt, bi, br
 
 
 def si_chunk_table(kind: str, N: int, P: int, min_chunk: int = 0, fac_divisor: float = 0.0) -> np.ndarray:

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libspinimg.so")
 SOURCES = ["runtime.hip", "k_scene.hip", "k_spin.hip", "batch.hip", "autotune.hip",
-           "cost_model.hip", "probe.hip", "noalloc.hip"]
+           "cost_model.hip", "probe.hip", "noalloc.hip", "k_match.hip"]
 ARCH = os.environ.get("SI_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

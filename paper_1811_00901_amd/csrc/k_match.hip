@@ -1,0 +1,366 @@
+// Workloads next to spin-image generation, on gfx950.
+//
+// * Mesh resolution (si_mesh_resolution): the paper sets the bin size B as a
+//   factor of the mesh resolution (Section 2.1, notation table); read as the
+//   mean distance from a point to its nearest other point.  One thread per
+//   query point searches the scene's cell grid in shells of cells at
+//   Chebyshev distance r = 0, 1, 2, ... from its own cell; every point not yet
+//   searched is farther than r h, so the search stops as soon as the best
+//   distance is within r h (exact, whatever the spacing).
+// * Spin-image correlation (si_correlate): the normalised linear correlation
+//   coefficient of two images' bins, the comparison by which spin images are
+//   matched in object recognition (Johnson and Hebert, cited by the paper):
+//       R = (N sum pq - sum p sum q) / sqrt((N sum p^2 - (sum p)^2)(N sum q^2 - (sum q)^2))
+//   over N = W^2 bins, for every pair of two image sets.  sum pq over all
+//   pairs is a dense contraction (n_a x n_b x N): it runs on the matrix cores
+//   with fp16 operands and fp32 accumulation.  Each image is first scaled by
+//   its largest bin (R does not change under a positive scale) and rounded to
+//   fp16; its sums are taken from the rounded values, so R is the exact
+//   correlation of the rounded images up to fp32 accumulation.
+#include "si_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+namespace si {
+namespace {
+
+// ------------------------------------------------------ mesh resolution --
+__global__ void __launch_bounds__(256) k_nn(SceneView sc, const int32_t* __restrict__ idx,
+                                            int64_t n, float* __restrict__ nn,
+                                            double* __restrict__ acc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double mine = 0.0;
+    double bad = 0.0;
+    if (i < n) {
+        const int o = idx ? idx[i] : (int)i;
+        if (o < 0 || o >= sc.M) {
+            if (nn) nn[i] = __int_as_float(0x7fc00000);
+            bad = 1.0;
+        } else {
+            const int sp = sc.inv[o];
+            const float4 p = sc.pos[sp];
+            const int cell = __float_as_int(p.w);
+            const int c0 = cell % sc.dims[0];
+            const int c1 = (cell / sc.dims[0]) % sc.dims[1];
+            const int c2 = cell / (sc.dims[0] * sc.dims[1]);
+            const int rmax = max(max(max(c0, sc.dims[0] - 1 - c0), max(c1, sc.dims[1] - 1 - c1)),
+                                 max(c2, sc.dims[2] - 1 - c2));
+            float best = __int_as_float(0x7f800000);
+            for (int r = 0; r <= rmax; ++r) {
+                for (int dz = -r; dz <= r; ++dz) {
+                    const int z = c2 + dz;
+                    if (z < 0 || z >= sc.dims[2]) continue;
+                    for (int dy = -r; dy <= r; ++dy) {
+                        const int y = c1 + dy;
+                        if (y < 0 || y >= sc.dims[1]) continue;
+                        // on the shell: all of x when y or z is at distance r
+                        const bool face = (dz == -r || dz == r || dy == -r || dy == r);
+                        for (int dx = -r; dx <= r; dx += (face || r == 0) ? 1 : 2 * r) {
+                            const int x = c0 + dx;
+                            if (x < 0 || x >= sc.dims[0]) continue;
+                            const int key = ((z * sc.dims[1] + y) * sc.dims[0] + x) * kSubX;
+                            const int a = sc.sub_start[key], b = sc.sub_start[key + kSubX];
+                            for (int j = a; j < b; ++j) {
+                                if (j == sp) continue;
+                                const float4 q = sc.pos[j];
+                                const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
+                                best = fminf(best, fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
+                            }
+                        }
+                    }
+                }
+                // every point outside shells 0..r lies more than r h away
+                const double lim = (double)r * sc.h * (1.0 - 1e-6);
+                if ((double)best <= lim * lim) break;
+            }
+            const float d = sqrtf(best);
+            if (nn) nn[i] = d;
+            mine = (double)d;
+        }
+    }
+    // block sums of the distances (and of invalid indices), one atomic each
+    __shared__ double s_sum[256 / 64], s_bad[256 / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        mine += __shfl_xor(mine, off, 64);
+        bad += __shfl_xor(bad, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_sum[threadIdx.x >> 6] = mine;
+        s_bad[threadIdx.x >> 6] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0, u = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            t += s_sum[w];
+            u += s_bad[w];
+        }
+        if (t != 0.0) atomicAdd(acc, t);
+        if (u != 0.0) atomicAdd(acc + 1, u);
+    }
+}
+
+// ----------------------------------------------------------- correlation --
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 128;  // rows of A and of B per workgroup tile
+constexpr int kBK = 64;     // K (bins) per LDS stage
+constexpr int kLdsRow = kBK + 8;  // halves per LDS row (16 bytes of padding)
+
+// One wave per image: scale by the largest bin, round to fp16 into a row of
+// Kp halves (zero beyond N), and keep the rounded image's sum s and
+// rs = 1 / sqrt(N sum h^2 - s^2) (0 when the image has no variance).
+__global__ void __launch_bounds__(256) k_corr_prep(const float* __restrict__ X, int64_t n, int N,
+                                                   int Kp, _Float16* __restrict__ H,
+                                                   float2* __restrict__ stats) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    const float* x = X + row * (int64_t)N;
+    float mx = 0.0f;
+    for (int k = lane; k < N; k += 64) mx = fmaxf(mx, fabsf(x[k]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    const float inv = mx > 0.0f ? 1.0f / mx : 1.0f;
+    double s = 0.0, q = 0.0;
+    _Float16* h = H + row * (int64_t)Kp;
+    for (int k = lane; k < Kp; k += 64) {
+        const _Float16 v = (_Float16)(k < N ? x[k] * inv : 0.0f);
+        h[k] = v;
+        const double f = (double)(float)v;
+        s += f;
+        q += f * f;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        q += __shfl_xor(q, off, 64);
+    }
+    if (lane == 0) {
+        const double var = (double)N * q - s * s;
+        stats[row] = make_float2((float)s, var > 0.0 ? (float)(1.0 / sqrt(var)) : 0.0f);
+    }
+}
+
+// Order-preserving 64-bit key of (R, j): larger R first, then smaller j.
+__device__ __forceinline__ unsigned long long best_key(float r, int j) {
+    const uint32_t b = __float_as_uint(r);
+    const uint32_t o = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ((unsigned long long)o << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
+}
+
+// R for a 128 x 128 tile of (A image, B image) pairs.  Four waves, each a
+// 64 x 64 quarter as 4 x 4 products of 16 x 16 (v_mfma_f32_16x16x32_f16:
+// lane l holds row l % 16 of the A operand and of B's image at K = 8 (l / 16)
+// .. + 7, and receives column l % 16, rows 4 (l / 16) .. + 3 of the result).
+// Operands stage through LDS 64 bins at a time; the next stage's global loads
+// are issued before the current one's products.  Tiles are numbered so that
+// consecutive workgroups of one XCD (workgroup ids congruent mod 8) take
+// consecutive tiles of one A row band, which they share in that XCD's L2.
+__global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ HA,
+                                                   const _Float16* __restrict__ HB,
+                                                   const float2* __restrict__ SA,
+                                                   const float2* __restrict__ SB, int64_t n_a,
+                                                   int64_t n_b, int N, int Kp, int64_t tiles_n,
+                                                   int64_t n_tiles, float* __restrict__ Rout,
+                                                   unsigned long long* __restrict__ best) {
+    __shared__ __attribute__((aligned(16))) _Float16 As[kTile * kLdsRow];
+    __shared__ __attribute__((aligned(16))) _Float16 Bs[kTile * kLdsRow];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // XCD-aware tile order
+    const int64_t L = blockIdx.x;
+    const int64_t per = (n_tiles + 7) / 8;
+    const int64_t tile = (L % 8) * per + L / 8;
+    if (tile >= n_tiles) return;
+    const int64_t m0 = (tile / tiles_n) * kTile, n0 = (tile % tiles_n) * kTile;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int r16 = lane & 15, kq = lane >> 4;
+
+    // global -> registers: 4 chunks of 8 halves per matrix per thread
+    h8 ga[4], gb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = tid + 256 * i;
+            const int row = c >> 3, col = (c & 7) * 8;
+            const int64_t ra = m0 + row, rb = n0 + row;
+            h8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+            ga[i] = ra < n_a ? *reinterpret_cast<const h8*>(HA + ra * Kp + k0 + col) : z;
+            gb[i] = rb < n_b ? *reinterpret_cast<const h8*>(HB + rb * Kp + k0 + col) : z;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = tid + 256 * i;
+            const int row = c >> 3, col = (c & 7) * 8;
+            *reinterpret_cast<h8*>(As + row * kLdsRow + col) = ga[i];
+            *reinterpret_cast<h8*>(Bs + row * kLdsRow + col) = gb[i];
+        }
+    };
+
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+
+    load(0);
+    for (int k0 = 0; k0 < Kp; k0 += kBK) {
+        __syncthreads();  // the previous stage's reads are done
+        store();
+        __syncthreads();
+        if (k0 + kBK < Kp) load(k0 + kBK);
+#pragma unroll
+        for (int ks = 0; ks < kBK; ks += 32) {
+            h8 fa[4], fb[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                fa[t] = *reinterpret_cast<const h8*>(As + (wm * 64 + t * 16 + r16) * kLdsRow +
+                                                     ks + 8 * kq);
+                fb[t] = *reinterpret_cast<const h8*>(Bs + (wn * 64 + t * 16 + r16) * kLdsRow +
+                                                     ks + 8 * kq);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[a], fb[b], acc[a][b],
+                                                                        0, 0, 0);
+        }
+    }
+
+    // epilogue: R, optional store, and each row's best column in this tile
+    const float fN = (float)N;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = m0 + wm * 64 + a * 16 + 4 * kq + v;
+            const bool row_ok = row < n_a;
+            const float2 sa = row_ok ? SA[row] : make_float2(0.0f, 0.0f);
+            unsigned long long key = 0ull;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int64_t col = n0 + wn * 64 + b * 16 + r16;
+                if (row_ok && col < n_b) {
+                    const float2 sb = SB[col];
+                    const float r = (fN * acc[a][b][v] - sa.x * sb.x) * sa.y * sb.y;
+                    if (Rout) Rout[row * n_b + col] = r;
+                    key = max(key, best_key(r, (int)col));
+                }
+            }
+            if (best) {
+                // the 16 lanes of one row hold its 64 columns of this wave
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) {
+                    const unsigned long long o = __shfl_xor(key, off, 64);
+                    key = max(key, o);
+                }
+                if (r16 == 0 && row_ok && key) atomicMax(best + row, key);
+            }
+        }
+    }
+}
+
+__global__ void k_corr_best(const unsigned long long* __restrict__ best, int64_t n,
+                            int32_t* __restrict__ idx, float* __restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const unsigned long long k = best[i];
+    const uint32_t o = (uint32_t)(k >> 32);
+    const uint32_t b = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    if (idx) idx[i] = (int32_t)(0xFFFFFFFFu - (uint32_t)k);
+    if (r) r[i] = __uint_as_float(b);
+}
+
+size_t rup256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+}  // namespace si
+
+using namespace si;
+
+extern "C" si_status si_mesh_resolution(const si_scene* scene, const int32_t* idx, int64_t n,
+                                        float* nn_out, double* mean_out, void* hip_stream) {
+    if (!scene) return fail(SI_E_INVALID, "scene is NULL");
+    if (!mean_out) return fail(SI_E_INVALID, "mean_out is NULL");
+    if (scene->M < 2) return fail(SI_E_INVALID, "a scene of one point has no nearest neighbour");
+    if (!idx) n = scene->M;
+    if (n <= 0 || n >= INT32_MAX) return fail(SI_E_INVALID, "n must be in [1, 2^31 - 1)");
+    int cur = 0;
+    SI_HIP(hipGetDevice(&cur));
+    if (cur != scene->device) return fail(SI_E_INVALID, "scene lives on another device");
+    hipStream_t s = (hipStream_t)hip_stream;
+    double* acc = nullptr;
+    SI_HIP(pool_alloc((void**)&acc, 2 * sizeof(double), s));
+    hipError_t e = launch_fill(reinterpret_cast<int32_t*>(acc), 4, 0, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_nn, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           view_of(*scene), idx, n, nn_out, acc);
+        e = hipGetLastError();
+    }
+    double h[2] = {0.0, 0.0};
+    if (e == hipSuccess) e = hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(acc, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "mesh resolution");
+    if (h[1] > 0.0) return fail(SI_E_INVALID, "idx holds indices outside [0, M)");
+    *mean_out = h[0] / (double)n;
+    return SI_OK;
+}
+
+extern "C" si_status si_correlate(const float* A, int64_t n_a, const float* B, int64_t n_b,
+                                  int32_t n_bins, float* R_out, int32_t* best_out,
+                                  float* best_R_out, void* hip_stream) {
+    if (n_a < 0 || n_b < 0) return fail(SI_E_INVALID, "n_a and n_b must be >= 0");
+    if (n_bins < 2 || n_bins > 65536) return fail(SI_E_INVALID, "n_bins must be in [2, 65536]");
+    if (n_a >= INT32_MAX || n_b >= INT32_MAX)
+        return fail(SI_E_INVALID, "n_a and n_b must be below 2^31 - 1");
+    if (n_a == 0 || n_b == 0) return SI_OK;
+    if (!A || !B) return fail(SI_E_INVALID, "A and B must be non-NULL");
+    if (!R_out && !best_out && !best_R_out)
+        return fail(SI_E_INVALID, "give at least one of R_out, best_out, best_R_out");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int Kp = (n_bins + kBK - 1) / kBK * kBK;
+    const bool want_best = best_out || best_R_out;
+    const size_t b_ha = rup256(sizeof(_Float16) * (size_t)n_a * Kp);
+    const size_t b_hb = rup256(sizeof(_Float16) * (size_t)n_b * Kp);
+    const size_t b_sa = rup256(sizeof(float2) * (size_t)n_a);
+    const size_t b_sb = rup256(sizeof(float2) * (size_t)n_b);
+    const size_t b_best = want_best ? rup256(sizeof(unsigned long long) * (size_t)n_a) : 0;
+    char* m = nullptr;
+    SI_HIP(pool_alloc((void**)&m, b_ha + b_hb + b_sa + b_sb + b_best, s));
+    _Float16* HA = reinterpret_cast<_Float16*>(m);
+    _Float16* HB = reinterpret_cast<_Float16*>(m + b_ha);
+    float2* SA = reinterpret_cast<float2*>(m + b_ha + b_hb);
+    float2* SB = reinterpret_cast<float2*>(m + b_ha + b_hb + b_sa);
+    unsigned long long* best =
+        want_best ? reinterpret_cast<unsigned long long*>(m + b_ha + b_hb + b_sa + b_sb) : nullptr;
+    hipError_t e = hipSuccess;
+    if (best) e = launch_fill(reinterpret_cast<int32_t*>(best), 2 * n_a, 0, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_corr_prep, dim3((unsigned)((n_a + 3) / 4)), dim3(256), 0, s, A, n_a,
+                           (int)n_bins, Kp, HA, SA);
+        hipLaunchKernelGGL(k_corr_prep, dim3((unsigned)((n_b + 3) / 4)), dim3(256), 0, s, B, n_b,
+                           (int)n_bins, Kp, HB, SB);
+        const int64_t tiles_n = (n_b + kTile - 1) / kTile;
+        const int64_t n_tiles = ((n_a + kTile - 1) / kTile) * tiles_n;
+        const int64_t grid = (n_tiles + 7) / 8 * 8;
+        if (grid > INT32_MAX) e = hipErrorInvalidValue;
+        else
+            hipLaunchKernelGGL(k_corr_gemm, dim3((unsigned)grid), dim3(256), 0, s, HA, HB, SA, SB,
+                               n_a, n_b, (int)n_bins, Kp, tiles_n, n_tiles, R_out, best);
+        if (e == hipSuccess) e = hipGetLastError();
+    }
+    if (e == hipSuccess && best) {
+        hipLaunchKernelGGL(k_corr_best, dim3((unsigned)((n_a + 255) / 256)), dim3(256), 0, s, best,
+                           n_a, best_out, best_R_out);
+        e = hipGetLastError();
+    }
+    (void)hipFreeAsync(m, s);
+    if (e != hipSuccess) return hip_fail(e, "spin-image correlation");
+    return SI_OK;
+}

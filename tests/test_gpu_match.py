@@ -1,0 +1,158 @@
+"""GPU: the workloads next to spin-image generation against the oracle.
+
+Mesh resolution: every point's nearest-neighbour distance against FP64 brute
+force or SciPy's k-d tree (FP32 coordinates: relative 2e-6), the lattice
+closed form exactly, the mean, and bin = factor x resolution.
+Correlation: R of every pair against the FP64 definition within the fp16
+rounding bound 2u (1 + |R|) (k_P + k_Q) + 1e-5 (u = 2^-11, k = sqrt(1 +
+mean^2 / variance) per image; 1e-5 covers fp32 accumulation), on ragged set
+sizes and bin counts that are not multiples of the tiles; each best match
+is a largest R of its row within that bound and equals the argmax of the
+launch's own R.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+S60 = float(np.float32(math.pi / 3))
+U16 = 2.0 ** -11
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import oracle
+    from oracle import matching
+    import paper_1811_00901_amd as si
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, si, oracle, matching
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def lattice(n, a, origin):
+    g = np.arange(n) * a
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    return (np.stack([x, y, z], -1).reshape(-1, 3) + np.asarray(origin)).astype(np.float32)
+
+
+def test_mesh_resolution_lattice_and_brute(env):
+    print("\n[case] mesh resolution lattice / brute", flush=True)
+    torch, si, _, Mt = env
+    X = lattice(12, 0.25, (3.0, -2.0, 7.5))
+    nrm = np.tile(np.float32([0, 0, 1]), (len(X), 1))
+    for radius in (0.3, 0.05, 0.0):  # finer and coarser grids than the spacing, one cell
+        sc = si.si_build_scene(dev(torch, X), dev(torch, nrm), radius)
+        mean, nn = si.si_mesh_resolution(sc, nn_out=True)
+        assert mean == 0.25 and bool((nn == 0.25).all()), radius
+    rng = np.random.default_rng(1)
+    for M, radius in ((3000, 0.3), (3000, 0.02), (800, 0.0)):
+        Y = rng.uniform(-1, 2, (M, 3)).astype(np.float32)
+        Y[7] = Y[100]  # a duplicate point: distance 0
+        ny = np.tile(np.float32([0, 0, 1]), (M, 1))
+        sc = si.si_build_scene(dev(torch, Y), dev(torch, ny), radius)
+        q = rng.choice(M, 500, replace=False).astype(np.int32)
+        q[0] = 7
+        mean, nn = si.si_mesh_resolution(sc, dev(torch, q), nn_out=True)
+        ref = Mt.nn_distances(Y, q)
+        np.testing.assert_allclose(nn.cpu().numpy(), ref, rtol=2e-6, atol=1e-12)
+        assert nn[0].item() == 0.0
+        assert abs(mean - ref.mean()) <= 2e-6 * ref.mean()
+
+
+@pytest.mark.parametrize("name,M", [("prims100k", None), ("clustered2m", None)])
+def test_mesh_resolution_workloads(env, name, M):
+    print(f"\n[case] mesh resolution {name}", flush=True)
+    torch, si, _, Mt = env
+    xyz, nrm = sg.config_scene(name, M)
+    params = si.Params(32, 0.02, S60)
+    sc = si.si_build_scene(dev(torch, xyz), dev(torch, nrm), si.si_support_radius(params))
+    q = np.sort(np.random.default_rng(2).choice(len(xyz), 20000, replace=False)).astype(np.int32)
+    mean, nn = si.si_mesh_resolution(sc, dev(torch, q), nn_out=True)
+    ref = Mt.nn_distances_tree(xyz, q)
+    np.testing.assert_allclose(nn.cpu().numpy(), ref, rtol=2e-6, atol=1e-12)
+    assert abs(mean - ref.mean()) <= 2e-6 * ref.mean()
+    assert si.si_bin_size(sc, 1.5, dev(torch, q)) == pytest.approx(1.5 * mean, rel=1e-12)
+    if name == "prims100k":  # every point
+        allm = si.si_mesh_resolution(sc)
+        assert abs(allm - Mt.nn_distances_tree(xyz).mean()) <= 2e-6 * allm
+
+
+def test_mesh_resolution_errors(env):
+    torch, si, _, _ = env
+    X = np.random.default_rng(0).uniform(0, 1, (50, 3)).astype(np.float32)
+    sc = si.si_build_scene(dev(torch, X), dev(torch, X), 0.2)
+    with pytest.raises(si.SiError):
+        si.si_mesh_resolution(sc, dev(torch, np.array([1, 50], np.int32)))
+    one = si.si_build_scene(dev(torch, X[:1]), dev(torch, X[:1]), 0.2)
+    with pytest.raises(si.SiError):
+        si.si_mesh_resolution(one)
+
+
+def corr_bound(Mt, A, B):
+    A = A.reshape(len(A), -1).astype(np.float64)
+    B = B.reshape(len(B), -1).astype(np.float64)
+    R = Mt.correlation(A, B)
+    ka = np.sqrt(1 + A.mean(1) ** 2 / np.maximum(A.var(1), 1e-300))
+    kb = np.sqrt(1 + B.mean(1) ** 2 / np.maximum(B.var(1), 1e-300))
+    tol = 2 * U16 * (1 + np.abs(R)) * (ka[:, None] + kb[None, :]) + 1e-5
+    return R, tol
+
+
+@pytest.mark.parametrize("W,n_a,n_b", [(32, 1037, 2091), (16, 300, 4097), (7, 129, 255)])
+def test_correlation_vs_oracle(env, W, n_a, n_b):
+    print(f"\n[case] correlation W={W} {n_a}x{n_b}", flush=True)
+    torch, si, oracle, Mt = env
+    xyz, nrm = sg.config_scene("prims100k", M=30000)
+    params = si.Params(W, 0.02, S60)
+    sc = si.si_build_scene(dev(torch, xyz), dev(torch, nrm), si.si_support_radius(params))
+    rng = np.random.default_rng(W)
+    ia = rng.choice(30000, n_a, replace=False).astype(np.int32)
+    ib = rng.choice(30000, n_b, replace=False).astype(np.int32)
+    ib[:n_a // 2] = ia[:n_a // 2]  # half of A has its exact image in B
+    A, _, _ = si.si_generate(sc, dev(torch, ia), params)
+    B, _, _ = si.si_generate(sc, dev(torch, ib), params)
+    A[3] = 0.0   # an empty image and a constant one: no variance, R = 0
+    B[5] = 2.5
+    R, bi, br = si.si_correlate(A, B)
+    _, bi2, br2 = si.si_correlate(A, B, R=False)
+    torch.cuda.synchronize()
+    Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+    Rg = R.cpu().numpy().astype(np.float64)
+    Ro, tol = corr_bound(Mt, Ah, Bh)
+    err = np.abs(Rg - Ro)
+    worst = np.unravel_index(np.argmax(err - tol), err.shape)
+    assert np.all(err <= tol), (worst, err[worst], tol[worst])
+    assert np.all(Rg[3] == 0) and np.all(Rg[:, 5] == 0)
+    bi, br = bi.cpu().numpy(), br.cpu().numpy()
+    # the launch's own argmax (lowest index on ties), with or without R_out
+    np.testing.assert_array_equal(bi, np.argmax(Rg, axis=1))
+    np.testing.assert_array_equal(br, Rg[np.arange(n_a), bi].astype(np.float32))
+    np.testing.assert_array_equal(bi2.cpu().numpy(), bi)
+    # a largest R of its row within the bound
+    rows = np.arange(n_a)
+    jo = np.argmax(Ro, axis=1)
+    assert np.all(Ro[rows, bi] >= Ro[rows, jo] - tol[rows, bi] - tol[rows, jo])
+    # images present in B are found (R = 1 up to rounding); rows 3 and 5 lost
+    # their copy to the empty and the constant image
+    keep = np.setdiff1d(np.arange(n_a // 2), [3, 5])
+    assert np.all(br[keep] > 1 - 1e-3)
+
+
+def test_correlation_errors(env):
+    torch, si, _, _ = env
+    A = torch.rand((10, 64), device="cuda")
+    with pytest.raises(si.SiError):
+        si.si_correlate(A, torch.rand((10, 64), device="cuda"), R=False, best=False)
+    with pytest.raises(ValueError):
+        si.si_correlate(A, torch.rand((10, 32), device="cuda"))
+    R, bi, br = si.si_correlate(A[:0], A)
+    assert R.shape == (0, 10)
