@@ -67,3 +67,49 @@ def best_match(A, B):
     R = correlation(A, B)
     j = np.argmax(R, axis=1)
     return j, R[np.arange(len(R)), j]
+
+
+# ---------------------------------------------------------------------------
+# Normal estimation.  The paper takes oriented points with known normals
+# (Section 2.1); for raw points the usual estimate is the direction of least
+# spread of the neighbourhood.  Reading: the neighbours of p are the points x
+# with |x - p| <= r, p itself included; their covariance (about their
+# centroid, divided by their count) has eigenvalues l0 <= l1 <= l2, and the
+# normal is the unit eigenvector of l0, signed so that n . (p - v) >= 0 for a
+# given viewpoint v (pointing away from v).  A neighbour within band
+# (relative) of the sphere, |x - p|^2 / r^2 - 1| < band, could be counted
+# either way at FP32 distance precision: such points are flagged, as are
+# points whose two smallest eigenvalues are too close for the direction to be
+# defined ((l1 - l0) / max(l2, tiny) < gap) and points with
+# |n . (p - v)| < 1e-6 |p - v| (sign undefined).
+# ---------------------------------------------------------------------------
+def estimate_normals(xyz, radius: float, viewpoint, idx=None, band: float = 1e-5,
+                     gap: float = 1e-4, block: int = 128):
+    """(normals (n, 3), neighbour counts (n,), flagged (n,) bool) for the
+    chosen points, FP64, brute-force neighbourhoods."""
+    X = np.asarray(xyz, dtype=np.float32).astype(np.float64)
+    idx = np.arange(len(X)) if idx is None else np.asarray(idx, dtype=np.int64)
+    r2 = float(np.float32(radius)) ** 2
+    v = np.asarray(viewpoint, dtype=np.float32).astype(np.float64)
+    normals = np.zeros((len(idx), 3))
+    counts = np.zeros(len(idx), dtype=np.int64)
+    flag = np.zeros(len(idx), dtype=bool)
+    for a in range(0, len(idx), block):
+        q = idx[a:a + block]
+        d2 = ((X[None, :, :] - X[q][:, None, :]) ** 2).sum(axis=2)
+        for t, i in enumerate(q):
+            near = d2[t] <= r2
+            flag[a + t] |= bool((np.abs(d2[t] / r2 - 1.0) < band).any())
+            nb = X[near]
+            counts[a + t] = len(nb)
+            c = nb.mean(axis=0)
+            C = (nb - c).T @ (nb - c) / len(nb)
+            lam, vec = np.linalg.eigh(C)
+            n = vec[:, 0]
+            if (lam[1] - lam[0]) < gap * max(lam[2], 1e-300):
+                flag[a + t] = True
+            s = float(n @ (X[i] - v))
+            if abs(s) < 1e-6 * np.linalg.norm(X[i] - v):
+                flag[a + t] = True
+            normals[a + t] = n if s >= 0 else -n
+    return normals, counts, flag
