@@ -603,6 +603,28 @@ si_status si_mesh_resolution(const si_scene* scene, const int32_t* idx, int64_t 
                              float* nn_out, double* mean_out, void* hip_stream);
 
 /*
+ * Normals of raw points, for scenes without them (the paper's oriented
+ * points come with known normals, Section 2.1): for each point p, the
+ * points x with |x - p| <= radius (p included; the test |x - p|^2 <= r^2 in
+ * float32), their covariance about their centroid (FP64 sums), and the unit
+ * eigenvector of its smallest eigenvalue, signed so that n . (p - v) >= 0
+ * for the viewpoint v (pointing away from it).  A neighbourhood whose
+ * covariance is a multiple of the identity (e.g. the point alone) gets
+ * (0, 0, 1) signed the same way.
+ *   points_xyz   device, M x 3 float32
+ *   viewpoint    host, 3 floats
+ *   normals_out  device, M x 3 float32 (may not alias points_xyz)
+ *   counts_out   device, M int32 neighbour counts, or NULL
+ * Builds a temporary grid of cell edge >= radius on hip_stream and frees it
+ * at the end, which synchronises the device.  Returns SI_E_INVALID for M
+ * out of [1, 2^31 - 1), a radius that is not positive and finite, or NULL
+ * or non-finite arguments.
+ */
+si_status si_estimate_normals(const float* points_xyz, int64_t M, float radius,
+                              const float* viewpoint, float* normals_out, int32_t* counts_out,
+                              void* hip_stream);
+
+/*
  * Spin-image matching: the normalised linear correlation coefficient of
  * every pair of images from two sets (the comparison by which spin images
  * are matched in object recognition, Johnson and Hebert, cited by the paper)

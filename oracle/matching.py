@@ -85,8 +85,10 @@ def best_match(A, B):
 # ---------------------------------------------------------------------------
 def estimate_normals(xyz, radius: float, viewpoint, idx=None, band: float = 1e-5,
                      gap: float = 1e-4, block: int = 128):
-    """(normals (n, 3), neighbour counts (n,), flagged (n,) bool) for the
-    chosen points, FP64, brute-force neighbourhoods."""
+    """(normals (n, 3), neighbour counts (n,), flagged (n,) bool, eigenvalue
+    gap (l1 - l0) / l2 (n,)) for the chosen points, FP64, brute-force
+    neighbourhoods.  The gap bounds how far rounding of the inputs can turn
+    the normal: about (relative error of the covariance) / gap radians."""
     X = np.asarray(xyz, dtype=np.float32).astype(np.float64)
     idx = np.arange(len(X)) if idx is None else np.asarray(idx, dtype=np.int64)
     r2 = float(np.float32(radius)) ** 2
@@ -94,6 +96,7 @@ def estimate_normals(xyz, radius: float, viewpoint, idx=None, band: float = 1e-5
     normals = np.zeros((len(idx), 3))
     counts = np.zeros(len(idx), dtype=np.int64)
     flag = np.zeros(len(idx), dtype=bool)
+    gaps = np.zeros(len(idx))
     for a in range(0, len(idx), block):
         q = idx[a:a + block]
         d2 = ((X[None, :, :] - X[q][:, None, :]) ** 2).sum(axis=2)
@@ -106,10 +109,11 @@ def estimate_normals(xyz, radius: float, viewpoint, idx=None, band: float = 1e-5
             C = (nb - c).T @ (nb - c) / len(nb)
             lam, vec = np.linalg.eigh(C)
             n = vec[:, 0]
-            if (lam[1] - lam[0]) < gap * max(lam[2], 1e-300):
+            gaps[a + t] = (lam[1] - lam[0]) / max(lam[2], 1e-300)
+            if gaps[a + t] < gap:
                 flag[a + t] = True
             s = float(n @ (X[i] - v))
             if abs(s) < 1e-6 * np.linalg.norm(X[i] - v):
                 flag[a + t] = True
             normals[a + t] = n if s >= 0 else -n
-    return normals, counts, flag
+    return normals, counts, flag, gaps

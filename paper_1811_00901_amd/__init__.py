@@ -28,7 +28,7 @@ __all__ = [
     "si_cost_model_predict_planner", "si_cost_model_gradient",
     "si_features_batched", "si_chunk_table", "si_learned_table", "si_support_radius", "si_abi_version",
     "si_set_kernel_events", "si_set_emulated_workers", "si_autotune", "si_peak_probe",
-    "si_mesh_resolution", "si_bin_size", "si_correlate",
+    "si_mesh_resolution", "si_bin_size", "si_correlate", "si_estimate_normals",
     "si_set_emulated_mode", "si_set_worker_weights", "si_rule_wf_chunk", "si_rule_awf_weight",
     "si_rule_af_chunk",
     "SCHED", "MODE", "PROBE",
@@ -142,6 +142,7 @@ def lib():
             "si_peak_probe": (I32, [I32, ctypes.POINTER(ctypes.c_double), P]),
             "si_mesh_resolution": (I32, [P, P, I64, P, ctypes.POINTER(ctypes.c_double), P]),
             "si_correlate": (I32, [P, I64, P, I64, I32, P, P, P, P]),
+            "si_estimate_normals": (I32, [P, I64, F, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -577,6 +578,22 @@ def si_mesh_resolution(scene: Scene, idx: torch.Tensor | None = None, nn_out: bo
                                     ctypes.c_void_p(nn.data_ptr()) if nn is not None else None,
                                     ctypes.byref(mean), _stream(stream)))
     return (float(mean.value), nn) if nn_out else float(mean.value)
+
+
+def si_estimate_normals(points: torch.Tensor, radius: float, viewpoint=(0.0, 0.0, 0.0),
+                        counts: bool = False, stream=None):
+    """Normals of device (M, 3) float32 points from the covariance of their
+    neighbours within ``radius``, pointing away from ``viewpoint``.  Returns
+    normals (M, 3) (and int32 neighbour counts with counts=True)."""
+    M = int(points.shape[0])
+    pp = _dev_ptr(points, torch.float32, "points", (M, 3))
+    out = torch.empty((M, 3), dtype=torch.float32, device=points.device)
+    cnt = torch.empty((M,), dtype=torch.int32, device=points.device) if counts else None
+    vp = (ctypes.c_float * 3)(*[float(v) for v in viewpoint])
+    _check(lib().si_estimate_normals(pp, M, float(radius), vp, ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(cnt.data_ptr()) if cnt is not None else None,
+                                     _stream(stream)))
+    return (out, cnt) if counts else out
 
 
 def si_bin_size(scene: Scene, factor: float, idx: torch.Tensor | None = None) -> float:

@@ -17,6 +17,10 @@
 //   its largest bin (R does not change under a positive scale) and rounded to
 //   fp16; its sums are taken from the rounded values, so R is the exact
 //   correlation of the rounded images up to fp32 accumulation.
+// * Normal estimation (si_estimate_normals), for points without normals
+//   (the paper's oriented points come with them): the eigenvector of the
+//   smallest eigenvalue of the covariance of each point's neighbours within a
+//   radius, signed away from a viewpoint.
 #include "si_internal.h"
 
 #include <math.h>
@@ -278,6 +282,101 @@ __global__ void k_corr_best(const unsigned long long* __restrict__ best, int64_t
 
 size_t rup256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// ------------------------------------------------------ normal estimation --
+// Unit eigenvector of the smallest eigenvalue of the symmetric 3 x 3 matrix
+// [[a00 a01 a02] [a01 a11 a12] [a02 a12 a22]]: the eigenvalue from the
+// trigonometric closed form of the characteristic cubic, the vector as the
+// longest cross product of two rows of A - l0 I (each row is orthogonal to
+// it).  A multiple of the identity has no preferred direction: e_z.
+__device__ void smallest_eigvec(double a00, double a01, double a02, double a11, double a12,
+                                double a22, double n[3]) {
+    const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+    const double q = (a00 + a11 + a22) / 3.0;
+    const double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+    const double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * p1;
+    n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+    if (!(p2 > 0.0)) return;
+    const double p = sqrt(p2 / 6.0);
+    const double c00 = b00 / p, c11 = b11 / p, c22 = b22 / p;
+    const double c01 = a01 / p, c02 = a02 / p, c12 = a12 / p;
+    double r = 0.5 * (c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) +
+                      c02 * (c01 * c12 - c11 * c02));
+    r = fmin(1.0, fmax(-1.0, r));
+    const double phi = acos(r) / 3.0;
+    const double l0 = q + 2.0 * p * cos(phi + 2.0943951023931957);  // + 2 pi / 3
+    const double r0[3] = {a00 - l0, a01, a02};
+    const double r1[3] = {a01, a11 - l0, a12};
+    const double r2[3] = {a02, a12, a22 - l0};
+    auto cross = [](const double* u, const double* v, double* w) {
+        w[0] = u[1] * v[2] - u[2] * v[1];
+        w[1] = u[2] * v[0] - u[0] * v[2];
+        w[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    double c[3][3];
+    cross(r0, r1, c[0]);
+    cross(r0, r2, c[1]);
+    cross(r1, r2, c[2]);
+    int best = 0;
+    double bn = -1.0;
+    for (int k = 0; k < 3; ++k) {
+        const double m = c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2];
+        if (m > bn) { bn = m; best = k; }
+    }
+    if (!(bn > 0.0)) return;
+    const double inv = 1.0 / sqrt(bn);
+    n[0] = c[best][0] * inv; n[1] = c[best][1] * inv; n[2] = c[best][2] * inv;
+}
+
+// One thread per point in the grid's sorted order (neighbouring threads share
+// cells): the points within r among the 27 cells around it (cell edge >= r),
+// their FP64 sums relative to the point, covariance about their centroid, the
+// smallest-eigenvalue eigenvector signed away from the viewpoint, written at
+// the point's original index.
+__global__ void __launch_bounds__(256) k_normals(SceneView sc, float r, float vx, float vy,
+                                                 float vz, float* __restrict__ out,
+                                                 int32_t* __restrict__ counts) {
+    const int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= sc.M) return;
+    const float4 p = sc.pos[sp];
+    const int o = __float_as_int(sc.nrm[sp].w);
+    const float r2 = r * r;
+    const int cell = __float_as_int(p.w);
+    const int c0 = cell % sc.dims[0];
+    const int c1 = (cell / sc.dims[0]) % sc.dims[1];
+    const int c2 = cell / (sc.dims[0] * sc.dims[1]);
+    double n = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+    double sxx = 0.0, sxy = 0.0, sxz = 0.0, syy = 0.0, syz = 0.0, szz = 0.0;
+    for (int z = max(c2 - 1, 0); z <= min(c2 + 1, sc.dims[2] - 1); ++z)
+        for (int y = max(c1 - 1, 0); y <= min(c1 + 1, sc.dims[1] - 1); ++y) {
+            const int x0 = max(c0 - 1, 0), x1 = min(c0 + 1, sc.dims[0] - 1);
+            const int base = (z * sc.dims[1] + y) * sc.dims[0];
+            // the cells x0..x1 of a row are one run of the sorted points
+            const int a = sc.sub_start[(base + x0) * kSubX], b = sc.sub_start[(base + x1 + 1) * kSubX];
+            for (int j = a; j < b; ++j) {
+                const float4 q = sc.pos[j];
+                const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+                if (fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= r2) {
+                    const double ex = dx, ey = dy, ez = dz;
+                    n += 1.0;
+                    sx += ex; sy += ey; sz += ez;
+                    sxx += ex * ex; sxy += ex * ey; sxz += ex * ez;
+                    syy += ey * ey; syz += ey * ez; szz += ez * ez;
+                }
+            }
+        }
+    const double mx = sx / n, my = sy / n, mz = sz / n;
+    double v[3];
+    smallest_eigvec(sxx / n - mx * mx, sxy / n - mx * my, sxz / n - mx * mz, syy / n - my * my,
+                    syz / n - my * mz, szz / n - mz * mz, v);
+    const double s = v[0] * ((double)p.x - vx) + v[1] * ((double)p.y - vy) +
+                     v[2] * ((double)p.z - vz);
+    const double sg = s < 0.0 ? -1.0 : 1.0;
+    out[3 * (int64_t)o] = (float)(sg * v[0]);
+    out[3 * (int64_t)o + 1] = (float)(sg * v[1]);
+    out[3 * (int64_t)o + 2] = (float)(sg * v[2]);
+    if (counts) counts[o] = (int32_t)n;
+}
+
 }  // namespace
 }  // namespace si
 
@@ -362,5 +461,32 @@ extern "C" si_status si_correlate(const float* A, int64_t n_a, const float* B, i
     }
     (void)hipFreeAsync(m, s);
     if (e != hipSuccess) return hip_fail(e, "spin-image correlation");
+    return SI_OK;
+}
+
+extern "C" si_status si_estimate_normals(const float* points_xyz, int64_t M, float radius,
+                                         const float* viewpoint, float* normals_out,
+                                         int32_t* counts_out, void* hip_stream) {
+    if (!points_xyz || !normals_out) return fail(SI_E_INVALID, "points or normals_out is NULL");
+    if (!viewpoint) return fail(SI_E_INVALID, "viewpoint is NULL");
+    if (M <= 0 || M >= INT32_MAX) return fail(SI_E_INVALID, "M must be in [1, 2^31 - 1)");
+    if (!isfinite(radius) || !(radius > 0.0f)) return fail(SI_E_INVALID, "radius must be > 0");
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(viewpoint[k])) return fail(SI_E_INVALID, "viewpoint must be finite");
+    // a grid whose cell edge is at least r (the scene's grid for a support
+    // radius of 3r); the points stand in for the normals it does not read
+    si_scene* sc = nullptr;
+    si_status rc = si_build_scene(points_xyz, points_xyz, M, 3.0f * radius, hip_stream, &sc);
+    if (rc != SI_OK) return rc;
+    if (sc->h < (double)radius) {
+        si_free_scene(sc);
+        return fail(SI_E_DEVICE, "normal estimation: grid cell below the radius");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_normals, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, view_of(*sc),
+                       radius, viewpoint[0], viewpoint[1], viewpoint[2], normals_out, counts_out);
+    hipError_t e = hipGetLastError();
+    si_free_scene(sc);  // waits for the kernel
+    if (e != hipSuccess) return hip_fail(e, "normal estimation");
     return SI_OK;
 }

@@ -156,3 +156,46 @@ def test_correlation_errors(env):
         si.si_correlate(A, torch.rand((10, 32), device="cuda"))
     R, bi, br = si.si_correlate(A[:0], A)
     assert R.shape == (0, 10)
+
+
+@pytest.mark.parametrize("case", ["sphere", "prims"])
+def test_normals_vs_oracle(env, case):
+    """Estimated normals against the FP64 oracle on the same neighbourhoods:
+    neighbour counts exact and normals within 2e-6 / gap + 1e-6 radians
+    (gap = (l1 - l0) / l2 of the covariance) for every point the oracle does
+    not flag (a neighbour within 1e-5 of the radius, a near-tie of the two
+    smallest eigenvalues, or a sign left undefined by the viewpoint)."""
+    print(f"\n[case] normals {case}", flush=True)
+    torch, si, _, Mt = env
+    if case == "sphere":
+        xyz, true_n = sg.sphere_scene(4000, seed=3)
+        radius, view, q = 0.12, (0.0, 0.0, 0.0), np.arange(0, 4000, 4)
+    else:
+        xyz, true_n = sg.config_scene("prims100k", M=40000)
+        radius, view = 0.15, (5.0, 5.0, -20.0)
+        q = np.sort(np.random.default_rng(4).choice(40000, 1500, replace=False))
+    n_gpu, c_gpu = si.si_estimate_normals(dev(torch, xyz), radius, view, counts=True)
+    n_gpu = n_gpu.cpu().numpy()[q].astype(np.float64)
+    c_gpu = c_gpu.cpu().numpy()[q]
+    n_ref, c_ref, flag, gap = Mt.estimate_normals(xyz, radius, view, idx=q)
+    ok = ~flag
+    assert ok.mean() > 0.9
+    np.testing.assert_array_equal(c_gpu[ok], c_ref[ok])
+    sin = np.linalg.norm(np.cross(n_gpu, n_ref), axis=1)
+    tol = 2e-6 / np.maximum(gap, 1e-300) + 1e-6
+    assert np.all(sin[ok] <= tol[ok]), float((sin - tol)[ok].max())
+    assert np.all((n_gpu * n_ref).sum(1)[ok] > 0)   # same sign
+    np.testing.assert_allclose(np.linalg.norm(n_gpu, axis=1), 1.0, atol=1e-6)
+    if case == "sphere":   # outward; about 14 noisy neighbours: a few degrees off radial
+        dots = (n_gpu * true_n[q]).sum(1)
+        assert np.all(dots > 0) and np.median(dots) > 0.99
+
+
+def test_normals_errors(env):
+    torch, si, _, _ = env
+    X = torch.rand((100, 3), device="cuda")
+    for r in (0.0, -1.0, float("nan")):
+        with pytest.raises(si.SiError):
+            si.si_estimate_normals(X, r)
+    with pytest.raises(si.SiError):
+        si.si_estimate_normals(X, 0.1, (0.0, float("inf"), 0.0))

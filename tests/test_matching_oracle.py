@@ -75,14 +75,14 @@ def test_normals_of_a_plane_and_a_sphere():
     rng = np.random.default_rng(8)
     # points on the plane z = 2: the normal is e_z, away from a viewpoint below
     P = np.c_[rng.uniform(0, 1, 400), rng.uniform(0, 1, 400), np.full(400, 2.0)].astype(np.float32)
-    n, c, f = Mt.estimate_normals(P, 0.2, (0.5, 0.5, -5.0))
+    n, c, f, _ = Mt.estimate_normals(P, 0.2, (0.5, 0.5, -5.0))
     ok = ~f
     assert ok.sum() > 350
     np.testing.assert_allclose(n[ok], np.tile([0, 0, 1.0], (ok.sum(), 1)), atol=1e-9)
     # a unit sphere sampled densely: normals radial (outward from the centre)
     g = rng.normal(size=(3000, 3))
     S = (g / np.linalg.norm(g, axis=1, keepdims=True)).astype(np.float32)
-    n, c, f = Mt.estimate_normals(S, 0.15, (0, 0, 0), idx=np.arange(300))
+    n, c, f, _ = Mt.estimate_normals(S, 0.15, (0, 0, 0), idx=np.arange(300))
     cosang = (n * S[:300]).sum(1) / np.linalg.norm(S[:300], axis=1)
     assert np.all(cosang[~f] > 0.995)
     assert np.all(c >= 3)
@@ -91,7 +91,7 @@ def test_normals_of_a_plane_and_a_sphere():
 def test_normals_counts_equal_brute_radius_counts():
     rng = np.random.default_rng(9)
     X = rng.uniform(0, 1, (500, 3)).astype(np.float32)
-    _, c, _ = Mt.estimate_normals(X, 0.15, (0, 0, -1.0))
+    _, c, _, _ = Mt.estimate_normals(X, 0.15, (0, 0, -1.0))
     from scipy.spatial import cKDTree
     t = cKDTree(X.astype(np.float64))
     ref = np.array([len(t.query_ball_point(p, 0.15 * (1 + 1e-12))) for p in X.astype(np.float64)])
