@@ -26,6 +26,10 @@
  *     result back to the host it synchronises the stream, and says so.
  *   - The caller owns every buffer it passes in.  The library owns scenes and
  *     cost models until the matching si_free_* call.
+ *   - Chunk tables are built on the host once per schedule and device, then
+ *     uploaded on the stream of their first use (from pinned staging, without
+ *     waiting) and cached (64 per device; the least recently used is freed
+ *     once the launches that read it are done).
  *   - Distinct scenes, models and streams may be used from different threads.
  *     Calls that run concurrently on different streams share a pool of 64
  *     work-counter slots per device, so at most 64 generation launches may be

@@ -236,7 +236,7 @@ int64_t chunk_sizes(int kind, int64_t N, int P, int min_chunk, float divisor, in
 }
 
 si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk,
-                           float divisor, Chunk** out, int* n_out) {
+                           float divisor, Chunk** out, int* n_out, hipStream_t s, void** entry) {
     // the parameter: FAC's divisor (0 = 2), FAC_PROB's cost variation (0 kept)
     uint32_t dbits;
     const float dv = kind == SI_SCHED_FAC_PROB ? divisor : divisor > 0.0f ? divisor : 2.0f;
@@ -245,36 +245,81 @@ si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk,
     const bool param = kk == SI_SCHED_FAC || kk == SI_SCHED_FAC_PROB;
     auto key = std::make_tuple(kk, N, P, kind == SI_SCHED_STATIC ? 0 : std::max(1, min_chunk),
                                param ? dbits : 0u);
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        auto it = st->tables.find(key);
-        if (it != st->tables.end()) {
-            *out = it->second.first;
-            *n_out = it->second.second;
-            return SI_OK;
-        }
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = st->tables.find(key);
+    if (it != st->tables.end()) {
+        DeviceState::Table& t = it->second;
+        t.tick = ++st->table_tick;
+        SI_HIP(hipStreamWaitEvent(s, t.ready, 0));  // uploaded on another stream
+        *out = t.dev;
+        *n_out = t.n;
+        *entry = &t;
+        return SI_OK;
     }
     const int64_t n = chunk_sizes(kind, N, P, min_chunk, dv, nullptr, 0);
     if (n > INT32_MAX) return fail(SI_E_INVALID, "schedule has too many chunks");
     std::vector<int64_t> starts(n + 1);
     chunk_sizes(kind, N, P, min_chunk, dv, starts.data(), n + 1);
-    std::vector<Chunk> h(n);
+    if (st->tables.size() >= 64) {
+        // evict the least recently used table once the work that reads it is done
+        auto lru = st->tables.begin();
+        for (auto i = st->tables.begin(); i != st->tables.end(); ++i)
+            if (i->second.tick < lru->second.tick) lru = i;
+        DeviceState::Table& t = lru->second;
+        for (auto& u : t.uses) {
+            SI_HIP(hipEventSynchronize(u.second));
+            (void)hipEventDestroy(u.second);
+        }
+        SI_HIP(hipEventSynchronize(t.ready));
+        (void)hipEventDestroy(t.ready);
+        SI_HIP(hipFreeAsync(t.dev, s));
+        st->tables.erase(lru);
+    }
+    // the host table into the pinned staging buffer (after its previous copy)
+    const size_t bytes = sizeof(Chunk) * (size_t)std::max<int64_t>(n, 1);
+    if (!st->stage_done) SI_HIP(hipEventCreateWithFlags(&st->stage_done, hipEventDisableTiming));
+    SI_HIP(hipEventSynchronize(st->stage_done));
+    if (st->stage_bytes < bytes) {
+        if (st->stage) SI_HIP(hipHostFree(st->stage));
+        st->stage = nullptr;
+        st->stage_bytes = 0;
+        const size_t cap = std::max(bytes, (size_t)1 << 20);
+        SI_HIP(hipHostMalloc(&st->stage, cap, hipHostMallocDefault));
+        st->stage_bytes = cap;
+    }
+    Chunk* h = static_cast<Chunk*>(st->stage);
     for (int64_t i = 0; i < n; ++i) {
         h[i].item = 0;
         h[i].start = (int32_t)starts[i];
         h[i].end = (int32_t)starts[i + 1];
     }
-    Chunk* dptr = nullptr;
-    SI_HIP(hipMalloc(&dptr, sizeof(Chunk) * std::max<int64_t>(n, 1)));
-    if (n) SI_HIP(hipMemcpy(dptr, h.data(), sizeof(Chunk) * n, hipMemcpyHostToDevice));
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (st->tables.size() >= 64) {  // keep the cache small
-        for (auto& kv : st->tables) (void)hipFree(kv.second.first);
-        st->tables.clear();
+    DeviceState::Table t;
+    t.n = (int)n;
+    t.tick = ++st->table_tick;
+    SI_HIP(pool_alloc((void**)&t.dev, bytes, s));
+    hipError_t e = n ? hipMemcpyAsync(t.dev, h, sizeof(Chunk) * n, hipMemcpyHostToDevice, s)
+                     : hipSuccess;
+    if (e == hipSuccess) e = hipEventRecord(st->stage_done, s);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(t.ready, s);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(t.dev, s);
+        if (t.ready) (void)hipEventDestroy(t.ready);
+        return hip_fail(e, "chunk table upload");
     }
-    st->tables[key] = {dptr, (int)n};
-    *out = dptr;
-    *n_out = (int)n;
+    DeviceState::Table& in = st->tables[key] = t;
+    *out = in.dev;
+    *n_out = in.n;
+    *entry = &in;
+    return SI_OK;
+}
+
+si_status table_used(DeviceState* st, void* entry, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceState::Table* t = static_cast<DeviceState::Table*>(entry);
+    hipEvent_t& ev = t->uses[s];
+    if (!ev) SI_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    SI_HIP(hipEventRecord(ev, s));
     return SI_OK;
 }
 
@@ -988,6 +1033,7 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     }
     int32_t* order_mem = nullptr;
     char* rule_mem = nullptr;
+    void* table_entry = nullptr;
     if (kind >= SI_SCHED_WF) {
         // claims sized by the workgroups: FAC2's batch chunks by value, the
         // WF weights and the AWF / AF sums in one stream-ordered block
@@ -999,7 +1045,7 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     if (kind != SI_SCHED_LEARNED) {
         if (kind < SI_SCHED_WF) {
             rc = get_table(st, kind, N, n_wg, sched->min_chunk, sched->fac_divisor, &chunks,
-                           &n_chunks);
+                           &n_chunks, s, &table_entry);
             if (rc != SI_OK) return rc;
         }
         if (sched->order != SI_ORDER_GIVEN && scene->n_cells > 1) {
@@ -1016,6 +1062,10 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     d.n_chunks = n_chunks;
     d.dynamic = kind == SI_SCHED_STATIC ? 0 : 1;
     rc = run_launch(st, d, n_wg, w2, stats, s, kind);
+    if (table_entry) {
+        const si_status r2 = table_used(st, table_entry, s);
+        if (rc == SI_OK) rc = r2;
+    }
     if (order_mem) (void)hipFreeAsync(order_mem, s);
     if (learned_mem) (void)hipFreeAsync(learned_mem, s);
     if (rule_mem) (void)hipFreeAsync(rule_mem, s);

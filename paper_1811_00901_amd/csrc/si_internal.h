@@ -212,8 +212,24 @@ struct DeviceState {
     int max_lds = 65536;           // bytes of LDS one workgroup may allocate
     uint32_t* counters = nullptr;  // work-counter slots (a static device array), zero between launches
     uint32_t next_slot = 0;
-    // chunk-table cache: (kind, N, P, min_chunk, divisor bits) -> device table
-    std::map<std::tuple<int, int64_t, int, int, uint32_t>, std::pair<Chunk*, int>> tables;
+    // chunk-table cache: (kind, N, P, min_chunk, divisor bits) -> device table,
+    // uploaded on the stream of its first use (ready: recorded after the
+    // copy), with an event per stream recorded after each launch that read
+    // it; the least recently used entry is evicted once that stream work is
+    // done
+    struct Table {
+        Chunk* dev = nullptr;
+        int n = 0;
+        hipEvent_t ready = nullptr;
+        std::map<hipStream_t, hipEvent_t> uses;
+        uint64_t tick = 0;
+    };
+    std::map<std::tuple<int, int64_t, int, int, uint32_t>, Table> tables;
+    uint64_t table_tick = 0;
+    // pinned staging of table uploads (one buffer, reused once its last copy is done)
+    void* stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t stage_done = nullptr;
     // spin-kernel workgroups per CU: (max W^2, group) -> count
     std::map<std::pair<int, int>, int> wg_per_cu;
 };
@@ -242,8 +258,13 @@ int fit_group(DeviceState* st, int group, int max_w2);
 int auto_workgroups(DeviceState* st, int max_w2, int group);
 si_status cell_order(const Scene& sc, const int32_t* oriented, int64_t N, hipStream_t s,
                      int32_t** mem_out, const int32_t** perm_out);
+// The chunk table of a schedule on the device, ready for work queued on s
+// (uploaded there on first use, or waited for if another stream uploaded it);
+// *entry identifies it for table_used.
 si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk, float divisor,
-                    Chunk** out, int* n_out);
+                    Chunk** out, int* n_out, hipStream_t s, void** entry);
+// Record that work queued on s up to now reads the table `entry`.
+si_status table_used(DeviceState* st, void* entry, hipStream_t s);
 si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_stats* stats,
                      hipStream_t s, int sched_used);
 // Learned schedule of one scene, computed on the device in stream order:

@@ -383,6 +383,46 @@ def test_generation_is_asynchronous_on_its_stream(env):
     side.synchronize()
     assert queued_before_finish
     assert torch.equal(img, ref_img) and torch.equal(cnt, ref_cnt)
+    # a table the library has never built: its upload is queued on the side
+    # stream too (pinned staging, no host wait), then the default stream
+    # reuses it after the side stream's copy (the ready event)
+    fresh = si.Sched("gss", num_workgroups=777)
+    img2 = torch.empty_like(ref_img)
+    cnt2 = torch.empty_like(ref_cnt)
+    with torch.cuda.stream(side):
+        for _ in range(6):
+            si.si_generate(scene, idx, params, si.Sched("fac"), img, cnt, stream=side)
+        si.si_generate(scene, idx, params, fresh, img2, cnt2, stream=side)
+        done.record(side)
+        queued_first_use = not done.query()
+    img3, cnt3, _ = si.si_generate(scene, idx, params, fresh)
+    torch.cuda.synchronize()
+    assert queued_first_use
+    assert torch.equal(img2, ref_img) and torch.equal(cnt2, ref_cnt)
+    assert torch.equal(img3, ref_img) and torch.equal(cnt3, ref_cnt)
+
+
+def test_table_cache_eviction(env):
+    """More distinct schedules than the 64-entry table cache holds: the least
+    recently used tables are evicted one at a time once their launches are
+    done, and every result stays exact."""
+    print_case("table cache eviction")
+    torch, si, _ = env
+    xyz, nrm = sg.config_scene("prims100k", M=4000)
+    params = si.Params(16, 0.03, S60)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(params))
+    idx = to_dev(torch, np.arange(4000, dtype=np.int32))
+    ref_img, ref_cnt, _ = si.si_generate(scene, idx, params, si.Sched("fac"))
+    ref_img, ref_cnt = ref_img.clone(), ref_cnt.clone()
+    side = torch.cuda.Stream()
+    for k in range(80):
+        st = side if k % 3 == 0 else torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            img, cnt, _ = si.si_generate(scene, idx, params,
+                                         si.Sched("gss" if k % 2 else "fac", num_workgroups=64 + k),
+                                         stream=st)
+        st.synchronize()
+        assert torch.equal(img, ref_img) and torch.equal(cnt, ref_cnt), k
 
 
 def test_overflow_path_identical(env):
