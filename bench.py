@@ -18,6 +18,10 @@ Also reported (outside the timed steps):
     its speedup over STATIC and a bit-identity check of the images;
   * the learned cost model: trained on the in-support counts logged on the
     100k-point primitives scene and on this scene (80/20 split), held-out MAE;
+  * the schedules under emulated heterogeneous workers (half the workgroups
+    2x slower, idling or busy), and the claim-order effect of GSS;
+  * next to the path: mesh resolution, normal estimation and spin-image
+    matching (correlation on the matrix cores, against its roofline);
   * batching: 256 primitive scenes of log-uniform size in [1k, 200k] points
     and mixed W in {16, 32, 64}, one autotuned HIP-graph launch against a loop
     of 256 si_generate calls;
@@ -26,7 +30,7 @@ Also reported (outside the timed steps):
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
                     [--no-schedules] [--no-batch] [--no-extent] [--no-paper-shape]
-                    [--copy-calibration BYTES]
+                    [--no-adjacent] [--copy-calibration BYTES]
 """
 from __future__ import annotations
 
@@ -99,6 +103,8 @@ def parse():
     ap.add_argument("--no-schedules", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-paper-shape", action="store_true")
+    ap.add_argument("--no-adjacent", action="store_true",
+                    help="skip mesh resolution, normal estimation and spin-image matching")
     ap.add_argument("--no-extent", action="store_true",
                     help="stop after the timed steps (profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -176,9 +182,18 @@ def train_cost_model(torch, si, sg, main):
     curve = si.si_cost_model_train(model, f_tr, c_tr, epochs=4, lr=2e-3, batch=4096)
     train_s = time.perf_counter() - t
     mae = float((si.si_cost_model_predict(model, f_te).double() - y_te).abs().mean())
+    # baselines on the same held-out samples: the training mean, and the
+    # occupancy sum (count proportional to the 27-cell candidate count,
+    # feature 10 = log1p of it, the ratio fitted on the training samples)
+    y_tr = c_tr.to(torch.float64)
+    mae_mean = float((y_tr.mean() - y_te).abs().mean())
+    occ_tr = torch.expm1(f_tr[:, 10].double())
+    occ_te = torch.expm1(f_te[:, 10].double())
+    mae_occ = float((y_tr.sum() / occ_tr.sum() * occ_te - y_te).abs().mean())
     info = {"samples_train": n_tr, "samples_test": n - n_tr, "epochs": 4, "batch": 4096,
             "lr": 2e-3, "train_s": train_s, "loss_curve": [float(x) for x in curve],
-            "mae_test": mae, "mae_test_untrained": mae0, "mean_count_test": float(y_te.mean()),
+            "mae_test": mae, "mae_test_untrained": mae0, "mae_test_train_mean": mae_mean,
+            "mae_test_occupancy_sum": mae_occ, "mean_count_test": float(y_te.mean()),
             "data": "counts logged on prims100k (65,536 images) + clustered2m (2,000,000 images)"}
     sc2.free()
     return model, info
@@ -265,6 +280,68 @@ def batched(torch, si, sg, model):
                      "fac_divisor": tuned.fac_divisor, "min_chunk": tuned.min_chunk}}
     for it in items:
         it[0].free()
+    return out
+
+
+# dense fp16 matrix-core peak of the MI355X (no sparsity)
+PEAK_MFMA_FP16 = 2.5e15
+
+
+def adjacent_workloads(torch, si, sg, scene, d_xyz, stream):
+    """Mesh resolution (every point of the main scene), normal estimation
+    (every point, radius 3x the resolution) and spin-image matching (all
+    65,536 images of the 100k-point scene against each other, best match
+    per image, then against a fifth of them with every R stored)."""
+    out = {}
+
+    def ev_time(fn, reps=5):
+        ts = []
+        for r in range(1 + reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        return spread(ts)
+
+    res = si.si_mesh_resolution(scene)
+    out["mesh_resolution"] = {"workload": "clustered2m, nearest other point of all 2,000,000",
+                              "mean_nn_distance": res,
+                              "ms": ev_time(lambda: si.si_mesh_resolution(scene), reps=3)}
+    r_n = 3.0 * res
+    out["normals"] = {"workload": f"clustered2m, all 2,000,000 points, radius {r_n:.5f} "
+                                  "(3x the mesh resolution)",
+                      "ms": ev_time(lambda: si.si_estimate_normals(d_xyz, r_n, (20.0, 20.0, 20.0)),
+                                    reps=3)}
+    cfg = sg.CONFIGS["prims100k"]
+    xyz2, nrm2 = sg.config_scene("prims100k")
+    p2 = si.Params(cfg.W, cfg.bin, cfg.support_angle)
+    sc2 = si.si_build_scene(torch.from_numpy(xyz2).cuda(), torch.from_numpy(nrm2).cuda(),
+                            si.si_support_radius(p2))
+    idx2 = torch.arange(cfg.N, dtype=torch.int32, device="cuda")
+    A, _, _ = si.si_generate(sc2, idx2, p2, si.Sched("fac"))
+    n, bins = int(A.shape[0]), cfg.W * cfg.W
+    ms_best = ev_time(lambda: si.si_correlate(A, A, R=False))
+    _, bi, br = si.si_correlate(A, A, R=False)
+    q = A[: n // 5]
+    ms_full = ev_time(lambda: si.si_correlate(q, A, R=True, best=False), reps=3)
+    flops = 2.0 * n * n * bins
+    ach = flops / (ms_best["median"] * 1e-3)
+    out["correlation"] = {
+        "workload": f"prims100k: {n} spin images (W={cfg.W}) against each other, best match "
+                    f"per image; fp16 operands, fp32 sums, on the matrix cores",
+        "ms": ms_best, "full_R_ms": ms_full,
+        "full_R_workload": f"{n // 5} x {n} pairs, every R stored ({4 * (n // 5) * n / 1e9:.1f} GB)",
+        "self_matched": float((bi.cpu() == torch.arange(n)).float().mean()),
+        "roofline": {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_MFMA_FP16 / 1e12,
+                     "unit": "TFLOP/s", "frac": ach / PEAK_MFMA_FP16,
+                     "flops_per_call": flops,
+                     "note": "whole call (fp16 conversion of both sets, then the GEMM with "
+                             "its epilogue); algorithmic flops 2 n_a n_b N"}}
+    del A, q
+    sc2.free()
     return out
 
 
@@ -493,6 +570,9 @@ def main():
         cost_cv = float(cost.std() / cost.mean())
         del cost
         runs += [("tss", "tss", "spread"), ("fac_prob", "fac_prob", "spread")]
+        # three whose chunk the claiming workgroup sizes (instrumented build of
+        # the kernel: per-group timing): weighted, adaptive weighted, adaptive
+        runs += [("wf", "wf", "spread"), ("awf", "awf", "spread"), ("af", "af", "spread")]
         for name, kind, order in runs:
             sch = si.Sched(kind, model=model if kind == "learned" else None, order=order,
                            fac_divisor=cost_cv if kind == "fac_prob" else 0.0)
@@ -522,9 +602,19 @@ def main():
                 f"imbalance {sched_res[name]['imbalance']:.3f}")
         sched_res["fac_prob"]["cost_cv"] = cost_cv
         sched_res["fac_prob"]["cost_cv_source"] = cv_source
+        # the learned schedule against FAC2, same workgroups and group size
+        if "learned" in sched_res:
+            lk, fk = sched_res["learned"], sched_res["fac"]
+            sched_res["learned_vs_fac"] = {
+                "kernel_ratio": lk["kernel_ms"]["median"] / fk["kernel_ms"]["median"],
+                "call_ratio": lk["call_ms"]["median"] / fk["call_ms"]["median"],
+                "plan_ms": lk["call_ms"]["median"] - lk["kernel_ms"]["median"] -
+                           (fk["call_ms"]["median"] - fk["kernel_ms"]["median"])}
         base = sched_res["static"]["call_ms"]["median"]
         base_cell = sched_res["static_cell"]["call_ms"]["median"]
         for k in sched_res:
+            if "call_ms" not in sched_res[k]:
+                continue
             sched_res[k]["speedup_vs_static"] = base / sched_res[k]["call_ms"]["median"]
             if k.endswith("_cell"):
                 sched_res[k]["speedup_vs_static_cell"] = base_cell / sched_res[k]["call_ms"]["median"]
@@ -533,33 +623,62 @@ def main():
     # ---- heterogeneous workers, emulated (the paper's Section 5.2 setting) ----
     hetero = None
     if not args.no_schedules:
-        hetero = {"setting": "every 2nd workgroup 2x slower (it idles after each chunk for "
-                             "the chunk's own time); same images",
+        kinds = ("static", "ss", "gss", "fac", "tss", "fac_prob", "learned", "wf", "awf", "af")
+        hetero = {"setting": "every 2nd workgroup 2x slower: after each group of images it "
+                             "spends the group's own time again, idling (CU free) or with every "
+                             "thread spinning on arithmetic (CU busy); same images",
                   "slowdown": 2.0, "every": 2}
+
+        def hetero_run(kind, reps=5):
+            sch = si.Sched(kind, model=model if kind == "learned" else None,
+                           fac_divisor=cost_cv if kind == "fac_prob" else 0.0)
+            ks, ok = [], True
+            for r in range(2 + reps):
+                _, _, s2 = si.si_generate(scene, idx, params, sch, images, counts, stats=True)
+                ok = ok and bool(torch.equal(counts, ref_cnt))
+                if r >= 2:
+                    ks.append(s2["kernel_ms"])
+            busy = s2["wg_busy_ns"].astype(np.float64)
+            return {"kernel_ms": spread(ks), "counts_identical": ok,
+                    "imbalance": float(busy.max() / max(busy.mean(), 1.0))}
+
         try:
             si.si_set_emulated_workers(2, 2.0)
-            for kind in ("static", "ss", "gss", "fac", "tss", "fac_prob", "learned"):
-                sch = si.Sched(kind, model=model if kind == "learned" else None,
-                               fac_divisor=cost_cv if kind == "fac_prob" else 0.0)
-                ks, ok = [], True
-                for r in range(2 + 5):
-                    _, _, s2 = si.si_generate(scene, idx, params, sch, images, counts, stats=True)
-                    ok = ok and bool(torch.equal(counts, ref_cnt))
-                    if r >= 2:
-                        ks.append(s2["kernel_ms"])
-                busy = s2["wg_busy_ns"].astype(np.float64)
-                hetero[kind] = {"kernel_ms": spread(ks), "counts_identical": ok,
-                                "imbalance": float(busy.max() / max(busy.mean(), 1.0))}
+            for model_name, busy_mode in (("idle", False), ("busy", True)):
+                si.si_set_emulated_mode(busy_mode, "every")
+                res = {k: hetero_run(k) for k in kinds}
+                for k in kinds:
+                    res[k]["speedup_vs_static"] = (res["static"]["kernel_ms"]["median"] /
+                                                   res[k]["kernel_ms"]["median"])
+                hetero[model_name] = res
+                log(f"[bench] heterogeneous ({model_name}): " + ", ".join(
+                    f"{k} {res[k]['kernel_ms']['median']:.2f} ms" for k in kinds))
+            # the claim-order effect (Section 5.2): slow workgroups first or
+            # last to claim, GSS against FAC2
+            order = {}
+            for model_name, busy_mode in (("idle", False), ("busy", True)):
+                o = {}
+                for place in ("first", "last"):
+                    si.si_set_emulated_mode(busy_mode, place)
+                    for k in ("gss", "fac"):
+                        o[f"{k}_{place}"] = hetero_run(k, reps=3)["kernel_ms"]
+                for k in ("gss", "fac"):
+                    o[f"{k}_first_over_last"] = o[f"{k}_first"]["median"] / o[f"{k}_last"]["median"]
+                order[model_name] = o
+                log(f"[bench] claim order ({model_name}): GSS first/last "
+                    f"{o['gss_first_over_last']:.3f}, FAC {o['fac_first_over_last']:.3f}")
+            hetero["claim_order"] = order
         finally:
             si.si_set_emulated_workers(0, 1.0)
-        for kind in ("static", "ss", "gss", "fac", "tss", "fac_prob", "learned"):
-            hetero[kind]["speedup_vs_static"] = (hetero["static"]["kernel_ms"]["median"] /
-                                                 hetero[kind]["kernel_ms"]["median"])
-        log("[bench] heterogeneous: " + ", ".join(
-            f"{k} {hetero[k]['kernel_ms']['median']:.2f} ms"
-            for k in ("static", "ss", "gss", "fac", "tss", "fac_prob", "learned")))
+            si.si_set_emulated_mode(False, "every")
     torch.cuda.synchronize()
     del ref_img, ref_cnt
+
+    # ---- next to the path: mesh resolution, normals, spin-image matching ----
+    adjacent = None
+    if not args.no_adjacent:
+        adjacent = adjacent_workloads(torch, si, sg, scene, d_xyz, stream)
+        log(f"[bench] adjacent: {adjacent}")
 
     # ---- batching ----
     batch = None
@@ -640,6 +759,7 @@ def main():
         "schedules": sched_res,
         "heterogeneous_emulated": hetero,
         "cost_model": cm_info,
+        "adjacent": adjacent,
         "batched": batch,
         "paper_shape": paper,
         "roofline": roofline,

@@ -112,7 +112,7 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 128;  // rows of A and of B per workgroup tile
-constexpr int kBK = 64;     // K (bins) per LDS stage
+constexpr int kBK = 32;     // K (bins) per LDS stage
 constexpr int kLdsRow = kBK + 8;  // halves per LDS row (16 bytes of padding)
 
 // One wave per image: scale by the largest bin, round to fp16 into a row of
@@ -159,10 +159,13 @@ __device__ __forceinline__ unsigned long long best_key(float r, int j) {
 // 64 x 64 quarter as 4 x 4 products of 16 x 16 (v_mfma_f32_16x16x32_f16:
 // lane l holds row l % 16 of the A operand and of B's image at K = 8 (l / 16)
 // .. + 7, and receives column l % 16, rows 4 (l / 16) .. + 3 of the result).
-// Operands stage through LDS 64 bins at a time; the next stage's global loads
-// are issued before the current one's products.  Tiles are numbered so that
-// consecutive workgroups of one XCD (workgroup ids congruent mod 8) take
-// consecutive tiles of one A row band, which they share in that XCD's L2.
+// Operands stage through LDS 32 bins at a time, in two buffers: while the
+// products of one stage run, the next stage's global loads are in flight and
+// land in the other buffer, one barrier per stage.  LDS rows are padded to 40
+// halves, so the 16 rows one ds_read_b128 pass reads fall in distinct banks.
+// Tiles are numbered so that consecutive workgroups of one XCD (workgroup
+// ids congruent mod 8) take consecutive tiles of one A row band, which they
+// share in that XCD's L2.
 __global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ HA,
                                                    const _Float16* __restrict__ HB,
                                                    const float2* __restrict__ SA,
@@ -170,10 +173,9 @@ __global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ 
                                                    int64_t n_b, int N, int Kp, int64_t tiles_n,
                                                    int64_t n_tiles, float* __restrict__ Rout,
                                                    unsigned long long* __restrict__ best) {
-    __shared__ __attribute__((aligned(16))) _Float16 As[kTile * kLdsRow];
-    __shared__ __attribute__((aligned(16))) _Float16 Bs[kTile * kLdsRow];
+    __shared__ __attribute__((aligned(16))) _Float16 As[2][kTile * kLdsRow];
+    __shared__ __attribute__((aligned(16))) _Float16 Bs[2][kTile * kLdsRow];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // XCD-aware tile order
     const int64_t L = blockIdx.x;
     const int64_t per = (n_tiles + 7) / 8;
     const int64_t tile = (L % 8) * per + L / 8;
@@ -181,51 +183,49 @@ __global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ 
     const int64_t m0 = (tile / tiles_n) * kTile, n0 = (tile % tiles_n) * kTile;
     const int wm = wave >> 1, wn = wave & 1;
     const int r16 = lane & 15, kq = lane >> 4;
-
-    // global -> registers: 4 chunks of 8 halves per matrix per thread
-    h8 ga[4], gb[4];
+    constexpr int CPR = kBK / 8;             // 16-byte chunks per row of a stage
+    constexpr int NCH = kTile * CPR / 256;   // chunks per thread per matrix
+    auto off = [](int row, int ch) { return row * kLdsRow + 8 * ch; };
+    h8 ga[NCH], gb[NCH];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NCH; ++i) {
             const int c = tid + 256 * i;
-            const int row = c >> 3, col = (c & 7) * 8;
+            const int row = c / CPR, ch = c % CPR;
             const int64_t ra = m0 + row, rb = n0 + row;
             h8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-            ga[i] = ra < n_a ? *reinterpret_cast<const h8*>(HA + ra * Kp + k0 + col) : z;
-            gb[i] = rb < n_b ? *reinterpret_cast<const h8*>(HB + rb * Kp + k0 + col) : z;
+            ga[i] = ra < n_a ? *reinterpret_cast<const h8*>(HA + ra * Kp + k0 + 8 * ch) : z;
+            gb[i] = rb < n_b ? *reinterpret_cast<const h8*>(HB + rb * Kp + k0 + 8 * ch) : z;
         }
     };
-    auto store = [&]() {
+    auto store = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NCH; ++i) {
             const int c = tid + 256 * i;
-            const int row = c >> 3, col = (c & 7) * 8;
-            *reinterpret_cast<h8*>(As + row * kLdsRow + col) = ga[i];
-            *reinterpret_cast<h8*>(Bs + row * kLdsRow + col) = gb[i];
+            const int row = c / CPR, ch = c % CPR;
+            *reinterpret_cast<h8*>(&As[buf][off(row, ch)]) = ga[i];
+            *reinterpret_cast<h8*>(&Bs[buf][off(row, ch)]) = gb[i];
         }
     };
-
     f4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
-
     load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
     for (int k0 = 0; k0 < Kp; k0 += kBK) {
-        __syncthreads();  // the previous stage's reads are done
-        store();
-        __syncthreads();
-        if (k0 + kBK < Kp) load(k0 + kBK);
+        const bool more = k0 + kBK < Kp;
+        if (more) load(k0 + kBK);
 #pragma unroll
         for (int ks = 0; ks < kBK; ks += 32) {
             h8 fa[4], fb[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                fa[t] = *reinterpret_cast<const h8*>(As + (wm * 64 + t * 16 + r16) * kLdsRow +
-                                                     ks + 8 * kq);
-                fb[t] = *reinterpret_cast<const h8*>(Bs + (wn * 64 + t * 16 + r16) * kLdsRow +
-                                                     ks + 8 * kq);
+                fa[t] = *reinterpret_cast<const h8*>(&As[buf][off(wm * 64 + t * 16 + r16, ks / 8 + kq)]);
+                fb[t] = *reinterpret_cast<const h8*>(&Bs[buf][off(wn * 64 + t * 16 + r16, ks / 8 + kq)]);
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
@@ -234,8 +234,10 @@ __global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ 
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[a], fb[b], acc[a][b],
                                                                         0, 0, 0);
         }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
-
     // epilogue: R, optional store, and each row's best column in this tile
     const float fN = (float)N;
 #pragma unroll
