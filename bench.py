@@ -702,25 +702,41 @@ def main():
         oracle._load()
         threads = oracle.max_threads()
         order = np.random.default_rng(12345).permutation(N)
-        # batches of seeded-random images until at least cpu_seconds of CPU work
-        done, dt, pairs_cpu, batch_n = 0, 0.0, 0, threads * 4
-        while dt < args.cpu_seconds and done < N:
-            sample = order[done:done + batch_n]
-            t = time.perf_counter()
-            r = oracle.generate(xyz, nrm, sample, cfg.W, cfg.bin, cfg.support_angle,
-                                want_touch=False)
-            el = time.perf_counter() - t
-            dt += el
-            done += len(sample)
-            pairs_cpu += int(r["cnt_sure"].sum() + r["cnt_amb"].sum())
-            left = args.cpu_seconds - dt
-            batch_n = int(min(max(threads, len(sample) * max(left, 0.5) / max(el, 1e-3)), 200000))
-        log(f"[bench] cpu oracle: {done} images, {threads} threads, {dt:.1f} s")
+
+        def sample_rate(seconds, grid):
+            # batches of seeded-random images until `seconds` of CPU work
+            done, dt, pairs_cpu = 0, 0.0, 0
+            batch_n = threads * (64 if grid else 4)
+            while dt < seconds and done < N:
+                sample = order[done:done + batch_n]
+                t = time.perf_counter()
+                r = oracle.generate(xyz, nrm, sample, cfg.W, cfg.bin, cfg.support_angle,
+                                    want_touch=False, grid=grid)
+                el = time.perf_counter() - t
+                dt += el
+                done += len(sample)
+                pairs_cpu += int(r["cnt_sure"].sum() + r["cnt_amb"].sum())
+                left = seconds - dt
+                batch_n = int(min(max(threads, len(sample) * max(left, 0.5) / max(el, 1e-3)),
+                                  400000))
+            return done, dt, pairs_cpu
+
+        # the oracle's cell-grid form: the same pairs as brute force over the
+        # 7 x 7 x 7 cells around each image's point, the algorithm the GPU runs
+        done, dt, pairs_cpu = sample_rate(args.cpu_seconds, True)
+        log(f"[bench] cpu oracle (grid): {done} images, {threads} threads, {dt:.1f} s")
         cpu = {"value": float(pairs_cpu / dt), "unit": "pairs/s", "cores": threads,
                "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
-               "sample": f"{done} seeded-random images of {cfg.name} (brute force over all {M} "
-                         f"points each, FP64), {dt:.1f} s",
+               "sample": f"{done} seeded-random images of {cfg.name}, FP64 oracle in its cell-grid "
+                         f"form (the pairs of the 7 x 7 x 7 cells around each image's point, grid "
+                         f"built in each call), {dt:.1f} s",
                "images_per_s": done / dt}
+        # and its brute-force form (every image against all M points)
+        done, dt, pairs_cpu = sample_rate(max(3.0, args.cpu_seconds / 3), False)
+        log(f"[bench] cpu oracle (brute force): {done} images, {dt:.1f} s")
+        cpu["brute_force"] = {"pairs_per_s": float(pairs_cpu / dt), "images_per_s": done / dt,
+                              "sample": f"{done} seeded-random images, brute force over all "
+                                        f"{M} points each, FP64, {dt:.1f} s"}
         # one thread on the 2,000-point sphere workload (all 2,000 images, brute force)
         c1 = sg.CONFIGS["sphere2k"]
         sxyz, snrm = sg.config_scene("sphere2k")
