@@ -563,9 +563,12 @@ int64_t si_rule_af_chunk(double var_over_mu_sum, double inv_mu_sum, int32_t n_me
  * SS with one image per chunk included (64.0e6 bytes).
  * Every call on a device reuses that device's array and leaves its contents
  * behind: calls that overlap on one device (other streams, other threads)
- * race and must not be issued.  The chunk table is computed on the host and
- * copied from pageable memory with hipMemcpyAsync on hip_stream.  Invalid
- * indices are reported by si_device_errors.
+ * race and must not be issued.  The chunk table is computed on the host
+ * into one of four vectors kept per thread and copied with hipMemcpyAsync
+ * on hip_stream; a call first waits for the upload made four calls before
+ * from the same vector (events created at the thread's first calls), so
+ * up to four calls are queued before the host waits.  Invalid indices are
+ * reported by si_device_errors.
  */
 #define SI_NOALLOC_SCRATCH_BYTES (64u << 20)
 si_status si_generate_noalloc(const si_scene* scene, const int32_t* oriented_idx, int64_t N,

@@ -54,10 +54,15 @@ si_status scratch_of_device(char** out) {
 
 size_t rup256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// The host copy of the chunk table of the last call on this thread; its
-// storage is kept between calls.
+// Host copies of this thread's last chunk tables, in a ring of kRing: a
+// call reuses the oldest once the upload recorded on its event is done, so
+// up to kRing calls can be queued before the host waits.  Their storage is
+// kept between calls.
+constexpr int kRing = 4;
 thread_local std::vector<int64_t> t_starts;
-thread_local std::vector<Chunk> t_table;
+thread_local std::vector<Chunk> t_table[kRing];
+thread_local hipEvent_t t_copied[kRing] = {};
+thread_local int t_next = 0;
 
 }  // namespace
 }  // namespace si
@@ -124,14 +129,19 @@ extern "C" si_status si_generate_noalloc(const si_scene* scene, const int32_t* o
                         "), more than the " + std::to_string((size_t)SI_NOALLOC_SCRATCH_BYTES) +
                         " it has");
 
-    // ---- chunk table (host) ----
+    // ---- chunk table (host), in the oldest ring slot once its upload is done ----
+    const int slot = t_next;
+    t_next = (t_next + 1) % kRing;
+    if (!t_copied[slot]) SI_HIP(hipEventCreateWithFlags(&t_copied[slot], hipEventDisableTiming));
+    SI_HIP(hipEventSynchronize(t_copied[slot]));
+    std::vector<Chunk>& host_table = t_table[slot];
     t_starts.resize((size_t)n_chunks + 1);
     chunk_sizes(kind, N, n_wg, sched->min_chunk, dv, t_starts.data(), n_chunks + 1);
-    t_table.resize((size_t)n_chunks);
+    host_table.resize((size_t)n_chunks);
     for (int64_t i = 0; i < n_chunks; ++i) {
-        t_table[i].item = 0;
-        t_table[i].start = (int32_t)t_starts[i];
-        t_table[i].end = (int32_t)t_starts[i + 1];
+        host_table[i].item = 0;
+        host_table[i].start = (int32_t)t_starts[i];
+        host_table[i].end = (int32_t)t_starts[i + 1];
     }
 
     uint32_t* counter = reinterpret_cast<uint32_t*>(base);
@@ -158,11 +168,12 @@ extern "C" si_status si_generate_noalloc(const si_scene* scene, const int32_t* o
 
     // ---- enqueue: clear the counter, upload the table, order, launch ----
     hipError_t e = launch_fill(reinterpret_cast<int32_t*>(counter), 2, 0, s);
-    // the table comes from pageable host memory: the copy returns once the
-    // runtime holds its bytes, so the host vector is free for the next call
+    // the table comes from this thread's ring slot; the call that reuses the
+    // slot waits for this event first
     if (e == hipSuccess)
-        e = hipMemcpyAsync(table, t_table.data(), sizeof(Chunk) * (size_t)n_chunks,
+        e = hipMemcpyAsync(table, host_table.data(), sizeof(Chunk) * (size_t)n_chunks,
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(t_copied[slot], s);
     if (e == hipSuccess && ordered) {
         int32_t* perm = reinterpret_cast<int32_t*>(base + off_order);
         int32_t* key = perm + N;

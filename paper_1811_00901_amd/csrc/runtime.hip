@@ -921,8 +921,12 @@ si_status rule_setup(int kind, int64_t N, int n_wg, const si_sched* sched, Launc
         d.bases[d.n_bases++] = (int32_t)std::min<int64_t>(c, INT32_MAX);
         R -= std::min(R, c * (int64_t)n_wg);
     }
-    // weights: the caller's, else the emulated speeds, else 1; sum n_wg
+    // weights: the caller's, else the emulated speeds, else 1; sum n_wg.
+    // The host vector is this thread's, reused once its last upload is done.
     static thread_local std::vector<float> w;
+    static thread_local hipEvent_t w_copied = nullptr;
+    if (!w_copied) SI_HIP(hipEventCreateWithFlags(&w_copied, hipEventDisableTiming));
+    SI_HIP(hipEventSynchronize(w_copied));
     w.assign(n_wg, 1.0f);
     const std::vector<float>& given = worker_weights();
     if (!given.empty()) {
@@ -938,10 +942,10 @@ si_status rule_setup(int kind, int64_t N, int n_wg, const si_sched* sched, Launc
     char* mem = nullptr;
     SI_HIP(pool_alloc((void**)&mem, bytes, s));
     hipError_t e = launch_fill(reinterpret_cast<int32_t*>(mem), 8, 0, s);
-    // pageable source: the copy returns once the runtime holds the bytes
     if (e == hipSuccess)
         e = hipMemcpyAsync(mem + 4 * sizeof(double), w.data(), sizeof(float) * (size_t)n_wg,
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(w_copied, s);
     if (e != hipSuccess) {
         (void)hipFreeAsync(mem, s);
         return hip_fail(e, "worker-sized claims");

@@ -111,3 +111,30 @@ def test_noalloc_rejections(env):
         si.si_device_errors()
     assert cnt4.cpu().numpy().view(np.uint32)[2] == 0xFFFFFFFF
 
+
+
+def test_noalloc_queued_calls(env):
+    """Six calls queued back to back on one stream, no synchronisation in
+    between (the host tables rotate through their four buffers), with
+    different sizes and schedules: every output equals si_generate's."""
+    print("\n[case] noalloc queued calls", flush=True)
+    torch, si, _ = env
+    params = si.Params(32, 0.02, S60)
+    xyz, nrm = sg.config_scene("prims100k", M=25_000)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(params))
+    cases = [("fac", 9000), ("gss", 4001), ("tss", 12000), ("static", 777), ("ss", 2500),
+             ("fac_prob", 6000)]
+    outs = []
+    for k, (kind, n) in enumerate(cases):
+        idx = to_dev(torch, np.random.default_rng(k).permutation(25_000)[:n].astype(np.int32))
+        img = torch.empty((n, 32, 32), dtype=torch.float32, device="cuda")
+        cnt = torch.empty((n,), dtype=torch.int32, device="cuda")
+        sched = si.Sched(kind, fac_divisor=0.8 if kind == "fac_prob" else 0.0)
+        si.si_generate_noalloc(scene, idx, params, sched, img, cnt)
+        outs.append((idx, sched, img, cnt))
+    torch.cuda.synchronize()
+    for idx, sched, img, cnt in outs:
+        rimg, rcnt, _ = si.si_generate(scene, idx, params, sched)
+        torch.cuda.synchronize()
+        assert torch.equal(cnt, rcnt) and torch.equal(img, rimg), sched.kind
+    si.si_device_errors()
