@@ -402,8 +402,9 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // Rows (z, y) of grid cells that may hold candidates of the group, each with
 // the contiguous run of points, in quarter-cell steps along x (the sort key
 // of the scene), that meets the support sphere and the beta slab of some
-// image of the group (double precision; radius inflated by 1e-5 relative and
-// slab by 1e-4 R, far above the rounding of the reciprocals used here).  Two
+// image of the group (float32 relative to the image's point; the sphere, the
+// slab and the x range are widened by a margin of 2e-6 of the scene's largest
+// coordinate, many ulp of it, so rounding never cuts a candidate).  Two
 // phases, both called by every thread of the block: rows_cull: thread t
 // bounds row t % 64 against images t / 64 and t / 64 + 4 into the key range
 // part_x0/part_x1[t]; rows_emit (after a barrier): lane r of wave 0 merges
@@ -422,49 +423,60 @@ __device__ __forceinline__ void rows_cull(const SceneView& sc, const SpinParams&
     if (r < n_rows) {
         const int cy = lo[1] + r % ny_rows;
         const int cz = lo[2] + r / ny_rows;
-        const double h = sc.h;
-        const double inv_h = 1.0 / h;
-        const double R = (double)p.radius;
-        const double R2 = R * R;
+        // eps: 2e-6 of the largest coordinate, against row bounds and point
+        // offsets that are each a few ulp of it off the exact ones; the
+        // chord's sqrt near zero cancellation is covered since eps R > ulp(R^2)
+        // for every cell size h >= R / 4
+        const float h = (float)sc.h;
+        const float qx = (float)kSubX / h;
+        float mag = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            mag = fmaxf(mag, fabsf(sc.origin[a]) + (float)sc.dims[a] * h);
+        const float eps = 2e-6f * mag + 1e-6f;
+        const float R = p.radius + eps;
+        const float R2 = R * R;
         // float32 beta is accurate to ~1e-6; the slab keeps a much wider margin
-        const double slab_eps = 1e-4 * fmax(1.0, R);
-        const double ylo = (double)sc.origin[1] + cy * h, yhi = ylo + h;
-        const double zlo = (double)sc.origin[2] + cz * h, zhi = zlo + h;
+        const float slab_eps = 1e-4f * fmaxf(1.0f, p.radius) + eps;
 #pragma unroll
         for (int g = 0; g < kMaxGroup; ++g) {
             if (g >= ng) break;
             if ((g & 3) != q) continue;  // wave q takes images q and q + 4
-            const double py = gi[g].py, pz = gi[g].pz, px = gi[g].px;
+            const float py = gi[g].py, pz = gi[g].pz, px = gi[g].px;
             if (!(py == py) || !(pz == pz) || !(px == px)) continue;  // invalid image
-            const double dy = fmax(0.0, fmax(ylo - py, py - yhi));
-            const double dz = fmax(0.0, fmax(zlo - pz, pz - zhi));
-            const double d2 = dy * dy + dz * dz;
+            // the row's y-z box relative to p
+            const float ylo = (sc.origin[1] - py) + (float)cy * h, yhi = ylo + h;
+            const float zlo = (sc.origin[2] - pz) + (float)cz * h, zhi = zlo + h;
+            const float dy = fmaxf(0.0f, fmaxf(ylo, -yhi));
+            const float dz = fmaxf(0.0f, fmaxf(zlo, -zhi));
+            const float d2 = fmaf(dz, dz, dy * dy);
             if (d2 > R2) continue;
-            const double half_chord = sqrt(R2 - d2);
-            double xa = px - half_chord, xb = px + half_chord;
+            const float half_chord = sqrtf(R2 - d2);
+            float xa = -half_chord, xb = half_chord;
             // slab beta_lo < n.(x - p) <= beta_hi over the row's y-z box
-            const double nx = gi[g].nx, ny = gi[g].ny, nz = gi[g].nz;
-            const double ty0 = ny * (ylo - py), ty1 = ny * (yhi - py);
-            const double tz0 = nz * (zlo - pz), tz1 = nz * (zhi - pz);
-            const double tmin = fmin(ty0, ty1) + fmin(tz0, tz1);
-            const double tmax = fmax(ty0, ty1) + fmax(tz0, tz1);
-            const double A = (double)p.beta_lo - slab_eps - tmax;  // bound of nx (x - px)
-            const double Bv = (double)p.beta_hi + slab_eps - tmin;
-            if (fabs(nx) > 1e-12) {
-                const double inv_nx = 1.0 / nx;
-                double s0 = A * inv_nx, s1 = Bv * inv_nx;
-                if (s0 > s1) { const double tt = s0; s0 = s1; s1 = tt; }
-                xa = fmax(xa, px + s0);
-                xb = fmin(xb, px + s1);
-            } else if (A > 0.0 || Bv < 0.0) {
+            const float nx = gi[g].nx, ny = gi[g].ny, nz = gi[g].nz;
+            const float ty0 = ny * ylo, ty1 = ny * yhi;
+            const float tz0 = nz * zlo, tz1 = nz * zhi;
+            const float tmin = fminf(ty0, ty1) + fminf(tz0, tz1);
+            const float tmax = fmaxf(ty0, ty1) + fmaxf(tz0, tz1);
+            const float A = p.beta_lo - slab_eps - tmax;  // bound of nx (x - px)
+            const float Bv = p.beta_hi + slab_eps - tmin;
+            if (fabsf(nx) > 1e-20f) {
+                const float inv_nx = __builtin_amdgcn_rcpf(nx);
+                float s0 = A * inv_nx, s1 = Bv * inv_nx;
+                if (s0 > s1) { const float tt = s0; s0 = s1; s1 = tt; }
+                xa = fmaxf(xa, s0 - fabsf(s0) * 1e-6f - eps);
+                xb = fminf(xb, s1 + fabsf(s1) * 1e-6f + eps);
+            } else if (A > 0.0f || Bv < 0.0f) {
                 continue;
             }
             if (!(xa <= xb)) continue;
             // keys along the row: kSubX per cell
-            const double fa = floor((xa - (double)sc.origin[0]) * (inv_h * kSubX));
-            const double fb = floor((xb - (double)sc.origin[0]) * (inv_h * kSubX));
-            const int a = (int)fmax(-1.0, fmin(fa, 1.0e9));
-            const int b = (int)fmax(-1.0, fmin(fb, 1.0e9));
+            const float ox = px - sc.origin[0];
+            const float fa = floorf((ox + xa - eps) * qx);
+            const float fb = floorf((ox + xb + eps) * qx);
+            const int a = (int)fmaxf(-1.0f, fminf(fa, 1.0e9f));
+            const int b = (int)fmaxf(-1.0f, fminf(fb, 1.0e9f));
             if (p.reach == 0) {
                 // single-cell scene: the paper's loop over all M points
                 x0 = 0;

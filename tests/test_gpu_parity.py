@@ -149,6 +149,26 @@ def test_cell_list_equals_brute_force(env):
     assert b[2]["pairs_tested"] < a[2]["pairs_tested"] / 5
 
 
+@pytest.mark.parametrize("shift,scale", [((1500.0, -800.0, 2300.0), 1.0),
+                                         ((-3.0e4, 2.0e4, 0.0), 1.0),
+                                         ((0.0, 0.0, 0.0), 250.0)])
+def test_cell_list_far_from_origin(env, shift, scale):
+    """The grid's row culling works in float32 relative to each image's point
+    with a margin scaled to the coordinates: scenes far from the origin, or
+    scaled up with their bin, give the same images as the brute-force loop
+    over all points (which culls nothing)."""
+    print_case(f"cell list far from origin shift={shift} scale={scale}")
+    xyz, nrm = sg.config_scene("prims100k", M=20000)
+    xyz = (xyz.astype(np.float64) * scale + np.array(shift)).astype(np.float32)
+    idx = np.arange(0, 20000, 5)
+    a = run(env, xyz, nrm, idx, 32, 0.02 * scale, S60, "bilinear", "fac", radius=0.0)
+    b = run(env, xyz, nrm, idx, 32, 0.02 * scale, S60, "bilinear", "fac")
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    assert int(a[1].astype(np.int64).sum()) > 0
+    assert b[2]["pairs_tested"] < a[2]["pairs_tested"] / 5
+
+
 @pytest.mark.parametrize("mode", ["bilinear", "ceil"])
 def test_prims100k_full_vs_oracle(env, mode):
     """The full uneven-density workload (100k points, the first 65,536
