@@ -111,9 +111,11 @@ __global__ void __launch_bounds__(256) k_nn(SceneView sc, const int32_t* __restr
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTile = 128;  // rows of A and of B per workgroup tile
-constexpr int kBK = 32;     // K (bins) per LDS stage
-constexpr int kLdsRow = kBK + 8;  // halves per LDS row (16 bytes of padding)
+constexpr int kTM = 256, kTN = 128;  // A rows and B rows (images) per workgroup tile
+constexpr int kWavesM = 4, kWavesN = 2;  // waves per tile, each 64 x 64
+constexpr int kGemmThreads = 64 * kWavesM * kWavesN;
+constexpr int kBK = 32;               // K (bins) per LDS stage: one MFMA depth
+constexpr int kSuperM = 8, kSuperN = 8;  // tiles one XCD runs at once (two per CU)
 
 // One wave per image: scale by the largest bin, round to fp16 into a row of
 // Kp halves (zero beyond N), and keep the rounded image's sum s and
@@ -155,56 +157,87 @@ __device__ __forceinline__ unsigned long long best_key(float r, int j) {
     return ((unsigned long long)o << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)j);
 }
 
-// R for a 128 x 128 tile of (A image, B image) pairs.  Four waves, each a
-// 64 x 64 quarter as 4 x 4 products of 16 x 16 (v_mfma_f32_16x16x32_f16:
-// lane l holds row l % 16 of the A operand and of B's image at K = 8 (l / 16)
-// .. + 7, and receives column l % 16, rows 4 (l / 16) .. + 3 of the result).
-// Operands stage through LDS 32 bins at a time, in two buffers: while the
-// products of one stage run, the next stage's global loads are in flight and
-// land in the other buffer, one barrier per stage.  LDS rows are padded to 40
-// halves, so the 16 rows one ds_read_b128 pass reads fall in distinct banks.
-// Tiles are numbered so that consecutive workgroups of one XCD (workgroup
-// ids congruent mod 8) take consecutive tiles of one A row band, which they
-// share in that XCD's L2.
-__global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ HA,
-                                                   const _Float16* __restrict__ HB,
-                                                   const float2* __restrict__ SA,
-                                                   const float2* __restrict__ SB, int64_t n_a,
-                                                   int64_t n_b, int N, int Kp, int64_t tiles_n,
-                                                   int64_t n_tiles, float* __restrict__ Rout,
-                                                   unsigned long long* __restrict__ best) {
-    __shared__ __attribute__((aligned(16))) _Float16 As[2][kTile * kLdsRow];
-    __shared__ __attribute__((aligned(16))) _Float16 Bs[2][kTile * kLdsRow];
+// Largest x, and smallest i, over the 16 lanes of each DPP row; every lane
+// receives the result (swap neighbours, swap pairs, mirror each half, mirror
+// the row).
+__device__ __forceinline__ float row16_max(float x) {
+    x = fmaxf(x, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false)));
+    x = fmaxf(x, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, false)));
+    x = fmaxf(x, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x141, 0xF, 0xF, false)));
+    x = fmaxf(x, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x140, 0xF, 0xF, false)));
+    return x;
+}
+__device__ __forceinline__ int row16_min(int i) {
+    i = min(i, __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false));
+    i = min(i, __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false));
+    i = min(i, __builtin_amdgcn_mov_dpp(i, 0x141, 0xF, 0xF, false));
+    i = min(i, __builtin_amdgcn_mov_dpp(i, 0x140, 0xF, 0xF, false));
+    return i;
+}
+
+// R for a 256 x 128 tile of (A image, B image) pairs.  Eight waves, each a
+// 64 x 64 part as 4 x 4 products of 16 x 16 (v_mfma_f32_16x16x32_f16: lane l
+// holds row l % 16 of the A operand and of B's image at K = 8 (l / 16) .. + 7,
+// and receives column l % 16, rows 4 (l / 16) .. + 3 of the result); two
+// workgroups per compute unit.  Operands stage through LDS 32 bins at a time,
+// in two buffers: while the products of one stage run, the next stage's
+// global loads are in flight and land in the other buffer, one barrier per
+// stage.  An LDS row is the 64 bytes of one image's stage, its four 16-byte
+// chunks XOR-swizzled by the row's low bits so that the rows one ds_read_b128
+// pass reads fall in distinct banks.  Rows past the end of A or B load the
+// last row (their results are never used), so the loads need no branches.
+// Tiles are numbered in super-tiles of 8 x 8: the 64 workgroups one XCD runs
+// at once (workgroup ids congruent mod 8) share 8 A bands and 8 B bands in
+// that XCD's L2.  Each row's best column is reduced over its 16 lanes with
+// DPP and merged across tiles by a 64-bit atomicMax.
+__global__ void __launch_bounds__(kGemmThreads, 2)
+    k_corr_gemm(const _Float16* __restrict__ HA, const _Float16* __restrict__ HB,
+                const float2* __restrict__ SA, const float2* __restrict__ SB, int64_t n_a,
+                int64_t n_b, int N, int Kp, int64_t tiles_m, int64_t tiles_n, int64_t super_n,
+                float* __restrict__ Rout, unsigned long long* __restrict__ best) {
+    constexpr int CPR = kBK / 8;  // 16-byte chunks per LDS row
+    constexpr int NCA = kTM * CPR / kGemmThreads, NCB = kTN * CPR / kGemmThreads;
+    static_assert(kTM * CPR % kGemmThreads == 0 && kTN * CPR % kGemmThreads == 0,
+                  "whole chunks per thread");
+    __shared__ __attribute__((aligned(16))) _Float16 As[2][kTM * kBK];
+    __shared__ __attribute__((aligned(16))) _Float16 Bs[2][kTN * kBK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t L = blockIdx.x;
-    const int64_t per = (n_tiles + 7) / 8;
-    const int64_t tile = (L % 8) * per + L / 8;
-    if (tile >= n_tiles) return;
-    const int64_t m0 = (tile / tiles_n) * kTile, n0 = (tile % tiles_n) * kTile;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t j = L >> 3;
+    const int64_t s = (j / (kSuperM * kSuperN)) * 8 + (L & 7);
+    const int i = (int)(j % (kSuperM * kSuperN));
+    const int64_t tm = (s / super_n) * kSuperM + i / kSuperN;
+    const int64_t tn = (s % super_n) * kSuperN + i % kSuperN;
+    if (tm >= tiles_m || tn >= tiles_n) return;
+    const int64_t m0 = tm * kTM, n0 = tn * kTN;
+    const int wm = wave / kWavesN, wn = wave % kWavesN;
     const int r16 = lane & 15, kq = lane >> 4;
-    constexpr int CPR = kBK / 8;             // 16-byte chunks per row of a stage
-    constexpr int NCH = kTile * CPR / 256;   // chunks per thread per matrix
-    auto off = [](int row, int ch) { return row * kLdsRow + 8 * ch; };
-    h8 ga[NCH], gb[NCH];
+    auto off = [](int row, int ch) { return row * kBK + 8 * (ch ^ (row & (CPR - 1))); };
+    h8 ga[NCA], gb[NCB];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < NCH; ++i) {
-            const int c = tid + 256 * i;
-            const int row = c / CPR, ch = c % CPR;
-            const int64_t ra = m0 + row, rb = n0 + row;
-            h8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-            ga[i] = ra < n_a ? *reinterpret_cast<const h8*>(HA + ra * Kp + k0 + 8 * ch) : z;
-            gb[i] = rb < n_b ? *reinterpret_cast<const h8*>(HB + rb * Kp + k0 + 8 * ch) : z;
+        for (int c = 0; c < NCA; ++c) {
+            const int q = tid + kGemmThreads * c;
+            const int64_t ra = min(m0 + q / CPR, n_a - 1);
+            ga[c] = *reinterpret_cast<const h8*>(HA + ra * Kp + k0 + 8 * (q % CPR));
+        }
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+            const int q = tid + kGemmThreads * c;
+            const int64_t rb = min(n0 + q / CPR, n_b - 1);
+            gb[c] = *reinterpret_cast<const h8*>(HB + rb * Kp + k0 + 8 * (q % CPR));
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < NCH; ++i) {
-            const int c = tid + 256 * i;
-            const int row = c / CPR, ch = c % CPR;
-            *reinterpret_cast<h8*>(&As[buf][off(row, ch)]) = ga[i];
-            *reinterpret_cast<h8*>(&Bs[buf][off(row, ch)]) = gb[i];
+        for (int c = 0; c < NCA; ++c) {
+            const int q = tid + kGemmThreads * c;
+            *reinterpret_cast<h8*>(&As[buf][off(q / CPR, q % CPR)]) = ga[c];
+        }
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+            const int q = tid + kGemmThreads * c;
+            *reinterpret_cast<h8*>(&Bs[buf][off(q / CPR, q % CPR)]) = gb[c];
         }
     };
     f4 acc[4][4];
@@ -219,20 +252,16 @@ __global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ 
     for (int k0 = 0; k0 < Kp; k0 += kBK) {
         const bool more = k0 + kBK < Kp;
         if (more) load(k0 + kBK);
+        h8 fb[4];
 #pragma unroll
-        for (int ks = 0; ks < kBK; ks += 32) {
-            h8 fa[4], fb[4];
+        for (int t = 0; t < 4; ++t)
+            fb[t] = *reinterpret_cast<const h8*>(&Bs[buf][off(wn * 64 + t * 16 + r16, kq)]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                fa[t] = *reinterpret_cast<const h8*>(&As[buf][off(wm * 64 + t * 16 + r16, ks / 8 + kq)]);
-                fb[t] = *reinterpret_cast<const h8*>(&Bs[buf][off(wn * 64 + t * 16 + r16, ks / 8 + kq)]);
-            }
+        for (int a = 0; a < 4; ++a) {
+            const h8 fa = *reinterpret_cast<const h8*>(&As[buf][off(wm * 64 + a * 16 + r16, kq)]);
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[a], fb[b], acc[a][b],
-                                                                        0, 0, 0);
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa, fb[b], acc[a][b], 0, 0, 0);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -240,6 +269,13 @@ __global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ 
     }
     // epilogue: R, optional store, and each row's best column in this tile
     const float fN = (float)N;
+    float2 sb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t col = n0 + wn * 64 + b * 16 + r16;
+        sb[b] = col < n_b ? SB[col] : make_float2(0.0f, 0.0f);
+    }
+    const float ninf = -__builtin_inff();
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -247,25 +283,25 @@ __global__ void __launch_bounds__(256) k_corr_gemm(const _Float16* __restrict__ 
             const int64_t row = m0 + wm * 64 + a * 16 + 4 * kq + v;
             const bool row_ok = row < n_a;
             const float2 sa = row_ok ? SA[row] : make_float2(0.0f, 0.0f);
-            unsigned long long key = 0ull;
+            float rb = ninf;
+            int bb = 0;
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int64_t col = n0 + wn * 64 + b * 16 + r16;
-                if (row_ok && col < n_b) {
-                    const float2 sb = SB[col];
-                    const float r = (fN * acc[a][b][v] - sa.x * sb.x) * sa.y * sb.y;
-                    if (Rout) Rout[row * n_b + col] = r;
-                    key = max(key, best_key(r, (int)col));
+                const float r = (fN * acc[a][b][v] - sa.x * sb[b].x) * sa.y * sb[b].y;
+                if (Rout && row_ok && col < n_b) Rout[row * n_b + col] = r;
+                // strictly larger: the lowest column wins ties (-0 equals +0)
+                if (col < n_b && r > rb) {
+                    rb = r;
+                    bb = b;
                 }
             }
             if (best) {
-                // the 16 lanes of one row hold its 64 columns of this wave
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1) {
-                    const unsigned long long o = __shfl_xor(key, off, 64);
-                    key = max(key, o);
-                }
-                if (r16 == 0 && row_ok && key) atomicMax(best + row, key);
+                // the 16 lanes of one row hold its columns of this wave
+                const float m = row16_max(rb);
+                const int c = row16_min(rb == m ? wn * 64 + bb * 16 + r16 : 0x7fffffff);
+                if (r16 == 0 && row_ok && m > ninf)
+                    atomicMax(best + row, best_key(m == 0.0f ? 0.0f : m, (int)(n0 + c)));
             }
         }
     }
@@ -447,13 +483,16 @@ extern "C" si_status si_correlate(const float* A, int64_t n_a, const float* B, i
                            (int)n_bins, Kp, HA, SA);
         hipLaunchKernelGGL(k_corr_prep, dim3((unsigned)((n_b + 3) / 4)), dim3(256), 0, s, B, n_b,
                            (int)n_bins, Kp, HB, SB);
-        const int64_t tiles_n = (n_b + kTile - 1) / kTile;
-        const int64_t n_tiles = ((n_a + kTile - 1) / kTile) * tiles_n;
-        const int64_t grid = (n_tiles + 7) / 8 * 8;
+        const int64_t tiles_m = (n_a + kTM - 1) / kTM, tiles_n = (n_b + kTN - 1) / kTN;
+        const int64_t super_m = (tiles_m + kSuperM - 1) / kSuperM;
+        const int64_t super_n = (tiles_n + kSuperN - 1) / kSuperN;
+        // every super-tile takes 64 workgroups, numbered 8 apart (one XCD)
+        const int64_t grid = (super_m * super_n + 7) / 8 * 8 * (kSuperM * kSuperN);
         if (grid > INT32_MAX) e = hipErrorInvalidValue;
         else
-            hipLaunchKernelGGL(k_corr_gemm, dim3((unsigned)grid), dim3(256), 0, s, HA, HB, SA, SB,
-                               n_a, n_b, (int)n_bins, Kp, tiles_n, n_tiles, R_out, best);
+            hipLaunchKernelGGL(k_corr_gemm, dim3((unsigned)grid), dim3(kGemmThreads), 0, s, HA,
+                               HB, SA, SB, n_a, n_b, (int)n_bins, Kp, tiles_m, tiles_n, super_n,
+                               R_out, best);
         if (e == hipSuccess) e = hipGetLastError();
     }
     if (e == hipSuccess && best) {
