@@ -175,17 +175,30 @@ __device__ __forceinline__ int row16_min(int i) {
     return i;
 }
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
 // R for a 256 x 128 tile of (A image, B image) pairs.  Eight waves, each a
 // 64 x 64 part as 4 x 4 products of 16 x 16 (v_mfma_f32_16x16x32_f16: lane l
 // holds row l % 16 of the A operand and of B's image at K = 8 (l / 16) .. + 7,
 // and receives column l % 16, rows 4 (l / 16) .. + 3 of the result); two
-// workgroups per compute unit.  Operands stage through LDS 32 bins at a time,
-// in two buffers: while the products of one stage run, the next stage's
-// global loads are in flight and land in the other buffer, one barrier per
-// stage.  An LDS row is the 64 bytes of one image's stage, its four 16-byte
-// chunks XOR-swizzled by the row's low bits so that the rows one ds_read_b128
-// pass reads fall in distinct banks.  Rows past the end of A or B load the
-// last row (their results are never used), so the loads need no branches.
+// workgroups per compute unit.
+//
+// Operands move from global memory straight into LDS (global_load_lds_dwordx4,
+// no registers in between), 32 bins per stage, into a ring of three stages:
+// while the products of stage s run, the loads of stages s + 1 and s + 2 are
+// in flight.  A stage is 24 groups of 16 rows x 64 bytes, three per wave; in
+// a group, lane l fills bytes 16 l .. 16 l + 15, i.e. row l / 4, slot l % 4,
+// and loads the chunk (l % 4) ^ (row % 4) of that row, so that each row's
+// four 16-byte chunks sit XOR-swizzled by the row's low bits and the rows one
+// ds_read_b128 pass reads fall in distinct banks.  Each iteration waits on
+// vmcnt for this wave's loads of stage s only, then a barrier (with no
+// memory fence, which would wait for every load in flight) makes all waves'
+// loads of stage s visible and guarantees that the stage read two iterations
+// ago is no longer read, before its slot receives stage s + 2.  Rows past
+// the end of A or B load the last row (their results are never used), so
+// the loads need no branches.
+//
 // Tiles are numbered in super-tiles of 8 x 8: the 64 workgroups one XCD runs
 // at once (workgroup ids congruent mod 8) share 8 A bands and 8 B bands in
 // that XCD's L2.  Each row's best column is reduced over its 16 lanes with
@@ -195,12 +208,13 @@ __global__ void __launch_bounds__(kGemmThreads, 2)
                 const float2* __restrict__ SA, const float2* __restrict__ SB, int64_t n_a,
                 int64_t n_b, int N, int Kp, int64_t tiles_m, int64_t tiles_n, int64_t super_n,
                 float* __restrict__ Rout, unsigned long long* __restrict__ best) {
-    constexpr int CPR = kBK / 8;  // 16-byte chunks per LDS row
-    constexpr int NCA = kTM * CPR / kGemmThreads, NCB = kTN * CPR / kGemmThreads;
-    static_assert(kTM * CPR % kGemmThreads == 0 && kTN * CPR % kGemmThreads == 0,
-                  "whole chunks per thread");
-    __shared__ __attribute__((aligned(16))) _Float16 As[2][kTM * kBK];
-    __shared__ __attribute__((aligned(16))) _Float16 Bs[2][kTN * kBK];
+    constexpr int kWaves = kWavesM * kWavesN;
+    constexpr int CPR = kBK / 8;                // 16-byte chunks per LDS row
+    constexpr int kStage = (kTM + kTN) * kBK;   // halves per stage
+    constexpr int kGroups = (kTM + kTN) / 16;   // 1 KB loads per stage
+    constexpr int PW = kGroups / kWaves;        // ... per wave
+    static_assert(kGroups % kWaves == 0 && PW < 16, "whole loads per wave, vmcnt field");
+    __shared__ __attribute__((aligned(16))) _Float16 ring[3][kStage];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t L = blockIdx.x;
     const int64_t j = L >> 3;
@@ -213,59 +227,59 @@ __global__ void __launch_bounds__(kGemmThreads, 2)
     const int wm = wave / kWavesN, wn = wave % kWavesN;
     const int r16 = lane & 15, kq = lane >> 4;
     auto off = [](int row, int ch) { return row * kBK + 8 * (ch ^ (row & (CPR - 1))); };
-    h8 ga[NCA], gb[NCB];
-    auto load = [&](int k0) {
+    // this lane's sources: groups wave, wave + 8, wave + 16 of the stage's
+    // rows (A's 256, then B's 128)
+    const int lr = lane >> 2;
+    const int lch = (lane & 3) ^ (lr & 3);
+    const _Float16* src[PW];
+    int dst[PW];
 #pragma unroll
-        for (int c = 0; c < NCA; ++c) {
-            const int q = tid + kGemmThreads * c;
-            const int64_t ra = min(m0 + q / CPR, n_a - 1);
-            ga[c] = *reinterpret_cast<const h8*>(HA + ra * Kp + k0 + 8 * (q % CPR));
-        }
+    for (int k = 0; k < PW; ++k) {
+        const int g = wave + kWaves * k;
+        if (g < kTM / 16)
+            src[k] = HA + min(m0 + 16 * g + lr, n_a - 1) * Kp + 8 * lch;
+        else
+            src[k] = HB + min(n0 + 16 * (g - kTM / 16) + lr, n_b - 1) * Kp + 8 * lch;
+        dst[k] = 16 * g * kBK;
+    }
+    auto issue = [&](int st) {
+        _Float16* r = ring[st % 3];
+        const int k0 = st * kBK;
 #pragma unroll
-        for (int c = 0; c < NCB; ++c) {
-            const int q = tid + kGemmThreads * c;
-            const int64_t rb = min(n0 + q / CPR, n_b - 1);
-            gb[c] = *reinterpret_cast<const h8*>(HB + rb * Kp + k0 + 8 * (q % CPR));
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int c = 0; c < NCA; ++c) {
-            const int q = tid + kGemmThreads * c;
-            *reinterpret_cast<h8*>(&As[buf][off(q / CPR, q % CPR)]) = ga[c];
-        }
-#pragma unroll
-        for (int c = 0; c < NCB; ++c) {
-            const int q = tid + kGemmThreads * c;
-            *reinterpret_cast<h8*>(&Bs[buf][off(q / CPR, q % CPR)]) = gb[c];
-        }
+        for (int k = 0; k < PW; ++k)
+            __builtin_amdgcn_global_load_lds((const glb_void_t*)(src[k] + k0),
+                                             (lds_void_t*)(r + dst[k]), 16, 0, 0);
     };
     f4 acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
-    load(0);
-    store(0);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < Kp; k0 += kBK) {
-        const bool more = k0 + kBK < Kp;
-        if (more) load(k0 + kBK);
+    const int n_st = Kp / kBK;
+    issue(0);
+    if (n_st > 1) issue(1);
+    for (int st = 0; st < n_st; ++st) {
+        // s_waitcnt immediates: vmcnt in bits 3:0, expcnt and lgkmcnt at their
+        // maxima (no wait on them)
+        if (st + 1 < n_st) __builtin_amdgcn_s_waitcnt(0x0F70 | PW);  // vmcnt(PW)
+        else __builtin_amdgcn_s_waitcnt(0x0F70);                     // vmcnt(0)
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no LDS access moves across
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (st + 2 < n_st) issue(st + 2);
+        const _Float16* As = ring[st % 3];
+        const _Float16* Bs = As + kTM * kBK;
         h8 fb[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-            fb[t] = *reinterpret_cast<const h8*>(&Bs[buf][off(wn * 64 + t * 16 + r16, kq)]);
+            fb[t] = *reinterpret_cast<const h8*>(&Bs[off(wn * 64 + t * 16 + r16, kq)]);
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const h8 fa = *reinterpret_cast<const h8*>(&As[buf][off(wm * 64 + a * 16 + r16, kq)]);
+            const h8 fa = *reinterpret_cast<const h8*>(&As[off(wm * 64 + a * 16 + r16, kq)]);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa, fb[b], acc[a][b], 0, 0, 0);
         }
-        if (more) store(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
     }
     // epilogue: R, optional store, and each row's best column in this tile
     const float fN = (float)N;
