@@ -251,6 +251,7 @@ si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk,
         DeviceState::Table& t = it->second;
         t.tick = ++st->table_tick;
         SI_HIP(hipStreamWaitEvent(s, t.ready, 0));  // uploaded on another stream
+        ++t.pins;
         *out = t.dev;
         *n_out = t.n;
         *entry = &t;
@@ -260,11 +261,14 @@ si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk,
     if (n > INT32_MAX) return fail(SI_E_INVALID, "schedule has too many chunks");
     std::vector<int64_t> starts(n + 1);
     chunk_sizes(kind, N, P, min_chunk, dv, starts.data(), n + 1);
-    if (st->tables.size() >= 64) {
-        // evict the least recently used table once the work that reads it is done
-        auto lru = st->tables.begin();
+    // evict the least recently used table not held by a call in progress,
+    // once the work that reads it is done
+    auto lru = st->tables.end();
+    if (st->tables.size() >= 64)
         for (auto i = st->tables.begin(); i != st->tables.end(); ++i)
-            if (i->second.tick < lru->second.tick) lru = i;
+            if (i->second.pins == 0 && (lru == st->tables.end() || i->second.tick < lru->second.tick))
+                lru = i;
+    if (lru != st->tables.end()) {
         DeviceState::Table& t = lru->second;
         for (auto& u : t.uses) {
             SI_HIP(hipEventSynchronize(u.second));
@@ -307,6 +311,7 @@ si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk,
         if (t.ready) (void)hipEventDestroy(t.ready);
         return hip_fail(e, "chunk table upload");
     }
+    t.pins = 1;
     DeviceState::Table& in = st->tables[key] = t;
     *out = in.dev;
     *n_out = in.n;
@@ -314,9 +319,11 @@ si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk,
     return SI_OK;
 }
 
-si_status table_used(DeviceState* st, void* entry, hipStream_t s) {
+si_status table_used(DeviceState* st, void* entry, hipStream_t s, bool launched) {
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceState::Table* t = static_cast<DeviceState::Table*>(entry);
+    --t->pins;
+    if (!launched) return SI_OK;
     hipEvent_t& ev = t->uses[s];
     if (!ev) SI_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     SI_HIP(hipEventRecord(ev, s));
@@ -1054,7 +1061,10 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
         }
         if (sched->order != SI_ORDER_GIVEN && scene->n_cells > 1) {
             rc = cell_order(*scene, oriented_idx, N, s, &order_mem, &d.single.perm);
-            if (rc != SI_OK) return rc;
+            if (rc != SI_OK) {
+                if (table_entry) (void)table_used(st, table_entry, s, false);
+                return rc;
+            }
             if (sched->order == SI_ORDER_SPREAD) {
                 d.single.spread_full = (int32_t)(N / kSpreadUnit);
                 d.single.spread_mult = spread_mult(N / kSpreadUnit);
@@ -1067,7 +1077,9 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     d.dynamic = kind == SI_SCHED_STATIC ? 0 : 1;
     rc = run_launch(st, d, n_wg, w2, stats, s, kind);
     if (table_entry) {
-        const si_status r2 = table_used(st, table_entry, s);
+        // recorded even after a failed launch: work enqueued before the
+        // failure may still read the table
+        const si_status r2 = table_used(st, table_entry, s, true);
         if (rc == SI_OK) rc = r2;
     }
     if (order_mem) (void)hipFreeAsync(order_mem, s);

@@ -223,6 +223,7 @@ struct DeviceState {
         hipEvent_t ready = nullptr;
         std::map<hipStream_t, hipEvent_t> uses;
         uint64_t tick = 0;
+        int pins = 0;  // calls between get_table and table_used: never evicted
     };
     std::map<std::tuple<int, int64_t, int, int, uint32_t>, Table> tables;
     uint64_t table_tick = 0;
@@ -260,11 +261,13 @@ si_status cell_order(const Scene& sc, const int32_t* oriented, int64_t N, hipStr
                      int32_t** mem_out, const int32_t** perm_out);
 // The chunk table of a schedule on the device, ready for work queued on s
 // (uploaded there on first use, or waited for if another stream uploaded it);
-// *entry identifies it for table_used.
+// *entry identifies it for table_used, which every successful call must be
+// followed by: until then the table is held and cannot be evicted.
 si_status get_table(DeviceState* st, int kind, int64_t N, int P, int min_chunk, float divisor,
                     Chunk** out, int* n_out, hipStream_t s, void** entry);
-// Record that work queued on s up to now reads the table `entry`.
-si_status table_used(DeviceState* st, void* entry, hipStream_t s);
+// Release the hold of get_table; with `launched`, first record that work
+// queued on s up to now reads the table `entry`.
+si_status table_used(DeviceState* st, void* entry, hipStream_t s, bool launched);
 si_status run_launch(DeviceState* st, LaunchDesc& d, int n_wg, int max_w2, si_stats* stats,
                      hipStream_t s, int sched_used);
 // Learned schedule of one scene, computed on the device in stream order:
