@@ -405,6 +405,10 @@ def paper_shape(torch, si, sg):
         out[kind] = {"ms": ms, "pair_tests_per_s": N * M / (ms["median"] * 1e-3),
                      "images_per_s": N / (ms["median"] * 1e-3)}
     out["in_support_pairs"] = int(cnt.to(torch.int64).sum())
+    # the same candidate loop with no culling, no angle test and almost no
+    # binning: its 13 lane-ops per pair test (3 subtractions, 3 for beta, 3
+    # for |d|^2, 1 for alpha^2, 3 comparisons) against the VALU peak
+    out["fac"]["test_valu_frac"] = out["fac"]["pair_tests_per_s"] * 13 / PEAK_VALU_OPS
     out["paper_context"] = {
         "pair_tests_per_s": PAPER_TESTS_PER_S_160_CORES_SS,
         "hardware": "160 Xeon E5-2640 cores (8 nodes), MPI, EPSIA-SS, Ramesses ~826K points",

@@ -108,7 +108,7 @@ def corr_bound(Mt, A, B):
 
 
 @pytest.mark.parametrize("W,n_a,n_b", [(32, 1037, 2091), (16, 300, 4097), (7, 129, 255),
-                                         (5, 70, 300)])
+                                         (5, 70, 300), (64, 256, 384)])
 def test_correlation_vs_oracle(env, W, n_a, n_b):
     print(f"\n[case] correlation W={W} {n_a}x{n_b}", flush=True)
     torch, si, oracle, Mt = env
