@@ -477,17 +477,19 @@ extern "C" si_status si_correlate(const float* A, int64_t n_a, const float* B, i
     hipStream_t s = (hipStream_t)hip_stream;
     const int Kp = (n_bins + kBK - 1) / kBK * kBK;
     const bool want_best = best_out || best_R_out;
+    // one set against itself: its fp16 rows and sums serve as both operands
+    const bool same = A == B && n_a == n_b;
     const size_t b_ha = rup256(sizeof(_Float16) * (size_t)n_a * Kp);
-    const size_t b_hb = rup256(sizeof(_Float16) * (size_t)n_b * Kp);
+    const size_t b_hb = same ? 0 : rup256(sizeof(_Float16) * (size_t)n_b * Kp);
     const size_t b_sa = rup256(sizeof(float2) * (size_t)n_a);
-    const size_t b_sb = rup256(sizeof(float2) * (size_t)n_b);
+    const size_t b_sb = same ? 0 : rup256(sizeof(float2) * (size_t)n_b);
     const size_t b_best = want_best ? rup256(sizeof(unsigned long long) * (size_t)n_a) : 0;
     char* m = nullptr;
     SI_HIP(pool_alloc((void**)&m, b_ha + b_hb + b_sa + b_sb + b_best, s));
     _Float16* HA = reinterpret_cast<_Float16*>(m);
-    _Float16* HB = reinterpret_cast<_Float16*>(m + b_ha);
+    _Float16* HB = same ? HA : reinterpret_cast<_Float16*>(m + b_ha);
     float2* SA = reinterpret_cast<float2*>(m + b_ha + b_hb);
-    float2* SB = reinterpret_cast<float2*>(m + b_ha + b_hb + b_sa);
+    float2* SB = same ? SA : reinterpret_cast<float2*>(m + b_ha + b_hb + b_sa);
     unsigned long long* best =
         want_best ? reinterpret_cast<unsigned long long*>(m + b_ha + b_hb + b_sa + b_sb) : nullptr;
     hipError_t e = hipSuccess;
@@ -495,8 +497,9 @@ extern "C" si_status si_correlate(const float* A, int64_t n_a, const float* B, i
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_corr_prep, dim3((unsigned)((n_a + 3) / 4)), dim3(256), 0, s, A, n_a,
                            (int)n_bins, Kp, HA, SA);
-        hipLaunchKernelGGL(k_corr_prep, dim3((unsigned)((n_b + 3) / 4)), dim3(256), 0, s, B, n_b,
-                           (int)n_bins, Kp, HB, SB);
+        if (!same)
+            hipLaunchKernelGGL(k_corr_prep, dim3((unsigned)((n_b + 3) / 4)), dim3(256), 0, s, B,
+                               n_b, (int)n_bins, Kp, HB, SB);
         const int64_t tiles_m = (n_a + kTM - 1) / kTM, tiles_n = (n_b + kTN - 1) / kTN;
         const int64_t super_m = (tiles_m + kSuperM - 1) / kSuperM;
         const int64_t super_n = (tiles_n + kSuperN - 1) / kSuperN;

@@ -148,6 +148,31 @@ def test_correlation_vs_oracle(env, W, n_a, n_b):
     assert np.all(br[keep] > 1 - 1e-3)
 
 
+def test_correlation_self_equals_copy(env):
+    """One set against itself is converted to fp16 once; the result equals
+    that of the set against a copy of itself, bit for bit, and every image
+    is its own best match."""
+    print("\n[case] correlation of a set with itself", flush=True)
+    torch, si, _, _ = env
+    xyz, nrm = sg.config_scene("prims100k", M=20000)
+    params = si.Params(16, 0.02, S60)
+    sc = si.si_build_scene(dev(torch, xyz), dev(torch, nrm), si.si_support_radius(params))
+    idx = np.arange(0, 20000, 13).astype(np.int32)
+    A, _, _ = si.si_generate(sc, dev(torch, idx), params)
+    R1, b1, r1 = si.si_correlate(A, A)
+    R2, b2, r2 = si.si_correlate(A, A.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(R1, R2) and torch.equal(b1, b2) and torch.equal(r1, r2)
+    # every image with variance correlates with itself to 1 (up to fp16
+    # rounding), and its best match is at least that good
+    Rh = R1.cpu().numpy()
+    diag = np.diag(Rh)
+    var = A.reshape(len(idx), -1).cpu().numpy().astype(np.float64).var(axis=1) > 0
+    assert np.all(diag[var] > 1 - 1e-3)
+    np.testing.assert_array_equal(r1.cpu().numpy(), Rh[np.arange(len(idx)), b1.cpu().numpy()])
+    assert np.all(r1.cpu().numpy()[var] >= diag[var])
+
+
 def test_correlation_errors(env):
     torch, si, _, _ = env
     A = torch.rand((10, 64), device="cuda")
