@@ -649,9 +649,10 @@ si_status si_estimate_normals(const float* points_xyz, int64_t M, float radius,
  * (R is unchanged by that) and rounded to fp16, and all sums are taken from
  * the rounded values.  Rounding moves R by at most about
  * 2u (1 + |R|) (k_P + k_Q), u = 2^-11, k = sqrt(1 + mean^2 / variance) of
- * the image's bins.  Bins must be finite.  Asynchronous on hip_stream; the
- * temporaries (fp16 copies, 2 n_bins bytes per image) come from the
- * device's stream-ordered pool.  n_a or n_b = 0 does nothing.  Returns
+ * the image's bins.  Bins must be finite.  A and B may be the same array
+ * (then, with n_a = n_b, it is converted once).  Asynchronous on
+ * hip_stream; the temporaries (fp16 copies, 2 n_bins bytes per image) come
+ * from the device's stream-ordered pool.  n_a or n_b = 0 does nothing.  Returns
  * SI_E_INVALID for negative sizes, sizes of 2^31 - 1 or more, n_bins out of
  * [2, 65536], NULL inputs or no output.
  */
