@@ -447,11 +447,18 @@ def main():
     stream = torch.cuda.current_stream()
     fac = si.Sched("fac")
 
-    def step():
+    def new_events():
+        # created (and their HIP events made) outside the timed region: the
+        # scene build synchronises, so host work after it delays the kernels
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for e in ev:
+            e.record(stream)
+        return ev
+
+    def step(ev):
         # e0/e1: the whole generation call (cell ordering + spin kernel);
         # e2/e3: recorded by the library around the spin kernel alone
         scene = si.si_build_scene(d_xyz, d_nrm, radius)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record(stream)
         si.si_set_kernel_events(ev[2], ev[3])
         si.si_generate(scene, idx, params, fac, images, counts)
@@ -461,15 +468,15 @@ def main():
 
     log("[bench] warmup")
     for _ in range(args.warmup):
-        step()
+        step(new_events())
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
-    events, scenes = [], []
+    events = [new_events() for _ in range(args.steps)]
+    scenes = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sc, ev = step()
-        events.append(ev)
+    for ev in events:
+        sc, _ = step(ev)
         scenes.append(sc)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
