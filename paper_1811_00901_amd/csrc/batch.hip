@@ -71,6 +71,9 @@ struct FlatMem {
     int32_t* tmp = nullptr;
     unsigned long long* stats = nullptr;  // 4 + n_wg words
     LearnedMulti lm;                      // learned schedule only
+    // host copy of the item table with its device pointers filled in: the
+    // source of an asynchronous upload, so it lives as long as this record
+    std::vector<Item> host_items;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -254,9 +257,11 @@ si_status build_launches(DeviceState* st, const si_batch_item* items, int32_t n_
     return SI_OK;
 }
 
-// Upload the host-side tables into m (synchronous copies from pageable memory).
+// Upload the host-side tables into m, on s; the caller synchronises s before
+// f's tables go (the item table's staged copy lives in m).
 si_status upload(const Flat& f, FlatMem& m, hipStream_t s) {
-    std::vector<Item> items = f.items;
+    std::vector<Item>& items = m.host_items;
+    items = f.items;
     for (size_t i = 0; i < items.size(); ++i)
         items[i].perm = f.learned   ? m.lm.perm + f.item_off[i]
                         : f.ordered ? m.perm + f.item_off[i]

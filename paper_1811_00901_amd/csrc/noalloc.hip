@@ -54,15 +54,18 @@ si_status scratch_of_device(char** out) {
 
 size_t rup256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Host copies of this thread's last chunk tables, in a ring of kRing: a
-// call reuses the oldest once the upload recorded on its event is done, so
-// up to kRing calls can be queued before the host waits.  Their storage is
-// kept between calls.
+// Host copies of this thread's last chunk tables on each device, in a ring
+// of kRing: a call reuses the oldest once the upload recorded on its event
+// (an event of that device) is done, so up to kRing calls can be queued
+// before the host waits.  Their storage is kept between calls.
 constexpr int kRing = 4;
+struct HostRing {
+    std::vector<Chunk> table[kRing];
+    hipEvent_t copied[kRing] = {};
+    int next = 0;
+};
 thread_local std::vector<int64_t> t_starts;
-thread_local std::vector<Chunk> t_table[kRing];
-thread_local hipEvent_t t_copied[kRing] = {};
-thread_local int t_next = 0;
+thread_local std::map<int, HostRing> t_rings;  // device -> ring
 
 }  // namespace
 }  // namespace si
@@ -130,11 +133,13 @@ extern "C" si_status si_generate_noalloc(const si_scene* scene, const int32_t* o
                         " it has");
 
     // ---- chunk table (host), in the oldest ring slot once its upload is done ----
-    const int slot = t_next;
-    t_next = (t_next + 1) % kRing;
-    if (!t_copied[slot]) SI_HIP(hipEventCreateWithFlags(&t_copied[slot], hipEventDisableTiming));
-    SI_HIP(hipEventSynchronize(t_copied[slot]));
-    std::vector<Chunk>& host_table = t_table[slot];
+    HostRing& ring = t_rings[cur_dev];
+    const int slot = ring.next;
+    ring.next = (ring.next + 1) % kRing;
+    hipEvent_t& copied = ring.copied[slot];
+    if (!copied) SI_HIP(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
+    SI_HIP(hipEventSynchronize(copied));
+    std::vector<Chunk>& host_table = ring.table[slot];
     t_starts.resize((size_t)n_chunks + 1);
     chunk_sizes(kind, N, n_wg, sched->min_chunk, dv, t_starts.data(), n_chunks + 1);
     host_table.resize((size_t)n_chunks);
@@ -173,7 +178,7 @@ extern "C" si_status si_generate_noalloc(const si_scene* scene, const int32_t* o
     if (e == hipSuccess)
         e = hipMemcpyAsync(table, host_table.data(), sizeof(Chunk) * (size_t)n_chunks,
                            hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventRecord(t_copied[slot], s);
+    if (e == hipSuccess) e = hipEventRecord(copied, s);
     if (e == hipSuccess && ordered) {
         int32_t* perm = reinterpret_cast<int32_t*>(base + off_order);
         int32_t* key = perm + N;

@@ -929,9 +929,18 @@ si_status rule_setup(int kind, int64_t N, int n_wg, const si_sched* sched, Launc
         R -= std::min(R, c * (int64_t)n_wg);
     }
     // weights: the caller's, else the emulated speeds, else 1; sum n_wg.
-    // The host vector is this thread's, reused once its last upload is done.
-    static thread_local std::vector<float> w;
-    static thread_local hipEvent_t w_copied = nullptr;
+    // The host vector is this thread's for the current device, reused once
+    // its last upload (recorded on an event of that device) is done.
+    struct Upload {
+        std::vector<float> w;
+        hipEvent_t copied = nullptr;
+    };
+    static thread_local std::map<int, Upload> uploads;
+    int dev = 0;
+    SI_HIP(hipGetDevice(&dev));
+    Upload& up = uploads[dev];
+    std::vector<float>& w = up.w;
+    hipEvent_t& w_copied = up.copied;
     if (!w_copied) SI_HIP(hipEventCreateWithFlags(&w_copied, hipEventDisableTiming));
     SI_HIP(hipEventSynchronize(w_copied));
     w.assign(n_wg, 1.0f);
