@@ -144,15 +144,40 @@ __device__ __forceinline__ int key_of_point(const GridDesc& g, float x, float y,
     return ((c[2] * g.dims[1] + c[1]) * g.dims[0] + c[0]) * kSubX + sub;
 }
 
+// Rank of this lane's point among the points of its key: one atomic per run
+// of consecutive lanes with the same key (points in mesh order share cells,
+// so a wave holds few runs), the run's lanes numbered from the base that
+// atomic returns.  `ok` lanes form a prefix of the wave; every lane calls.
+__device__ __forceinline__ int32_t rank_in_key(bool ok, int k, int32_t* counter_of_k) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(k, 1, 64);
+    const bool start = ok && (lane == 0 || prev != k);
+    const uint64_t starts = __builtin_amdgcn_ballot_w64(start);
+    const uint64_t n_ok = (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(ok));
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);  // lanes 0..lane
+    const uint64_t mine = starts & upto;
+    const int run0 = mine ? 63 - __builtin_clzll(mine) : 0;  // this run's first lane
+    const uint64_t later = starts & ~upto;
+    const int run1 = later ? __builtin_ctzll(later) : (int)n_ok;  // the next run's
+    int base = 0;
+    if (start) base = atomicAdd(counter_of_k, run1 - run0);
+    base = __shfl(base, run0, 64);
+    return base + (lane - run0);
+}
+
 __global__ void __launch_bounds__(256) k_bin_points(const float* __restrict__ xyz, int64_t M,
                                                     GridDesc g, int32_t* __restrict__ key_of,
                                                     int32_t* __restrict__ rank,
                                                     int32_t* __restrict__ counts) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= M) return;
-    const int k = key_of_point(g, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
-    key_of[i] = k;
-    rank[i] = atomicAdd(counts + k, 1);
+    const bool ok = i < M;
+    int k = -1;
+    if (ok) {
+        k = key_of_point(g, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
+        key_of[i] = k;
+    }
+    const int32_t r = rank_in_key(ok, k, counts + (ok ? k : 0));
+    if (ok) rank[i] = r;
 }
 
 // Tile sums of the input.
@@ -176,21 +201,30 @@ __global__ void __launch_bounds__(256) k_scan_tiles(const T* __restrict__ in, in
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = red[0];
 }
 
-// Exclusive block scan of 256 values; returns the exclusive prefix, *total.
+// Exclusive block scan of 256 values (four waves); returns the exclusive
+// prefix, *total.  Each wave scans with shuffles; the four wave totals meet
+// in s (at least 4 entries), two barriers in all.
 template <typename T>
 __device__ T block_excl_scan(T v, T* s, T* total) {
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const T t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-        __syncthreads();
-        s[threadIdx.x] += t;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const T y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
     }
-    const T incl = s[threadIdx.x];
-    *total = s[255];
+    if (lane == 63) s[w] = x;
     __syncthreads();
-    return incl - v;
+    T before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T t = s[k];
+        if (k < w) before += t;
+        all += t;
+    }
+    __syncthreads();  // s may be reused
+    *total = all;
+    return before + x - v;
 }
 
 // Exclusive scan of the tile sums in place (one workgroup).
@@ -219,20 +253,50 @@ __global__ void __launch_bounds__(256) k_scan_apply(const T* __restrict__ in, in
                                                     const T* __restrict__ tile_off,
                                                     T* __restrict__ out) {
     __shared__ T s[256];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * (kScanTile / 256);
-    T v[kScanTile / 256];
+    constexpr int PER = kScanTile / 256;  // consecutive elements per thread
+    constexpr int VEC = 16 / sizeof(T);   // elements per 16-byte access
+    static_assert(PER % VEC == 0, "whole 16-byte accesses per thread");
+    typedef __attribute__((ext_vector_type(VEC))) T vec_t;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * PER;
+    // whole 16-byte accesses where the thread's elements are all in range
+    // and both addresses are 16-byte aligned (callers' arrays need not be)
+    const bool whole = base + PER <= n &&
+                       ((reinterpret_cast<uintptr_t>(in + base) |
+                         reinterpret_cast<uintptr_t>(out + base)) & 15) == 0;
+    T v[PER];
     T sum = 0;
+    if (whole) {
 #pragma unroll
-    for (int k = 0; k < kScanTile / 256; ++k) {
-        v[k] = (base + k < n) ? in[base + k] : 0;
-        sum += v[k];
+        for (int k = 0; k < PER; k += VEC) {
+            const vec_t x = *reinterpret_cast<const vec_t*>(in + base + k);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) v[k + j] = x[j];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) v[k] = (base + k < n) ? in[base + k] : 0;
     }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sum += v[k];
     T total;
     T run = block_excl_scan(sum, s, &total) + tile_off[blockIdx.x];
+    if (whole) {
 #pragma unroll
-    for (int k = 0; k < kScanTile / 256; ++k) {
-        if (base + k < n) out[base + k] = run;
-        run += v[k];
+        for (int k = 0; k < PER; k += VEC) {
+            vec_t x;
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                x[j] = run;
+                run += v[k + j];
+            }
+            *reinterpret_cast<vec_t*>(out + base + k) = x;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (base + k < n) out[base + k] = run;
+            run += v[k];
+        }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = tile_off[blockIdx.x] + total;
 }
@@ -261,13 +325,18 @@ __global__ void __launch_bounds__(256) k_bin_points_multi(const BuildItem* __res
                                                           int32_t* __restrict__ rank,
                                                           int32_t* __restrict__ counts) {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= total_M) return;
-    const int s = find_item_block(pt_off, n, t);
-    const BuildItem& it = items[s];
-    const int64_t i = t - pt_off[s];
-    const int k = key_of_point(it.g, it.xyz[3 * i], it.xyz[3 * i + 1], it.xyz[3 * i + 2]);
-    key_of[t] = k;
-    rank[t] = atomicAdd(counts + it.key_base + k, 1);
+    const bool ok = t < total_M;
+    int k = -1;  // the key in the concatenated key space
+    if (ok) {
+        const int s = find_item_block(pt_off, n, t);
+        const BuildItem& it = items[s];
+        const int64_t i = t - pt_off[s];
+        const int kk = key_of_point(it.g, it.xyz[3 * i], it.xyz[3 * i + 1], it.xyz[3 * i + 2]);
+        key_of[t] = kk;
+        k = (int)(it.key_base + kk);
+    }
+    const int32_t r = rank_in_key(ok, k, counts + (ok ? k : 0));
+    if (ok) rank[t] = r;
 }
 
 // sub_start of every scene from the scan of the concatenated counts:
