@@ -545,10 +545,9 @@ int64_t si_rule_af_chunk(double var_over_mu_sum, double inv_mu_sum, int32_t n_me
 
 /*
  * si_generate without allocation, for callers that cannot allocate device
- * memory: code under HIP graph capture, tight serving loops, harnesses that
- * forbid hipMalloc.  Same arguments and results as si_generate (images and
- * counts identical to its for the same scene, indices, params and
- * schedule), without statistics.  What si_generate allocates per call (the
+ * memory: tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments and results as si_generate (images and counts identical to its
+ * for the same scene, indices, params and schedule), without statistics.  What si_generate allocates per call (the
  * claim counter, the chunk table, the temporaries of the cell-sorted loop
  * order) lives in one static device array of SI_NOALLOC_SCRATCH_BYTES that
  * each device holds from the library's load until the process ends; the
@@ -567,8 +566,10 @@ int64_t si_rule_af_chunk(double var_over_mu_sum, double inv_mu_sum, int32_t n_me
  * into one of four vectors kept per thread and copied with hipMemcpyAsync
  * on hip_stream; a call first waits for the upload made four calls before
  * from the same vector (events created at the thread's first calls), so
- * up to four calls are queued before the host waits.  Invalid indices are
- * reported by si_device_errors.
+ * up to four calls are queued before the host waits.  Because a graph would
+ * replay that copy from storage later calls refill, a hip_stream that is
+ * capturing returns SI_E_UNSUPPORTED before anything is enqueued.  Invalid
+ * indices are reported by si_device_errors.
  */
 #define SI_NOALLOC_SCRATCH_BYTES (64u << 20)
 si_status si_generate_noalloc(const si_scene* scene, const int32_t* oriented_idx, int64_t N,

@@ -1,6 +1,6 @@
 // si_generate_noalloc: spin-image generation that allocates no memory, for
-// callers that cannot allocate (code under HIP graph capture, tight serving
-// loops, harnesses that forbid it).
+// callers that cannot allocate (tight serving loops, harnesses that forbid
+// it).  It is not for stream capture: a capturing stream is refused.
 //
 // It runs the same kernels as si_generate (Section 2.1, Algorithm 1 per
 // image; the chunks of Section 2.2 claimed through one counter).  What
@@ -99,6 +99,15 @@ extern "C" si_status si_generate_noalloc(const si_scene* scene, const int32_t* o
     SI_HIP(hipGetDevice(&cur_dev));
     if (cur_dev != scene->device) return fail(SI_E_INVALID, "scene lives on another device");
     hipStream_t s = (hipStream_t)hip_stream;
+    // A captured copy would read the host table at every replay, from storage
+    // that later calls refill (and the wait on an earlier upload is not
+    // allowed under capture): refuse before anything is enqueued.
+    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
+    SI_HIP(hipStreamIsCapturing(s, &capture));
+    if (capture != hipStreamCaptureStatusNone)
+        return fail(SI_E_UNSUPPORTED,
+                    "si_generate_noalloc cannot be captured into a graph: its chunk table is "
+                    "copied from host memory that later calls reuse");
     DeviceState* st;
     rc = device_state(&st);  // attributes only: allocates nothing
     if (rc != SI_OK) return rc;

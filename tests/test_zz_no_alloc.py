@@ -138,3 +138,32 @@ def test_noalloc_queued_calls(env):
         torch.cuda.synchronize()
         assert torch.equal(cnt, rcnt) and torch.equal(img, rimg), sched.kind
     si.si_device_errors()
+
+
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
+def test_noalloc_refuses_stream_capture(env):
+    """A capturing stream is refused before anything is enqueued (a graph
+    would replay the table copy from a host buffer that later calls refill);
+    the same call outside the capture then matches si_generate."""
+    print("\n[case] noalloc under stream capture", flush=True)
+    torch, si, _ = env
+    params = si.Params(32, 0.02, S60)
+    xyz, nrm = sg.config_scene("prims100k", M=6_000)
+    scene = si.si_build_scene(to_dev(torch, xyz), to_dev(torch, nrm), si.si_support_radius(params))
+    idx = to_dev(torch, np.arange(0, 6_000, 2, dtype=np.int32))
+    img = torch.zeros((3_000, 32, 32), dtype=torch.float32, device="cuda")
+    cnt = torch.zeros((3_000,), dtype=torch.int32, device="cuda")
+    sched = si.Sched("fac")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with pytest.raises(si.SiError) as e:
+        with torch.cuda.graph(graph):
+            si.si_generate_noalloc(scene, idx, params, sched, img, cnt)
+    assert e.value.status == -4 and "captured" in str(e.value)
+    torch.cuda.synchronize()
+    assert int(cnt.abs().sum()) == 0  # nothing ran
+    si.si_generate_noalloc(scene, idx, params, sched, img, cnt)
+    rimg, rcnt, _ = si.si_generate(scene, idx, params, sched)
+    torch.cuda.synchronize()
+    assert torch.equal(cnt, rcnt) and torch.equal(img, rimg)
+    si.si_device_errors()
