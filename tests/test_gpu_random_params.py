@@ -6,7 +6,9 @@ thousand points), W in [2, 64], the bin width, the support angle (the angle
 test disabled at pi or more, as with the paper's 2 pi), the binning mode, the
 schedule (the paper's four, the later techniques, and the worker-sized ones),
 the loop order, the group size, the workgroup count, a cell-list or a
-single-cell (brute-force) scene, and oriented indices drawn with repetition.
+single-cell (brute-force) scene, oriented indices drawn with repetition, a
+shift of the whole scene away from the origin (its float32 coordinates are
+what both sides read) and duplicated points (coincident pairs, alpha = 0).
 """
 import math
 
@@ -24,7 +26,8 @@ KINDS = ["static", "ss", "gss", "fac", "tss", "fac_prob", "wf", "awf", "af"]
 ORDERS = ["spread", "cell", "given"]
 GROUPS = [0, 1, 2, 3, 4, 6, 8]
 WORKGROUPS = [0, 1, 7, 97, 1000]
-N_CASES = 16
+N_CASES = 64
+SHIFTS = [0.0, 0.0, 0.0, 37.5, -250.0, 1000.0]
 _pairs = {}  # seed -> in-support pairs binned, for the summary test
 
 
@@ -56,6 +59,8 @@ def draw(seed):
     c["idx"] = rng.integers(0, c["M"], c["N"]).astype(np.int32)  # with repetition
     c["divisor"] = float(rng.choice([0.0, 1.5, 3.0])) if c["kind"] != "fac_prob" else 0.8
     c["min_chunk"] = int(rng.choice([0, 1, 5]))
+    c["shift"] = float(rng.choice(SHIFTS))
+    c["dup"] = bool(rng.random() < 0.2)
     return c
 
 
@@ -69,6 +74,14 @@ def test_random_parameters_vs_oracle(env, seed):
         xyz, nrm = sg.config_scene("prims100k", M=c["M"])
     else:
         xyz, nrm = sg.uniform_box_scene(c["M"], seed=seed, box=1.0)
+    if c["dup"]:  # 5 % of the points become copies of others, normals included
+        g = np.random.default_rng(9000 + seed)
+        dst = g.choice(c["M"], c["M"] // 20, replace=False)
+        src = g.integers(0, c["M"], dst.shape[0])
+        xyz, nrm = xyz.copy(), nrm.copy()
+        xyz[dst], nrm[dst] = xyz[src], nrm[src]
+    if c["shift"]:
+        xyz = (xyz.astype(np.float64) + c["shift"]).astype(np.float32)
     mode = "bilinear" if c["mode"] == 0 else "ceil"
     params = si.Params(c["W"], c["bin"], c["S"], mode)
     radius = 0.0 if c["brute"] else si.si_support_radius(params)
