@@ -189,9 +189,14 @@ typedef __attribute__((address_space(1))) void glb_void_t;
 // while the products of stage s run, the loads of stages s + 1 and s + 2 are
 // in flight.  A stage is 24 groups of 16 rows x 64 bytes, three per wave; in
 // a group, lane l fills bytes 16 l .. 16 l + 15, i.e. row l / 4, slot l % 4,
-// and loads the chunk (l % 4) ^ (row % 4) of that row, so that each row's
-// four 16-byte chunks sit XOR-swizzled by the row's low bits and the rows one
-// ds_read_b128 pass reads fall in distinct banks.  Each iteration waits on
+// and loads the chunk (l % 4) ^ ((row / 2) % 4) of that row, so that each
+// row's four 16-byte chunks sit XOR-swizzled by bits 1-2 of the row.  Taking
+// a ds_read_b128 as eight lanes (128 bytes over 32 banks) per pass, a
+// fragment read's pass covers eight consecutive rows at one logical chunk,
+// in 16-byte slots 4 (row % 2) + chunk ^ ((row / 2) % 4): all distinct.
+// (Swizzled by the row's low bits, rows r and r + 2 shared banks; by bits
+// 2-3, right for 16 lanes per pass, it ran no faster: the measured order
+// matches the eight-lane model.)  Each iteration waits on
 // vmcnt for this wave's loads of stage s only, then a barrier (with no
 // memory fence, which would wait for every load in flight) makes all waves'
 // loads of stage s visible and guarantees that the stage read two iterations
@@ -226,11 +231,11 @@ __global__ void __launch_bounds__(kGemmThreads, 2)
     const int64_t m0 = tm * kTM, n0 = tn * kTN;
     const int wm = wave / kWavesN, wn = wave % kWavesN;
     const int r16 = lane & 15, kq = lane >> 4;
-    auto off = [](int row, int ch) { return row * kBK + 8 * (ch ^ (row & (CPR - 1))); };
+    auto off = [](int row, int ch) { return row * kBK + 8 * (ch ^ ((row >> 1) & (CPR - 1))); };
     // this lane's sources: groups wave, wave + 8, wave + 16 of the stage's
     // rows (A's 256, then B's 128)
     const int lr = lane >> 2;
-    const int lch = (lane & 3) ^ (lr & 3);
+    const int lch = (lane & 3) ^ ((lr >> 1) & 3);
     const _Float16* src[PW];
     int dst[PW];
 #pragma unroll
