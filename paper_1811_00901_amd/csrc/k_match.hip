@@ -6,7 +6,9 @@
 //   query point searches the scene's cell grid in shells of cells at
 //   Chebyshev distance r = 0, 1, 2, ... from its own cell; every point not yet
 //   searched is farther than r h, so the search stops as soon as the best
-//   distance is within r h (exact, whatever the spacing).
+//   distance is within r h (exact, whatever the spacing).  Inside a shell,
+//   cells and their quarter runs along x that lie farther than the best
+//   distance so far are skipped.
 // * Spin-image correlation (si_correlate): the normalised linear correlation
 //   coefficient of two images' bins, the comparison by which spin images are
 //   matched in object recognition (Johnson and Hebert, cited by the paper):
@@ -52,26 +54,53 @@ __global__ void __launch_bounds__(256) k_nn(SceneView sc, const int32_t* __restr
             const int c2 = cell / (sc.dims[0] * sc.dims[1]);
             const int rmax = max(max(max(c0, sc.dims[0] - 1 - c0), max(c1, sc.dims[1] - 1 - c1)),
                                  max(c2, sc.dims[2] - 1 - c2));
+            // boxes in float32 relative to the grid's origin: a box is skipped
+            // only when it is farther than the best distance by more than
+            // eps, many ulp of the largest coordinate (as the spin kernel's
+            // row culling), so rounding never skips a nearer point
+            const float h = (float)sc.h, hq = (float)(sc.h / kSubX);
+            float mag = 0.0f;
+            for (int a = 0; a < 3; ++a)
+                mag = fmaxf(mag, fabsf(sc.origin[a]) + (float)sc.dims[a] * h);
+            const float eps = 2e-6f * mag + 1e-6f;
+            const float ox = p.x - sc.origin[0], oy = p.y - sc.origin[1], oz = p.z - sc.origin[2];
+            // distance from the point to [lo, lo + w] along one axis, less eps
+            auto gap = [eps](float o, float lo, float w) {
+                return fmaxf(0.0f, fmaxf(lo - o, o - (lo + w)) - eps);
+            };
+            const int qp = min(max((int)floorf((ox - (float)c0 * h) / hq), 0), kSubX - 1);
             float best = __int_as_float(0x7f800000);
             for (int r = 0; r <= rmax; ++r) {
                 for (int dz = -r; dz <= r; ++dz) {
                     const int z = c2 + dz;
                     if (z < 0 || z >= sc.dims[2]) continue;
+                    const float gz = gap(oz, (float)z * h, h);
                     for (int dy = -r; dy <= r; ++dy) {
                         const int y = c1 + dy;
                         if (y < 0 || y >= sc.dims[1]) continue;
+                        const float gy = gap(oy, (float)y * h, h);
+                        const float dyz = fmaf(gz, gz, gy * gy);
+                        if (dyz > best) continue;
                         // on the shell: all of x when y or z is at distance r
                         const bool face = (dz == -r || dz == r || dy == -r || dy == r);
                         for (int dx = -r; dx <= r; dx += (face || r == 0) ? 1 : 2 * r) {
                             const int x = c0 + dx;
                             if (x < 0 || x >= sc.dims[0]) continue;
                             const int key = ((z * sc.dims[1] + y) * sc.dims[0] + x) * kSubX;
-                            const int a = sc.sub_start[key], b = sc.sub_start[key + kSubX];
-                            for (int j = a; j < b; ++j) {
-                                if (j == sp) continue;
-                                const float4 q = sc.pos[j];
-                                const float ex = q.x - p.x, ey = q.y - p.y, ez = q.z - p.z;
-                                best = fminf(best, fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
+                            // the cell's quarter runs along x, nearest first
+                            for (int t = 0; t < kSubX; ++t) {
+                                const int q = x < c0 ? kSubX - 1 - t
+                                              : x > c0 ? t
+                                              : (t == 0 ? qp : (t - 1 < qp ? t - 1 : t));
+                                const float gx = gap(ox, (float)x * h + (float)q * hq, hq);
+                                if (fmaf(gx, gx, dyz) > best) continue;
+                                const int a = sc.sub_start[key + q], b = sc.sub_start[key + q + 1];
+                                for (int j = a; j < b; ++j) {
+                                    if (j == sp) continue;
+                                    const float4 w = sc.pos[j];
+                                    const float ex = w.x - p.x, ey = w.y - p.y, ez = w.z - p.z;
+                                    best = fminf(best, fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
+                                }
                             }
                         }
                     }
