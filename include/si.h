@@ -30,6 +30,11 @@
  *     uploaded on the stream of their first use (from pinned staging, without
  *     waiting) and cached (64 per device; the least recently used is freed
  *     once the launches that read it are done).
+ *   - si_build_scene(s), si_generate, si_generate_batched, si_autotune and
+ *     si_generate_noalloc upload host data or wait on the host, so they
+ *     cannot be captured into a graph: on a capturing hip_stream they return
+ *     SI_E_UNSUPPORTED before enqueuing anything.  si_generate_batched with
+ *     use_graph = 1 captures and replays a graph of its own instead.
  *   - Distinct scenes, models and streams may be used from different threads.
  *     Calls that run concurrently on different streams share a pool of 64
  *     work-counter slots per device, so at most 64 generation launches may be
@@ -568,8 +573,8 @@ int64_t si_rule_af_chunk(double var_over_mu_sum, double inv_mu_sum, int32_t n_me
  * from the same vector (events created at the thread's first calls), so
  * up to four calls are queued before the host waits.  Because a graph would
  * replay that copy from storage later calls refill, a hip_stream that is
- * capturing returns SI_E_UNSUPPORTED before anything is enqueued.  Invalid
- * indices are reported by si_device_errors.
+ * capturing returns SI_E_UNSUPPORTED before anything is enqueued (as for
+ * si_generate).  Invalid indices are reported by si_device_errors.
  */
 #define SI_NOALLOC_SCRATCH_BYTES (64u << 20)
 si_status si_generate_noalloc(const si_scene* scene, const int32_t* oriented_idx, int64_t N,

@@ -164,8 +164,10 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
     if (kind < SI_SCHED_STATIC || kind > SI_SCHED_FAC_PROB) return fail(SI_E_INVALID, "bad kind");
     if (max_trials < 1) max_trials = 1;
     hipStream_t s = (hipStream_t)hip_stream;
+    si_status rc = refuse_capture(s, "si_autotune");
+    if (rc != SI_OK) return rc;
     DeviceState* st;
-    si_status rc = device_state(&st);
+    rc = device_state(&st);
     if (rc != SI_OK) return rc;
 
     si_sched base;

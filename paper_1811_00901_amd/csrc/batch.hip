@@ -542,6 +542,8 @@ extern "C" si_status si_generate_batched(const si_batch_item* items, int32_t n_i
         return fail(SI_E_UNSUPPORTED, "SI_SCHED_WF, AWF and AF run in si_generate only");
     if (rc != SI_OK) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
+    rc = refuse_capture(s, "si_generate_batched");
+    if (rc != SI_OK) return rc;
     DeviceState* st;
     rc = device_state(&st);
     if (rc != SI_OK) return rc;

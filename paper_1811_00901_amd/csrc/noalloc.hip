@@ -99,15 +99,10 @@ extern "C" si_status si_generate_noalloc(const si_scene* scene, const int32_t* o
     SI_HIP(hipGetDevice(&cur_dev));
     if (cur_dev != scene->device) return fail(SI_E_INVALID, "scene lives on another device");
     hipStream_t s = (hipStream_t)hip_stream;
-    // A captured copy would read the host table at every replay, from storage
-    // that later calls refill (and the wait on an earlier upload is not
-    // allowed under capture): refuse before anything is enqueued.
-    hipStreamCaptureStatus capture = hipStreamCaptureStatusNone;
-    SI_HIP(hipStreamIsCapturing(s, &capture));
-    if (capture != hipStreamCaptureStatusNone)
-        return fail(SI_E_UNSUPPORTED,
-                    "si_generate_noalloc cannot be captured into a graph: its chunk table is "
-                    "copied from host memory that later calls reuse");
+    // a captured copy would read the host table at every replay, from storage
+    // that later calls refill
+    rc = refuse_capture(s, "si_generate_noalloc");
+    if (rc != SI_OK) return rc;
     DeviceState* st;
     rc = device_state(&st);  // attributes only: allocates nothing
     if (rc != SI_OK) return rc;

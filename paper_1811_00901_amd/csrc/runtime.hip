@@ -34,6 +34,22 @@ si_status hip_fail(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? SI_E_OOM : SI_E_DEVICE;
 }
 
+// Entry points that upload host data or wait on the host cannot be captured
+// into a graph: a replay would repeat an upload from host storage that later
+// calls refill, and the waits are not allowed under capture.  They refuse a
+// capturing stream before enqueuing anything.
+si_status refuse_capture(hipStream_t s, const char* what) {
+    hipStreamCaptureStatus c = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(s, &c);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (c != hipStreamCaptureStatusNone)
+        return fail(SI_E_UNSUPPORTED,
+                    std::string(what) + " cannot be captured into a graph: it uploads host data "
+                    "or waits on the host (si_generate_batched with use_graph = 1 replays "
+                    "a graph of its own)");
+    return SI_OK;
+}
+
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t s) {
     if (const char* lim = getenv("SI_TEST_ALLOC_FAIL")) {
         if (bytes >= (size_t)strtoull(lim, nullptr, 10)) {
@@ -457,8 +473,10 @@ si_status si_build_scene(const float* points_xyz, const float* normals_xyz, int6
     if (M <= 0 || M >= INT32_MAX) return fail(SI_E_INVALID, "M must be in [1, 2^31 - 1)");
     if (!isfinite(max_support_radius)) return fail(SI_E_INVALID, "max_support_radius not finite");
     hipStream_t s = (hipStream_t)hip_stream;
+    si_status rc = refuse_capture(s, "si_build_scene");
+    if (rc != SI_OK) return rc;
     DeviceState* st;
-    si_status rc = device_state(&st);
+    rc = device_state(&st);
     if (rc != SI_OK) return rc;
 
     si_scene* sc = new (std::nothrow) si_scene();
@@ -539,8 +557,10 @@ si_status si_build_scenes(const si_scene_desc* descs, int32_t n, void* hip_strea
             return fail(SI_E_INVALID, at + "max_support_radius not finite");
     }
     hipStream_t s = (hipStream_t)hip_stream;
+    si_status rc = refuse_capture(s, "si_build_scenes");
+    if (rc != SI_OK) return rc;
     DeviceState* st;
-    si_status rc = device_state(&st);
+    rc = device_state(&st);
     if (rc != SI_OK) return rc;
     int dev = 0;
     SI_HIP(hipGetDevice(&dev));
@@ -1004,6 +1024,8 @@ extern "C" si_status si_generate(const si_scene* scene, const int32_t* oriented_
     SI_HIP(hipGetDevice(&cur_dev));
     if (cur_dev != scene->device) return fail(SI_E_INVALID, "scene lives on another device");
     hipStream_t s = (hipStream_t)hip_stream;
+    rc = refuse_capture(s, "si_generate");
+    if (rc != SI_OK) return rc;
     DeviceState* st;
     rc = device_state(&st);
     if (rc != SI_OK) return rc;

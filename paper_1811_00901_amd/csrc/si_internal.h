@@ -19,6 +19,8 @@ namespace si {
 void set_error(const std::string& msg);
 si_status fail(si_status st, const std::string& msg);
 si_status hip_fail(hipError_t e, const char* what);
+// SI_E_UNSUPPORTED when s is capturing (`what` names the entry point)
+si_status refuse_capture(hipStream_t s, const char* what);
 
 #define SI_HIP(call)                                         \
     do {                                                     \
