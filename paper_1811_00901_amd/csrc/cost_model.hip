@@ -700,12 +700,12 @@ __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restri
                                                          int64_t n_units, int P, float divisor,
                                                          Chunk* __restrict__ chunks,
                                                          int32_t* __restrict__ n_chunks) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t total = cpre[n_units];
     __shared__ int64_t start;
     __shared__ int emitted;
     __shared__ int32_t ends[kMaxLearnedP + 1];
-    __shared__ int pos[1024];
+    __shared__ int wsum[1024 / 64];
     __shared__ int64_t samp[kCostSamples];
     if (tid == 0) {
         start = 0;
@@ -730,15 +730,22 @@ __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restri
             const int j = tid * kPerThread + r + 1;
             if (j <= P && ends[j] > ends[j - 1]) ++mine;
         }
-        pos[tid] = mine;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int t = tid >= off ? pos[tid - off] : 0;
-            __syncthreads();
-            pos[tid] += t;
-            __syncthreads();
+        // block scan: shuffles inside each wave, then the 16 wave totals
+        int incl = mine;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
         }
-        int w = emitted + pos[tid] - mine;
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int before = 0, all = 0;
+        for (int q = 0; q < 1024 / 64; ++q) {
+            const int t = wsum[q];
+            before += q < wave ? t : 0;
+            all += t;
+        }
+        int w = emitted + before + incl - mine;
         for (int r = 0; r < kPerThread; ++r) {
             const int j = tid * kPerThread + r + 1;
             if (j <= P && ends[j] > ends[j - 1]) {
@@ -751,7 +758,7 @@ __global__ void __launch_bounds__(1024) k_learned_chunks(const int64_t* __restri
         }
         __syncthreads();
         if (tid == 0) {
-            emitted += pos[1023];
+            emitted += all;
             start = ends[P];
         }
         __syncthreads();
