@@ -113,12 +113,15 @@ typedef struct si_params {
  * Schedule of the per-image loop over P persistent workgroups.
  *   kind            SI_SCHED_*
  *   num_workgroups  P; 0 = library default for the device and W
- *   min_chunk       lower bound of every dynamic chunk (0 or 1 = none)
+ *   min_chunk       lower bound of every dynamic chunk (0 or 1 = none;
+ *                   0 in a batched SI_SCHED_FAC launch over several scenes
+ *                   takes 16)
  *   fac_divisor     x of SI_SCHED_FAC / SI_SCHED_LEARNED; 0 = 2 (FAC2), except
  *                   that a batched SI_SCHED_FAC launch over several scenes
- *                   takes 4 (their concatenated loop's iteration costs vary
+ *                   takes 12 (their concatenated loop's iteration costs vary
  *                   far more than one scene's, and the batch ratio grows
- *                   with that variation).
+ *                   with that variation; smaller first batches also keep
+ *                   the workgroups running at once on fewer scenes).
  *                   For SI_SCHED_FAC_PROB: cv = sigma / mu of the per-image
  *                   cost (>= 0), which sets each batch's ratio x_j
  *                   (Hummel, Schonberg and Flynn 1992): with

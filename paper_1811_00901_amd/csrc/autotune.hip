@@ -257,7 +257,7 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
             rc = try_set(c);
         }
         if (kind == SI_SCHED_FAC || kind == SI_SCHED_LEARNED) {
-            for (float x : {4.0f, 3.0f, 1.5f, 2.0f}) {
+            for (float x : {4.0f, 8.0f, 12.0f, 16.0f, 3.0f, 1.5f, 2.0f}) {
                 if (rc != SI_OK || x == cur.fac_divisor) continue;
                 si_sched c = cur;
                 c.fac_divisor = x;

@@ -224,14 +224,17 @@ si_status build_flat(DeviceState* st, const si_batch_item* items, const std::vec
         f.divisor = sched->fac_divisor;
     } else {
         // FAC's default ratio: x = 2 (FAC2) assumes iterations of similar
-        // cost, as in one spread-ordered scene; a concatenation of several
+        // cost, as in one spread-ordered scene.  A concatenation of several
         // scenes (other widths, densities and sizes) varies much more, and
-        // factoring's batch ratio grows with the cost variation, so a launch
-        // over several items takes x = 4 unless the caller sets one
-        const float dv = sched->fac_divisor > 0.0f ? sched->fac_divisor
-                         : (f.kind == SI_SCHED_FAC && f.items.size() > 1) ? 4.0f
-                                                                           : 0.0f;
-        flat_chunks(f, sched->min_chunk, dv);
+        // factoring's batch ratio grows with the cost variation; a larger
+        // ratio also makes the first batches cover fewer items, so the
+        // workgroups running at once share fewer scenes in the L2.  A launch
+        // over several items takes x = 12 and chunks of at least 16 images
+        // unless the caller sets them.
+        const bool multi = f.kind == SI_SCHED_FAC && f.items.size() > 1;
+        const float dv = sched->fac_divisor > 0.0f ? sched->fac_divisor : multi ? 12.0f : 0.0f;
+        const int mc = sched->min_chunk > 0 ? sched->min_chunk : multi ? 16 : 0;
+        flat_chunks(f, mc, dv);
     }
     return SI_OK;
 }
