@@ -363,15 +363,19 @@ si_status si_generate_batched(const si_batch_item* items, int32_t n_items,
  * si_generate_batched; one item for a single scene) for scheduling technique
  * `kind`.  Tuned: group (images per shared candidate pass, from 1, 2, 4, 6,
  * 8), num_workgroups (2, 3, 4, 5, 6 or 8 per compute unit), fac_divisor (FAC and
- * LEARNED: 1.5, 2, 3, 4) and min_chunk (dynamic techniques: 0, 4, 16), by two
- * sweeps of coordinate descent from the library's defaults (group and
- * num_workgroups 0: chosen per launch; a tuned value applies to every launch),
+ * LEARNED: 1.5, 2, 3, 4, 8, 12, 16), min_chunk (dynamic techniques: 0, 4, 16)
+ * and, jointly with chunk sizes, the loop order (dynamic techniques other
+ * than LEARNED: order, min_chunk and, for FAC, fac_divisor set together to
+ * cell 32 x16, cell 32 x64, cell 16 x16 or spread 16 x12; small chunks over
+ * the cell order make every workgroup sweep the scene at once, which keeps
+ * the groups running together on shared candidates), by two sweeps of
+ * coordinate descent from the library's defaults (group and num_workgroups
+ * 0: chosen per launch; a tuned value applies to every launch),
  * at most max_trials timed candidates (each the median of two launches after
  * a warm-up).  Every candidate's images and counts must give the same 64-bit
- * checksum as the first one,
- * else SI_E_DEVICE.  The winner is written to *best (kind and order filled,
- * model NULL) and its time to *best_ms (host, may be NULL).  Winners are
- * cached per (device, kind, use_graph, image widths, size class) in memory
+ * checksum as the first one, else SI_E_DEVICE.  The winner is written to
+ * *best (kind filled, model NULL) and its time to *best_ms (host, may be
+ * NULL).  Winners are cached per (device, kind, use_graph, image widths, size class) in memory
  * and, when the environment variable SI_AUTOTUNE_CACHE names a file, in that
  * file (one JSON object per line; unreadable lines are ignored).  A cached
  * winner is returned without running unless force = 1.  The items' output

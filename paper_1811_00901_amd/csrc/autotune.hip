@@ -3,8 +3,9 @@
 // The scheduling technique is the caller's choice (Section 2.2); what is tuned
 // here are the knobs of this implementation that do not change any image:
 // images per shared candidate pass (group), persistent workgroups (P), the
-// factoring divisor x and the minimum chunk.  The search is coordinate descent
-// (two sweeps) from the library defaults, each candidate timed with HIP events
+// factoring divisor x, the minimum chunk and the loop order.  The search is
+// coordinate descent (two sweeps) from the library defaults, with the loop
+// order tried jointly with chunk sizes, each candidate timed with HIP events
 // on the caller's workload; every candidate's images and counts must hash to
 // the same 64-bit checksum as the first one.  Winners are cached per (device,
 // technique, image widths, size class), in memory and optionally in a JSON
@@ -51,7 +52,7 @@ __global__ void __launch_bounds__(256) k_checksum(const uint32_t* __restrict__ a
 }
 
 struct Tuned {
-    int group = 0, num_workgroups = 0, min_chunk = 0;
+    int group = 0, num_workgroups = 0, min_chunk = 0, order = SI_ORDER_SPREAD;
     float divisor = 0.0f;
     double ms = 0.0;
 };
@@ -62,7 +63,8 @@ bool g_loaded = false;
 
 const char* cache_path() { return getenv("SI_AUTOTUNE_CACHE"); }
 
-// One entry per line: {"key": "...", "group": g, "workgroups": p, "divisor": x, "min_chunk": m, "ms": t}
+// One entry per line: {"key": "...", "group": g, "workgroups": p, "divisor": x, "min_chunk": m,
+// "order": o, "ms": t} (group and workgroups 0 = the library's per-launch defaults)
 void load_cache() {
     if (g_loaded) return;
     g_loaded = true;
@@ -76,10 +78,12 @@ void load_cache() {
         Tuned t;
         if (sscanf(line,
                    " {\"key\": \"%511[^\"]\", \"group\": %d, \"workgroups\": %d, \"divisor\": %f, "
-                   "\"min_chunk\": %d, \"ms\": %lf}",
-                   key, &t.group, &t.num_workgroups, &t.divisor, &t.min_chunk, &t.ms) == 6) {
-            if (t.group >= 1 && t.group <= kMaxGroup && t.num_workgroups >= 1 &&
-                t.divisor >= 0.0f && t.min_chunk >= 0)
+                   "\"min_chunk\": %d, \"order\": %d, \"ms\": %lf}",
+                   key, &t.group, &t.num_workgroups, &t.divisor, &t.min_chunk, &t.order,
+                   &t.ms) == 7) {
+            if (t.group >= 0 && t.group <= kMaxGroup && t.num_workgroups >= 0 &&
+                t.divisor >= 0.0f && t.min_chunk >= 0 && t.order >= SI_ORDER_SPREAD &&
+                t.order <= SI_ORDER_GIVEN)
                 g_tuned[key] = t;  // malformed lines are ignored
         }
     }
@@ -95,9 +99,9 @@ void save_cache() {
     for (auto& kv : g_tuned)
         fprintf(f,
                 "{\"key\": \"%s\", \"group\": %d, \"workgroups\": %d, \"divisor\": %.3f, "
-                "\"min_chunk\": %d, \"ms\": %.4f}\n",
+                "\"min_chunk\": %d, \"order\": %d, \"ms\": %.4f}\n",
                 kv.first.c_str(), kv.second.group, kv.second.num_workgroups, kv.second.divisor,
-                kv.second.min_chunk, kv.second.ms);
+                kv.second.min_chunk, kv.second.order, kv.second.ms);
     fclose(f);
     rename(tmp.c_str(), path);
 }
@@ -186,6 +190,7 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
             best->num_workgroups = it->second.num_workgroups;
             best->fac_divisor = it->second.divisor;
             best->min_chunk = it->second.min_chunk;
+            best->order = it->second.order;
             if (best_ms) *best_ms = it->second.ms;
             return SI_OK;
         }
@@ -242,6 +247,27 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
     };
     // two sweeps of coordinate descent while the trial budget lasts
     for (int sweep = 0; sweep < 2 && rc == SI_OK && trials < max_trials; ++sweep) {
+        // loop order with chunk sizes, jointly: small chunks over the
+        // contiguous cell order make every workgroup sweep the scene at
+        // once, so the candidates of the groups running together share the
+        // L2 (large chunks there give each workgroup its own region and
+        // dense clusters to a few); ratios x for the factoring kinds
+        if (kind != SI_SCHED_STATIC) {
+            struct Preset { int order; float x; int mc; };
+            const bool fac = kind == SI_SCHED_FAC;
+            const Preset presets[] = {{SI_ORDER_CELL, 16.0f, 32}, {SI_ORDER_CELL, 64.0f, 32},
+                                      {SI_ORDER_CELL, 16.0f, 16}, {SI_ORDER_SPREAD, 12.0f, 16}};
+            for (const Preset& q : presets) {
+                si_sched c = cur;
+                c.order = q.order;
+                c.min_chunk = q.mc;
+                if (fac) c.fac_divisor = q.x;
+                if (rc != SI_OK || (c.order == cur.order && c.min_chunk == cur.min_chunk &&
+                                    c.fac_divisor == cur.fac_divisor))
+                    continue;
+                rc = try_set(c);
+            }
+        }
         // images per shared pass
         for (int g : {4, 8, 2, 6, 1}) {
             if (rc != SI_OK || g == cur.group) continue;
@@ -283,6 +309,7 @@ extern "C" si_status si_autotune(const si_batch_item* items, int32_t n_items, in
     t.num_workgroups = cur.num_workgroups;
     t.divisor = cur.fac_divisor;
     t.min_chunk = cur.min_chunk;
+    t.order = cur.order;
     t.ms = cur_ms;
     g_tuned[key] = t;
     save_cache();
