@@ -263,8 +263,9 @@ def batched(torch, si, sg, model):
                for (_, _, _, img, cnt), r in zip(items, ref))
     learned = None
     if model is not None:
-        ls = si.Sched("learned", tuned.num_workgroups, tuned.min_chunk, tuned.fac_divisor, model,
-                      True, tuned.group)
+        # the tuned launch shape (group, workgroups); its own chunk sizes and
+        # order (FAC's tuned ratio and minimum chunk size FAC's chunks)
+        ls = si.Sched("learned", tuned.num_workgroups, 0, 0.0, model, True, tuned.group)
         learned_ms = timed(torch, lambda: si.si_generate_batched(items, ls, use_graph=True))
         st = si.si_generate_batched(items, ls, use_graph=True, stats=True)
         # the same with the library's defaults (no tuning)
