@@ -160,10 +160,11 @@ def test_autotune(env, tmp_path):
             assert torch.equal(b["img"], img)
             assert torch.equal(b["cnt"], cnt)
         text = cache.read_text()
-        assert '"group"' in text and "kind3" in text
+        assert '"group"' in text and '"order"' in text and "kind3" in text
         sched2, ms2 = si.si_autotune(items_of(batch), "fac", use_graph=True, max_trials=8)
-        assert (sched2.group, sched2.num_workgroups, sched2.min_chunk) == \
-            (sched.group, sched.num_workgroups, sched.min_chunk)
+        assert (sched2.group, sched2.num_workgroups, sched2.min_chunk, sched2.fac_divisor,
+                sched2.order) == (sched.group, sched.num_workgroups, sched.min_chunk,
+                                  sched.fac_divisor, sched.order)
         assert abs(ms2 - ms) < 1e-3
         # a single scene, static technique
         one = items_of(batch)[:1]

@@ -201,10 +201,12 @@ def clustered2m():
 
 
 def test_clustered2m_vs_oracle(env, clustered2m):
-    """The 2M-point clustered workload, every point oriented, in the
-    benchmark's launch configuration (FAC, library defaults):
+    """The 2M-point clustered workload, every point oriented, FAC at the
+    library's defaults:
       * 10,000 sampled images against the FP64 oracle (brute force over all
         2M points per image) in bilinear mode;
+      * the benchmark's main-step schedule (FAC, ratio 16, chunks of at
+        least 32, cell order) gives the same image tensor bit for bit;
       * the overflow statistic equals the number of images with 65,536 or
         more in-support pairs;
       * the learned schedule (a model trained on the logged counts) gives
@@ -244,6 +246,15 @@ def test_clustered2m_vs_oracle(env, clustered2m):
     torch.cuda.synchronize()
     assert st2["sched_used"] == si.SCHED["learned"]
     assert st2["pairs_in_support"] == st["pairs_in_support"]
+    assert torch.equal(cnt2, cnt)
+    assert torch.equal(img2, img)
+    # the benchmark's main-step schedule
+    img2.fill_(-1.0)
+    cnt2.fill_(-1)
+    sweep = si.Sched("fac", fac_divisor=16.0, min_chunk=32, order="cell")
+    _, _, st3 = si.si_generate(scene, idx, params, sweep, img2, cnt2, stats=True)
+    torch.cuda.synchronize()
+    assert st3["pairs_in_support"] == st["pairs_in_support"]
     assert torch.equal(cnt2, cnt)
     assert torch.equal(img2, img)
     del img2, cnt2, img
